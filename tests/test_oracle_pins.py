@@ -1,0 +1,316 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests recomputes a result with the oracle's own formula: each
+checks the oracle against an independent route (all-pairs brute force with no
+vote array, the 6-D exhaustive search of Alg. 1, Theorem 3, a k-d tree from
+scipy, closed forms on exact dyadic inputs, invariances the paper claims).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import oracle
+from paper_2502_00115_amd import synth
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _f64(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def _pair_bins_f64(src, tgt, R, delta):
+    """u = (y_j - R x_i)/delta for every pair, in double (test-side, no oracle code)."""
+    x, y = _f64(src), _f64(tgt)
+    p = x @ _f64(R).reshape(3, 3).T
+    return (y[None, :, :] - p[:, None, :]) / float(np.float32(delta))
+
+
+def _far_from_faces(u, margin=1e-3):
+    frac = (u + 0.5) - np.floor(u + 0.5)
+    return bool(np.all((frac > margin) & (frac < 1 - margin)))
+
+
+def _separated(rng, n, spread, min_dist):
+    pts = []
+    while len(pts) < n:
+        c = rng.uniform(-spread, spread, 3)
+        if all(np.linalg.norm(c - q) > min_dist for q in pts):
+            pts.append(c)
+    return np.array(pts)
+
+
+# ---------------------------------------------------------------------------
+# translation box
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("delta,klo,size", [(0.05, -20, 41), (0.03, -33, 67), (0.02, -50, 101),
+                                            (0.0625, -16, 33), (0.3, -3, 7)])
+def test_box_lattice_counts(delta, klo, size):
+    # Lattice points b*delta inside [-1, 1]: b in [-floor(1/delta), floor(1/delta)].
+    k_lo, sz = oracle.box(delta)
+    assert list(k_lo) == [klo] * 3 and list(sz) == [size] * 3
+
+
+def test_box_asymmetric():
+    k_lo, sz = oracle.box(0.125, [-0.25, 0.0, -1.0], [0.5, 0.125, 0.0])
+    assert list(k_lo) == [-2, 0, -8] and list(sz) == [7, 2, 9]
+
+
+# ---------------------------------------------------------------------------
+# vote array and mode (Lemma 2, Alg. 2 first loop)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(12))
+def test_vote_matches_all_pairs_brute_force(seed):
+    """Every pair's bin is counted by an O((NM)^2) comparison with no vote array."""
+    rng = np.random.default_rng(seed)
+    for _ in range(50):
+        n, m = int(rng.integers(2, 7)), int(rng.integers(2, 9))
+        delta = float(rng.choice([0.0625, 0.1, 0.25]))
+        src = rng.uniform(-0.6, 0.6, (n, 3)).astype(np.float32)
+        tgt = rng.uniform(-0.6, 0.6, (m, 3)).astype(np.float32)
+        if seed % 3 == 0:       # force repeated translations so that the mode is non-trivial
+            tgt[: m // 2] = (src[: m // 2] if n >= m // 2 else tgt[: m // 2]) + np.float32(0.2)
+        R = synth.random_rotations(rng, 1)[0].astype(np.float32)
+        if seed % 3 == 0:
+            R = np.eye(3, dtype=np.float32)
+        u = _pair_bins_f64(src, tgt, R, delta)
+        if _far_from_faces(u):
+            break
+    else:
+        pytest.skip("no face-free draw")
+    t_lo = -rng.uniform(0.3, 1.2, 3)
+    t_hi = rng.uniform(0.3, 1.2, 3)
+    hist, mode, M = oracle.vote(src, tgt, R, delta, t_lo, t_hi)
+    k_lo, size = oracle.box(delta, t_lo, t_hi)
+    b = np.floor(u + 0.5).astype(np.int64).reshape(-1, 3)
+    inbox = [tuple(v) for v in b if np.all(v >= k_lo) and np.all(v < k_lo + size)]
+    counts = {v: sum(1 for w in inbox if w == v) for v in inbox}     # all-pairs comparison
+    assert int(hist.sum()) == len(inbox)
+    for v, c in counts.items():
+        assert hist[tuple(np.array(v) - k_lo)] == c
+    if not inbox:
+        assert M == 0
+        return
+    best = max(counts.values())
+    first = min((v for v, c in counts.items() if c == best),
+                key=lambda v: ((v[0] - k_lo[0]) * size[1] + v[1] - k_lo[1]) * size[2] + v[2] - k_lo[2])
+    assert M == best
+    assert tuple(mode) == first
+
+
+def test_round_half_goes_up():
+    """ROUND's tie rule (the paper is silent): a translation exactly half a bin above a
+    lattice point rounds up; exactly half a bin below rounds up to the lattice point."""
+    d = 0.0625
+    src = np.zeros((1, 3), np.float32)
+    tgt = np.array([[0.5 * d, -0.5 * d, 1.5 * d]], np.float32)
+    _, mode, M = oracle.vote(src, tgt, np.eye(3, dtype=np.float32), d)
+    assert M == 1 and tuple(mode) == (1, 0, 2)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_lemma2_identity_shift(seed):
+    """X = subset of Y shifted by -c*delta, R = I, Y separated by > sqrt(3)*delta:
+    the mode is exactly c with frequency N (dyadic data, all arithmetic exact)."""
+    rng = np.random.default_rng(100 + seed)
+    d = 2.0 ** -4
+    tgt = np.round(_separated(rng, 20, 0.7, 2.0 * d) * 1024) / 1024
+    c = rng.integers(-5, 6, 3)
+    pick = rng.choice(20, 9, replace=False)
+    src = tgt[pick] - c * d
+    hist, mode, M = oracle.vote(src, tgt, np.eye(3), d)
+    assert M == 9 and tuple(mode) == tuple(c)
+    assert int(np.sum(hist == 9)) == 1
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_theorem3_against_exhaustive_alg1(seed):
+    """Theorem 3: with points separated by more than the discretisation, the mode count
+    of each rotation equals the best L0^{m1} inlier count of the 6-D exhaustive search
+    (Alg. 1) over every lattice translation in the box."""
+    rng = np.random.default_rng(200 + seed)
+    d = 0.125
+    for _ in range(100):
+        tgt = _separated(rng, 9, 0.55, math.sqrt(3) * d * 1.05)
+        R_true = synth.random_rotations(rng, 1)[0]
+        t_true = np.round(rng.uniform(-0.4, 0.4, 3) / d) * d
+        pick = rng.choice(9, 5, replace=False)
+        src = (tgt[pick] - t_true) @ R_true + rng.normal(0, 0.01, (5, 3))
+        src = np.vstack([src, rng.uniform(-0.5, 0.5, (2, 3))])
+        rots = np.concatenate([synth.random_rotations(rng, 3), R_true[None]])
+        src32, tgt32 = src.astype(np.float32), tgt.astype(np.float32)
+        rots32 = rots.reshape(-1, 9).astype(np.float32)
+        if all(_far_from_faces(_pair_bins_f64(src32, tgt32, r, d), 2e-3) for r in rots32):
+            break
+    else:
+        pytest.skip("no face-free draw")
+    if not all(np.all(np.linalg.norm(a - b) > math.sqrt(3) * d) for a, b in
+               itertools.combinations(_f64(src32), 2)):
+        pytest.skip("source not separated")
+    k_lo, size = oracle.box(d)
+    lattice = np.stack(np.meshgrid(*[np.arange(k_lo[a], k_lo[a] + size[a]) for a in range(3)],
+                                   indexing="ij"), -1).reshape(-1, 3) * d
+    recs = oracle.records(src32, tgt32, rots32, d)
+    best_alg1 = 0
+    for k, R in enumerate(rots32):
+        p = _f64(src32) @ _f64(R).reshape(3, 3).T                      # (N, 3)
+        # residual y_j - R x_i - t for every (t, i, j); inlier iff inside the half-open cube
+        res = _f64(tgt32)[None, None, :, :] - p[None, :, None, :] - lattice[:, None, None, :]
+        hit = np.all((res >= -d / 2) & (res < d / 2), axis=-1)          # (T, N, M)
+        inliers = hit.any(axis=2).sum(axis=1)                           # L0^{m1} count per t
+        assert int(inliers.max()) == int(recs["votes"][k])
+        best_alg1 = max(best_alg1, int(inliers.max()))
+    assert best_alg1 == int(recs["votes"].max())
+
+
+def test_translation_invariance_exact():
+    """Shifting the reference by a lattice vector shifts every mode by it (dyadic data and
+    signed-permutation rotations keep all float arithmetic exact)."""
+    rng = np.random.default_rng(7)
+    d = 2.0 ** -4
+    tgt = np.round(rng.uniform(-0.6, 0.6, (40, 3)) * 1024) / 1024
+    src = np.round(rng.uniform(-0.6, 0.6, (25, 3)) * 1024) / 1024
+    src[:10] = tgt[:10] - np.array([0.25, -0.125, 0.0625])
+    perms = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product([1, -1], repeat=3):
+            P = np.zeros((3, 3))
+            P[range(3), perm] = signs
+            if np.linalg.det(P) > 0:
+                perms.append(P)
+    rots = np.array(perms).reshape(-1, 9)
+    a = oracle.records(src, tgt, rots, d, t_min=-1.5, t_max=1.5)
+    shift = np.array([3, -2, 1])
+    b = oracle.records(src, tgt + shift * d, rots, d, t_min=-1.5, t_max=1.5)
+    np.testing.assert_array_equal(b["bin"], a["bin"] + shift)
+    np.testing.assert_array_equal(b["votes"], a["votes"])
+    np.testing.assert_array_equal(b["inliers"], a["inliers"])
+    np.testing.assert_allclose(b["error"], a["error"], rtol=1e-12, atol=1e-12)
+
+
+def test_permutation_invariance():
+    p = synth.make_c1(3)
+    rng = np.random.default_rng(0)
+    which = np.arange(0, 577, 9)
+    a = oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which)
+    b = oracle.records(p.src[rng.permutation(len(p.src))], p.tgt[rng.permutation(len(p.tgt))],
+                       p.rotations, p.eps, which=which)
+    np.testing.assert_array_equal(a["bin"], b["bin"])
+    np.testing.assert_array_equal(a["votes"], b["votes"])
+    np.testing.assert_array_equal(a["inliers"], b["inliers"])
+    np.testing.assert_allclose(a["error"], b["error"], rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# scoring (Eq. (1)/(2)) and selection
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("l1", [False, True])
+def test_nn_against_kdtree(l1):
+    rng = np.random.default_rng(11)
+    tgt = rng.uniform(-1, 1, (500, 3)).astype(np.float32)
+    q = rng.uniform(-1.2, 1.2, (300, 3))
+    ref, _ = cKDTree(_f64(tgt)).query(q, p=1 if l1 else 2)
+    np.testing.assert_allclose(oracle.nn(q, tgt, l1=l1), ref, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("metric", ["trunc_l2", "tls", "inliers", "trunc_l1"])
+def test_candidate_error_against_kdtree(metric):
+    """e(R, t*) sums over the partial source X and minimises over the full reference Y."""
+    p = synth.make_c1(5)
+    which = np.arange(0, 577, 23)
+    tau = 0.04
+    recs = oracle.records(p.src, p.tgt, p.rotations, p.eps, tau=tau, metric=metric, which=which)
+    tree = cKDTree(_f64(p.tgt))
+    eps = float(np.float32(p.eps))
+    tau = float(np.float32(tau))
+    for r, k in zip(recs, which):
+        R = _f64(p.rotations[k]).reshape(3, 3)
+        t = r["bin"] * float(np.float32(p.eps))
+        q = _f64(p.src) @ R.T + t
+        d2, _ = tree.query(q)
+        d1, _ = tree.query(q, p=1)
+        rho = {"trunc_l2": np.minimum(d2, tau), "tls": np.minimum(d2, tau) ** 2,
+               "inliers": (d2 >= eps).astype(float), "trunc_l1": np.minimum(d1, tau)}[metric]
+        assert r["inliers"] == int(np.sum(d2 < eps))
+        assert r["boundary"] == int(np.sum(np.abs(d2 - eps) <= 1e-6))
+        assert abs(r["error"] - rho.sum()) <= 1e-9 * max(1.0, rho.sum())
+
+
+def test_source_vs_reference_direction():
+    """Partial-to-full: extra reference points far from the source leave the error unchanged
+    (the sum runs over X, the minimum over Y); extra source points do change it."""
+    p = synth.make_c1_exact(1)
+    which = [p.true_index]
+    base = oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which)[0]
+    far = np.vstack([p.tgt, np.full((5, 3), 5.0, np.float32)])
+    more_ref = oracle.records(p.src, far, p.rotations, p.eps, which=which)[0]
+    assert more_ref["error"] == base["error"] and more_ref["inliers"] == base["inliers"]
+    junk = np.vstack([p.src, np.full((3, 3), 4.0, np.float32)])
+    more_src = oracle.records(junk, p.tgt, p.rotations, p.eps, which=which)[0]
+    assert more_src["error"] == pytest.approx(base["error"] + 3 * float(np.float32(p.eps)))
+
+
+def test_select_tie_breaks():
+    recs = np.zeros(5, oracle.RECORD_DTYPE)
+    recs["valid"] = [1, 1, 0, 1, 1]
+    recs["error"] = [2.0, 1.0, 0.5, 1.0, 1.0]
+    recs["inliers"] = [9, 5, 9, 7, 7]
+    assert oracle.select(recs) == 3            # lowest error, then most inliers, then index
+    recs["valid"] = 0
+    assert oracle.select(recs) == -1
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_exact_recovery(seed):
+    """Noise-free exact subset, true rotation on the list and t* on the lattice:
+    the true candidate is returned with every source point an inlier."""
+    p = synth.make_c1_exact(seed)
+    r = oracle.register(p.src, p.tgt, p.rotations, p.eps)
+    assert r["rot_index"] == p.true_index
+    np.testing.assert_allclose(r["t"], p.t_true, atol=1e-6)
+    assert r["inliers"] == len(p.src)
+    assert r["votes"] >= len(p.src)
+    assert r["error"] <= len(p.src) * 1e-6
+
+
+def test_no_vote_in_box_is_invalid():
+    src = np.zeros((3, 3), np.float32)
+    tgt = np.full((4, 3), 0.9, np.float32)
+    recs = oracle.records(src, tgt, np.eye(3).reshape(1, 9), 0.05, t_min=-0.2, t_max=0.2)
+    assert recs["valid"][0] == 0 and recs["votes"][0] == 0
+    assert oracle.select(recs) == -1
+
+
+# ---------------------------------------------------------------------------
+# distance field
+# ---------------------------------------------------------------------------
+def test_distance_field_against_kdtree():
+    p = synth.make_c1(2)
+    r, res = np.float32(0.05), 24
+    df = oracle.df_build(p.tgt, r, res)
+    tree = cKDTree(_f64(p.tgt))
+    idx = np.stack(np.meshgrid(*[np.arange(res)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    centres = _f64(df.lo) + (idx + 0.5) * _f64(df.h)
+    d, _ = tree.query(centres)
+    np.testing.assert_allclose(df.field.reshape(-1), np.minimum(d, float(r)), rtol=1e-12,
+                               atol=1e-15)
+    # box is the reference AABB padded by r
+    np.testing.assert_allclose(df.lo, p.tgt.min(0) - r, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(_f64(df.lo) + res * _f64(df.h), _f64(p.tgt.max(0)) + float(r),
+                               atol=1e-5)
+
+
+def test_distance_field_score_within_lipschitz_bound():
+    """Nearest-voxel lookup error is bounded by half a voxel diagonal (1-Lipschitz field)."""
+    p = synth.make_c1_exact(4)
+    r, res = np.float32(0.05), 48
+    df = oracle.df_build(p.tgt, r, res)
+    which = np.arange(0, 577, 11)
+    exact = oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which)
+    approx = oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which, df=df)
+    np.testing.assert_array_equal(exact["bin"], approx["bin"])
+    bound = len(p.src) * 0.5 * float(np.linalg.norm(_f64(df.h)))
+    assert np.all(np.abs(exact["error"] - approx["error"]) <= bound + 1e-9)

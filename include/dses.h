@@ -1,0 +1,286 @@
+/*
+ * dses.h -- C ABI of the MI355X (gfx950) implementation of Direct Semi-Exhaustive
+ * Search (DSES) for partial-to-full rigid point-cloud registration
+ * (Cheng, Papozov, Helmick, Tjersland, arXiv 2502.00115).
+ *
+ * The library runs the data-parallel hot path of the method on one GPU: for every
+ * rotation R of a caller-given candidate list it
+ *   1. votes every rotated point-pair translation y_j - R x_i into a translation
+ *      lattice of pitch delta and takes the mode t* and its frequency M
+ *      (Lemma 2, Eq. (5); first loop of Alg. 2);
+ *   2. scores the candidate {R, t*} directly: d_i = min_j ||R x_i + t* - y_j||,
+ *      inliers = #{d_i < eps}, error = sum_i rho(d_i) for the chosen robust metric
+ *      (Eq. (1)/(2); error loop of Alg. 2 with q = 0, i.e. every candidate scored);
+ *   3. returns the candidate with the smallest error (return step of Alg. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Point clouds are row-major float32 xyz arrays: src is N x 3 (the partial
+ *    observation X), tgt is M x 3 (the full reference Y).
+ *  - Rotations are row-major float32 3x3 matrices, K x 9, mapping the source frame
+ *    into the reference frame: a candidate transforms x as R x + t.
+ *  - Pointers are host pointers unless DSES_DEVICE_PTRS is set in the options flags,
+ *    in which case src/tgt/rotations (and dses_options.records) are device pointers
+ *    on the library's device (e.g. torch tensors' data_ptr()).
+ *  - The caller owns every buffer it passes; the library only reads inputs during
+ *    the call (for dses_server_submit: until dses_server_wait returns for that
+ *    request) and never frees caller memory.
+ *  - Every call returns a dses_status; on failure a message is available from
+ *    dses_last_error() (thread-local) and `out` is left untouched.
+ *
+ * Translation lattice and ROUND (Alg. 2, "ROUND(y_j - R x_i, delta_t)")
+ * ----------------------------------------------------------------------
+ * The vote array spans the translation box [t_min, t_max] (default [-1, 1]^3;
+ * the paper bounds it by the search range of its experiments, Sec. V).  Its bins
+ * are the lattice points b*delta with, per axis a,
+ *     k_lo_a = ceil(t_min_a/delta - 1e-4),  k_hi_a = floor(t_max_a/delta + 1e-4)
+ * (double precision), size_a = k_hi_a - k_lo_a + 1.  The bin of a pair is decided
+ * in IEEE single precision, exactly as follows (the paper fixes no precision):
+ *     s    = 1.0f / delta
+ *     p_a  = fmaf(R[a][2], x_z, fmaf(R[a][1], x_y, R[a][0] * x_x))
+ *     Y_a  = (y_a * s) + (0.5f - (float)k_lo_a)          (two roundings, no fma)
+ *     c_a  = floorf(Y_a - p_a * s)                        (box-relative bin)
+ * i.e. c_a = round-half-up((y_a - p_a)/delta) - k_lo_a.  A pair votes iff
+ * 0 <= c_a < size_a on every axis.  The mode is the bin with the largest count;
+ * ties go to the lowest linear index ((c_x * size_y + c_y) * size_z + c_z).
+ * The returned translation is t_a = (float)(c_a + k_lo_a) * delta (no refinement:
+ * the paper's answer is exact only up to the discretisation delta).
+ *
+ * Metrics (Eq. (1): "any desired norm"; Sec. IV-B uses a truncated norm)
+ * ----------------------------------------------------------------------
+ *   DSES_TRUNC_L2  error = sum_i min(d_i, tau), d_i the Euclidean NN distance
+ *   DSES_INLIERS   error = N - inliers  (the L0^{m1} objective of Eq. (3), Thm. 3)
+ *   DSES_TLS       error = sum_i min(d_i^2, tau^2)
+ *   DSES_TRUNC_L1  error = sum_i min(min_j ||q_i - y_j||_1, tau)
+ * inliers always counts d_i < eps with the Euclidean d_i.  All scoring runs in
+ * float32; ties in the final selection go to more inliers, then the lower
+ * rotation index (the paper is silent on ties).
+ */
+#ifndef DSES_H
+#define DSES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DSES_OK = 0,
+    DSES_E_INVAL = -1,        /* bad argument: NULL pointer, n/m/k <= 0, eps <= 0 or
+                                 non-finite, non-finite coordinate, coordinate too large
+                                 for the lattice, non-orthonormal rotation
+                                 (|R^T R - I|_max > 1e-4), empty box, bad option      */
+    DSES_E_NOCANDIDATE = -2,  /* no rotation received a vote inside the box            */
+    DSES_E_NOMEM = -3,        /* device allocation failed / request exceeds a budget   */
+    DSES_E_TIMEOUT = -4,      /* dses_server_wait timed out                            */
+    DSES_E_DEVICE = -5,       /* HIP runtime error, or no usable gfx950 device          */
+    DSES_E_STATE = -6         /* wrong handle state (e.g. unknown or consumed request)  */
+} dses_status;
+
+typedef enum {
+    DSES_TRUNC_L2 = 0,
+    DSES_INLIERS = 1,
+    DSES_TLS = 2,
+    DSES_TRUNC_L1 = 3
+} dses_metric;
+
+/* How the per-candidate nearest-neighbour term of Eq. (2) is evaluated. */
+typedef enum {
+    DSES_SCORER_AUTO = 0,   /* GRID, or DF when the target handle carries a field    */
+    DSES_SCORER_BRUTE = 1,  /* every reference point per source point (Alg. 2 as
+                               printed: "brute-force checking every nearest neighbor") */
+    DSES_SCORER_GRID = 2,   /* exact: only reference points within r = max(eps, tau)
+                               can change rho or the inlier test, found through a
+                               uniform cell grid of pitch >= r; same result as BRUTE  */
+    DSES_SCORER_DF = 3      /* voxel distance field of the reference (approximate,
+                               see dses_target_create); TRUNC_L1 is not supported     */
+} dses_scorer;
+
+#define DSES_DEVICE_PTRS 0x1u   /* inputs (and records) are device pointers            */
+#define DSES_TIMING 0x2u        /* time each kernel with HIP events (dses_kernel_stats) */
+
+typedef struct {
+    uint32_t struct_size;     /* sizeof(dses_options); 0-filled fields mean defaults  */
+    uint32_t flags;           /* DSES_DEVICE_PTRS | DSES_TIMING                         */
+    float delta_t;            /* translation bin pitch; 0 -> eps                        */
+    float tau;                /* truncation of the robust metrics; 0 -> eps             */
+    float t_min[3];           /* translation box; t_min == t_max == 0 -> [-1, 1]^3      */
+    float t_max[3];
+    int32_t scorer;           /* dses_scorer; 0 -> AUTO                                 */
+    int32_t reserved;
+    void *stream;             /* hipStream_t to run on; NULL -> the library's stream    */
+    void *records;            /* optional: K dses_record, one per rotation, filled on
+                                 DSES_OK (host memory, or device with DSES_DEVICE_PTRS) */
+} dses_options;
+
+/* Result of one registration. */
+typedef struct {
+    float R[9];               /* selected rotation (copied from the list)             */
+    float t[3];               /* its mode translation t* (a lattice point)            */
+    int32_t rot_index;        /* index into the rotation list                         */
+    int32_t inliers;          /* #{d_i < eps}                                         */
+    float error;              /* e(R, t*) under the metric                            */
+    uint32_t votes;           /* M: vote count of t*                                  */
+    int32_t n_valid;          /* rotations that received at least one in-box vote     */
+} dses_result;
+
+/* Per-rotation candidate record (24 bytes), optional output. */
+typedef struct {
+    int32_t bin[3];           /* mode bin b* (t* = b* delta); undefined if votes == 0 */
+    uint32_t votes;           /* M; 0 marks a rotation with no in-box vote (invalid)  */
+    int32_t inliers;
+    float error;              /* +inf for invalid rotations                           */
+} dses_record;
+
+/* Cumulative HIP-event kernel timings (DSES_TIMING), per kernel family. */
+typedef struct {
+    double vote_score_ms;     /* fused vote + mode + score kernel(s)                   */
+    double score_ms;          /* separate scoring kernel(s), if any                    */
+    double select_ms;         /* candidate selection                                   */
+    double stage_ms;          /* input staging / grids / distance fields               */
+    int64_t vote_score_launches;
+    int64_t score_launches;
+    int64_t pairs_voted;      /* sum of N*M over rotations swept (algorithmic)        */
+    int64_t pairs_scored;     /* sum of N*M over candidates scored by BRUTE            */
+    int64_t candidates;       /* rotations swept                                      */
+} dses_kstats;
+
+/* ---------------------------------------------------------------------------- */
+/* Library                                                                       */
+/* ---------------------------------------------------------------------------- */
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char *dses_last_error(void);
+
+/* Select and initialise the HIP device (default 0).  Optional: every entry point
+ * initialises device 0 on first use.  Returns DSES_E_DEVICE without a gfx950 GPU. */
+dses_status dses_init(int32_t device);
+
+/* Library version string. */
+const char *dses_version(void);
+
+/* Read (and with reset != 0 clear) the DSES_TIMING kernel statistics. */
+dses_status dses_kernel_stats(dses_kstats *out, int32_t reset);
+
+/* ---------------------------------------------------------------------------- */
+/* Plain registration (Alg. 2 with q = 0)                                        */
+/* ---------------------------------------------------------------------------- */
+
+/* Register src (n x 3) to tgt (m x 3) over the k rotations; synchronous on the
+ * chosen stream.  Requires n*m < 2^31.  opt may be NULL (all defaults, host
+ * pointers).  Writes *out and, if opt->records != NULL, k records. */
+dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t m,
+                          const float *rotations, int64_t k, float eps, dses_metric metric,
+                          const dses_options *opt, dses_result *out);
+
+/* ---------------------------------------------------------------------------- */
+/* Resident data: reference clouds (with optional distance field) and rotation   */
+/* lists kept in device memory across calls (the serving workload keeps them).   */
+/* ---------------------------------------------------------------------------- */
+typedef struct dses_target dses_target;
+typedef struct dses_rotset dses_rotset;
+
+typedef struct {
+    uint32_t struct_size;
+    uint32_t flags;           /* DSES_DEVICE_PTRS: tgt is a device pointer            */
+    float df_trunc;           /* > 0: build a distance field truncated at this radius  */
+    int32_t df_res;           /* field resolution per axis (0 -> 128)                  */
+} dses_target_opts;
+
+/* Upload a reference cloud (m x 3).  With df_trunc = r > 0 also build its voxel
+ * distance field: a df_res^3 float32 grid over the reference AABB padded by r,
+ * voxel centres c = lo + (idx + 1/2) h, value min(min_j ||c - y_j||, r), where in
+ * float32  lo_a = min_j y_a - r,  h_a = ((max_j y_a + r) - lo_a) / df_res.
+ * A DF query q (formed in float32 as R x + t) reads the voxel
+ * idx_a = floorf((q_a - lo_a) * (1.0f / h_a)); outside the grid its value is r.
+ * DF scoring then requires r == max(eps, tau) of the registration. */
+dses_status dses_target_create(const float *tgt, int64_t m, const dses_target_opts *opt,
+                               dses_target **out);
+dses_status dses_target_destroy(dses_target *t);
+/* Copy the distance field (df_res^3 floats, x slowest) and its lo[3]/h[3] to host
+ * buffers; for checking.  Returns DSES_E_STATE if the target has no field. */
+dses_status dses_target_field(const dses_target *t, float *field, float *lo, float *h);
+
+/* Upload a rotation list (k x 9) once. */
+dses_status dses_rotations_create(const float *rotations, int64_t k, uint32_t flags,
+                                  dses_rotset **out);
+dses_status dses_rotations_destroy(dses_rotset *r);
+
+/* dses_register against resident data (tgt/rotations arguments replaced). */
+dses_status dses_register_resident(const dses_target *tgt, const dses_rotset *rots,
+                                   const float *src, int64_t n, float eps, dses_metric metric,
+                                   const dses_options *opt, dses_result *out);
+
+/* ---------------------------------------------------------------------------- */
+/* Batched registration: many independent registrations in one persistent       */
+/* launch (captured once in a HIP graph and replayed).                           */
+/* ---------------------------------------------------------------------------- */
+typedef struct {
+    const float *src;         /* n x 3 */
+    int64_t n;
+    const float *tgt;         /* m x 3 (ignored when target != NULL) */
+    int64_t m;
+    const float *rotations;   /* k x 9 (ignored when rotset != NULL) */
+    int64_t k;
+    const dses_target *target;   /* optional resident reference */
+    const dses_rotset *rotset;   /* optional resident rotations */
+    float eps;
+    int32_t metric;
+    float delta_t, tau;       /* 0 -> eps */
+    float t_min[3], t_max[3]; /* both 0 -> [-1, 1]^3 */
+    void *records;            /* optional k dses_record */
+} dses_problem;
+
+typedef struct {
+    uint32_t struct_size;
+    uint32_t flags;           /* DSES_DEVICE_PTRS | DSES_TIMING */
+    int32_t scorer;           /* dses_scorer for every problem */
+    int32_t use_graph;        /* 1: capture the launch in a HIP graph and replay it */
+    int32_t tile_rot;         /* rotations per work item; 0 -> autotuned            */
+    int32_t reserved;
+    void *stream;
+} dses_batch_opts;
+
+/* Register every problem; results (and records) are identical to running each
+ * problem alone with dses_register.  Synchronous. */
+dses_status dses_register_batch(const dses_problem *probs, int32_t count,
+                                const dses_batch_opts *opt, dses_result *out,
+                                dses_status *status);
+
+/* ---------------------------------------------------------------------------- */
+/* Serving: a request loop with memory-based admission and continuous batching. */
+/* ---------------------------------------------------------------------------- */
+typedef struct dses_server dses_server;
+
+typedef struct {
+    uint32_t struct_size;
+    uint32_t flags;
+    int64_t memory_budget;    /* bytes of per-request device memory in flight (0: 1 GiB) */
+    int32_t max_inflight;     /* requests on the device at once (0: 64)               */
+    int32_t scorer;           /* dses_scorer for every request                         */
+} dses_server_opts;
+
+dses_status dses_server_create(const dses_server_opts *opt, dses_server **out);
+/* Queue a registration of host src (n x 3) against resident data; the source is
+ * copied at submit time.  Returns a request id. */
+dses_status dses_server_submit(dses_server *srv, const dses_target *tgt,
+                               const dses_rotset *rots, const float *src, int64_t n, float eps,
+                               dses_metric metric, uint64_t *req_id);
+/* Wait up to timeout_ms (< 0: forever) for a request; consumes it on success. */
+dses_status dses_server_wait(dses_server *srv, uint64_t req_id, int32_t timeout_ms,
+                             dses_result *out, dses_status *req_status);
+/* Non-blocking: 1 if finished, 0 if pending, < 0 on error. */
+int32_t dses_server_poll(dses_server *srv, uint64_t req_id);
+/* Submit-to-finish latency (seconds) of a finished request, and the moment (on the
+ * server's steady clock) it was admitted to the device. */
+dses_status dses_server_timing(dses_server *srv, uint64_t req_id, double *queue_s,
+                               double *total_s);
+dses_status dses_server_destroy(dses_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSES_H */

@@ -1,0 +1,602 @@
+// DSES C ABI: context, argument checking and the plain registration driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "host.h"
+
+namespace dses {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+dses_status DevBuf::ensure(size_t want)
+{
+    if (want <= bytes && ptr) return DSES_OK;
+    release();
+    size_t b = std::max<size_t>(want, 256);
+    b = (b + 4095) & ~size_t(4095);
+    if (hipMalloc(&ptr, b) != hipSuccess) {
+        ptr = nullptr;
+        bytes = 0;
+        (void)hipGetLastError();
+        set_error("device allocation of " + std::to_string(b) + " bytes failed");
+        return DSES_E_NOMEM;
+    }
+    bytes = b;
+    return DSES_OK;
+}
+
+void DevBuf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+static std::mutex g_init_mu;
+static Context *g_ctx = nullptr;
+
+static dses_status init_device(int device)
+{
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (g_ctx) {
+        if (device >= 0 && device != g_ctx->device) {
+            set_error("library already initialised on another device");
+            return DSES_E_STATE;
+        }
+        return DSES_OK;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        set_error("no HIP device available");
+        return DSES_E_DEVICE;
+    }
+    if (device < 0) device = 0;
+    if (device >= count) {
+        set_error("device index out of range");
+        return DSES_E_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    DSES_HIP(hipGetDeviceProperties(&prop, device));
+    std::string arch = prop.gcnArchName;
+    if (arch.rfind("gfx950", 0) != 0) {
+        set_error("unsupported GPU architecture " + arch + " (gfx950 required)");
+        return DSES_E_DEVICE;
+    }
+    DSES_HIP(hipSetDevice(device));
+    auto *c = new Context();
+    c->device = device;
+    c->arch = arch;
+    c->n_cu = prop.multiProcessorCount;
+    int lds = 0;
+    DSES_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    c->lds_max = std::min(lds, 160 * 1024);
+    DSES_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    void *hr = nullptr;
+    DSES_HIP(hipHostMalloc(&hr, sizeof(DevResult), hipHostMallocDefault));
+    c->host_res = static_cast<DevResult *>(hr);
+    g_ctx = c;
+    return DSES_OK;
+}
+
+Context *ctx()
+{
+    if (!g_ctx && init_device(-1) != DSES_OK) return nullptr;
+    if (g_ctx) (void)hipSetDevice(g_ctx->device);
+    return g_ctx;
+}
+
+dses_status resolve_params(float eps, int metric, float delta_t, float tau, const float *t_min,
+                           const float *t_max, int scorer, Params *p)
+{
+    if (!(eps > 0.0f) || !std::isfinite(eps)) {
+        set_error("eps must be positive and finite");
+        return DSES_E_INVAL;
+    }
+    if (metric < DSES_TRUNC_L2 || metric > DSES_TRUNC_L1) {
+        set_error("unknown metric");
+        return DSES_E_INVAL;
+    }
+    if (scorer < DSES_SCORER_AUTO || scorer > DSES_SCORER_DF) {
+        set_error("unknown scorer");
+        return DSES_E_INVAL;
+    }
+    p->eps = eps;
+    p->delta = delta_t == 0.0f ? eps : delta_t;
+    p->tau = tau == 0.0f ? eps : tau;
+    if (!(p->delta > 0.0f) || !std::isfinite(p->delta) || !(p->tau > 0.0f) ||
+        !std::isfinite(p->tau)) {
+        set_error("delta_t and tau must be positive and finite");
+        return DSES_E_INVAL;
+    }
+    p->r = std::max(p->eps, p->tau);
+    p->metric = metric;
+    p->scorer = scorer;
+    float lo[3] = {-1.0f, -1.0f, -1.0f}, hi[3] = {1.0f, 1.0f, 1.0f};
+    bool zero = true;
+    if (t_min && t_max)
+        for (int a = 0; a < 3; ++a) zero = zero && t_min[a] == 0.0f && t_max[a] == 0.0f;
+    if (!zero)
+        for (int a = 0; a < 3; ++a) { lo[a] = t_min[a]; hi[a] = t_max[a]; }
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(lo[a]) || !std::isfinite(hi[a])) {
+            set_error("translation box must be finite");
+            return DSES_E_INVAL;
+        }
+        const double kl = std::ceil((double)lo[a] / (double)p->delta - 1e-4);
+        const double kh = std::floor((double)hi[a] / (double)p->delta + 1e-4);
+        if (!(kh >= kl) || kh - kl + 1 > 4096 || std::fabs(kl) > 1e6 || std::fabs(kh) > 1e6) {
+            set_error("translation box is empty or has more than 4096 bins per axis");
+            return DSES_E_INVAL;
+        }
+        p->klo[a] = (int32_t)kl;
+        p->size[a] = (int32_t)(kh - kl + 1);
+    }
+    return DSES_OK;
+}
+
+dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, int counter_bits,
+                      Geom *g)
+{
+    (void)c;
+    g->n = n;
+    g->m = m;
+    g->delta = p.delta;
+    g->s = 1.0f / p.delta;
+    g->eps = p.eps;
+    g->tau = p.tau;
+    g->r = p.r;
+    g->metric = p.metric;
+    for (int a = 0; a < 3; ++a) { g->klo[a] = p.klo[a]; g->size[a] = p.size[a]; }
+    g->counter_bits = counter_bits;
+    g->row_words = counter_bits == 16 ? (p.size[2] + 1) / 2 : p.size[2];
+    const int64_t plane_words = (int64_t)p.size[1] * g->row_words;
+    const int64_t avail = kHistWordsMax & ~int64_t(3);
+    int64_t pps = avail / plane_words;
+    if (pps < 1) {
+        set_error("translation box plane (size_y * size_z bins) does not fit in LDS");
+        return DSES_E_INVAL;
+    }
+    pps = std::min<int64_t>(pps, p.size[0]);
+    const int64_t nslabs = (p.size[0] + pps - 1) / pps;
+    pps = (p.size[0] + nslabs - 1) / nslabs;
+    g->pps = (int32_t)pps;
+    g->nslabs = (int32_t)nslabs;
+    g->slab_words = (int32_t)(pps * plane_words);
+    return DSES_OK;
+}
+
+// Largest vote count any bin can reach: for a fixed source point the pairs that
+// share a bin have reference points inside one cube of side delta (widened by the
+// float rounding of the bin decision), and such a cube meets at most 2 cells per
+// axis of a grid of pitch slightly above delta.  So every count is at most
+// n * (largest reference population of a 2x2x2 block of cells).
+int64_t counter_bound(const float *tgt, int32_t m, int32_t n, const Params &p)
+{
+    double maxabs = 0.0;
+    for (int64_t e = 0; e < 3 * (int64_t)m; ++e) maxabs = std::max(maxabs, (double)std::fabs(tgt[e]));
+    int32_t kmax = 0;
+    for (int a = 0; a < 3; ++a) kmax = std::max(kmax, std::abs(p.klo[a]) + p.size[a]);
+    const double s = 1.0 / (double)p.delta;
+    const double slack = 16.0 * 5.97e-8 * (4.0 * maxabs * s + kmax + 2.0);   // bin units
+    const double h = (double)p.delta * (1.0 + std::max(1e-3, 4.0 * slack));
+    std::unordered_map<int64_t, int32_t> cell;
+    cell.reserve((size_t)m * 2);
+    auto key = [](int64_t x, int64_t y, int64_t z) {
+        return ((x + (1 << 20)) << 42) | ((y + (1 << 20)) << 21) | (z + (1 << 20));
+    };
+    std::vector<int64_t> ids((size_t)m * 3);
+    for (int32_t j = 0; j < m; ++j)
+        for (int a = 0; a < 3; ++a)
+            ids[3 * (size_t)j + a] = (int64_t)std::floor((double)tgt[3 * j + a] / h);
+    for (int32_t j = 0; j < m; ++j)
+        cell[key(ids[3 * j], ids[3 * j + 1], ids[3 * j + 2])] += 1;
+    int64_t best = 0;
+    for (const auto &kv : cell) {
+        const int64_t z = (kv.first & ((1 << 21) - 1)) - (1 << 20);
+        const int64_t y = ((kv.first >> 21) & ((1 << 21) - 1)) - (1 << 20);
+        const int64_t x = (kv.first >> 42) - (1 << 20);
+        for (int ox = -1; ox <= 0; ++ox)
+            for (int oy = -1; oy <= 0; ++oy)
+                for (int oz = -1; oz <= 0; ++oz) {
+                    int64_t tot = 0;
+                    for (int dx = 0; dx < 2; ++dx)
+                        for (int dy = 0; dy < 2; ++dy)
+                            for (int dz = 0; dz < 2; ++dz) {
+                                auto it = cell.find(key(x + ox + dx, y + oy + dy, z + oz + dz));
+                                if (it != cell.end()) tot += it->second;
+                            }
+                    best = std::max(best, tot);
+                }
+    }
+    return best * (int64_t)n;
+}
+
+// ---------------------------------------------------------------------------
+// exact cell grid (host build)
+// ---------------------------------------------------------------------------
+dses_status build_grid(const float *tgt, int32_t m, float r, HostGrid *out)
+{
+    // Cell pitch slightly above r so that, despite float rounding of the cell
+    // index, every reference point within r of a query is in the 27 cells around
+    // the query's cell.
+    const float h = r * 1.001f;
+    out->inv = 1.0f / h;
+    float mn[3] = {tgt[0], tgt[1], tgt[2]}, mx[3] = {tgt[0], tgt[1], tgt[2]};
+    for (int32_t j = 1; j < m; ++j)
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = std::min(mn[a], tgt[3 * j + a]);
+            mx[a] = std::max(mx[a], tgt[3 * j + a]);
+        }
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        out->lo[a] = mn[a];
+        const double span = ((double)mx[a] - (double)mn[a]) * (double)out->inv;
+        out->dim[a] = (int32_t)std::floor(span) + 2;
+        ncell *= out->dim[a];
+    }
+    if (ncell > (int64_t)64 << 20) {
+        set_error("reference extent too large for the cell grid at this eps/tau");
+        return DSES_E_INVAL;
+    }
+    std::vector<int32_t> cell(m);
+    out->start.assign((size_t)ncell + 1, 0);
+    for (int32_t j = 0; j < m; ++j) {
+        int32_t id[3];
+        for (int a = 0; a < 3; ++a) {
+            const float u = (tgt[3 * j + a] - out->lo[a]) * out->inv;
+            id[a] = std::min(std::max((int32_t)std::floor(u), 0), out->dim[a] - 1);
+        }
+        cell[j] = (id[0] * out->dim[1] + id[1]) * out->dim[2] + id[2];
+        out->start[cell[j] + 1]++;
+    }
+    for (int64_t q = 0; q < ncell; ++q) out->start[q + 1] += out->start[q];
+    std::vector<int32_t> cur(out->start.begin(), out->start.end() - 1);
+    out->pts.assign((size_t)3 * m, 0.0f);
+    for (int32_t j = 0; j < m; ++j) {
+        const int32_t at = cur[cell[j]]++;
+        for (int a = 0; a < 3; ++a) out->pts[(size_t)a * m + at] = tgt[3 * j + a];
+    }
+    return DSES_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host-side input checks
+// ---------------------------------------------------------------------------
+float coord_limit(const Params &p)
+{
+    int32_t kmax = 0;
+    for (int a = 0; a < 3; ++a)
+        kmax = std::max(kmax, std::max(std::abs(p.klo[a]), std::abs(p.klo[a] + p.size[a])));
+    const double lim = ((double)(1 << 22) - kmax - 4.0) * (double)p.delta / 4.0;
+    return (float)std::min(std::max(lim, 0.0), 1.0e4);
+}
+
+static dses_status check_host_inputs(const float *src, int64_t n, const float *tgt, int64_t m,
+                                     const float *rot, int64_t k, float limit)
+{
+    for (int64_t e = 0; e < 3 * n; ++e)
+        if (!(std::fabs(src[e]) <= limit)) {
+            set_error("source coordinate is non-finite or too large for the lattice");
+            return DSES_E_INVAL;
+        }
+    if (tgt)
+        for (int64_t e = 0; e < 3 * m; ++e)
+            if (!(std::fabs(tgt[e]) <= limit)) {
+                set_error("reference coordinate is non-finite or too large for the lattice");
+                return DSES_E_INVAL;
+            }
+    if (rot)
+        for (int64_t q = 0; q < k; ++q) {
+            const float *R = rot + 9 * q;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    float d = R[i] * R[j] + R[3 + i] * R[3 + j] + R[6 + i] * R[6 + j];
+                    d -= (i == j) ? 1.0f : 0.0f;
+                    if (!(std::fabs(d) <= 1e-4f)) {
+                        set_error("rotation " + std::to_string(q) +
+                                  " is not orthonormal (|R^T R - I| > 1e-4) or not finite");
+                        return DSES_E_INVAL;
+                    }
+                }
+        }
+    return DSES_OK;
+}
+
+void add_stats(Context *c, double vote_ms, double score_ms, double select_ms, double stage_ms,
+               int64_t launches, int64_t pairs_voted, int64_t pairs_scored, int64_t cands)
+{
+    std::lock_guard<std::mutex> lk(c->stats_mu);
+    c->stats.vote_score_ms += vote_ms;
+    c->stats.score_ms += score_ms;
+    c->stats.select_ms += select_ms;
+    c->stats.stage_ms += stage_ms;
+    c->stats.vote_score_launches += launches;
+    c->stats.pairs_voted += pairs_voted;
+    c->stats.pairs_scored += pairs_scored;
+    c->stats.candidates += cands;
+}
+
+static int effective_scorer(const Job &job)
+{
+    int s = job.p.scorer;
+    if (s == DSES_SCORER_AUTO)
+        s = (job.target && job.target->df && job.target->df_r == job.p.r &&
+             job.p.metric != DSES_TRUNC_L1)
+                ? DSES_SCORER_DF
+                : DSES_SCORER_GRID;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// the plain driver
+// ---------------------------------------------------------------------------
+dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check_inputs,
+                      dses_result *out, void *records, bool records_on_device)
+{
+    const Params &p = job.p;
+    const int scorer = effective_scorer(job);
+    if (scorer == DSES_SCORER_DF) {
+        if (!job.target || !job.target->df) {
+            set_error("DF scorer needs a resident target created with a distance field");
+            return DSES_E_INVAL;
+        }
+        if (job.target->df_r != p.r) {
+            set_error("distance field truncation must equal max(eps, tau)");
+            return DSES_E_INVAL;
+        }
+        if (p.metric == DSES_TRUNC_L1) {
+            set_error("the DF scorer does not support DSES_TRUNC_L1");
+            return DSES_E_INVAL;
+        }
+    }
+    const size_t m = (size_t)job.m;
+    dses_status st;
+    // host copy of the reference: needed for the counter bound and the cell grid
+    std::vector<float> host_copy;
+    const float *ht = job.target ? job.target->host_aos.data() : job.host_tgt;
+    if (!ht) {
+        host_copy.resize(3 * m);
+        DSES_HIP(hipMemcpyAsync(host_copy.data(), job.tgt, 3 * m * sizeof(float),
+                                hipMemcpyDeviceToHost, stream));
+        DSES_HIP(hipStreamSynchronize(stream));
+        for (float v : host_copy)
+            if (!(std::fabs(v) <= coord_limit(p))) {
+                set_error("reference coordinate is non-finite or too large for the lattice");
+                return DSES_E_INVAL;
+            }
+        ht = host_copy.data();
+    }
+    const int counter_bits = counter_bound(ht, job.m, job.n, p) <= 65535 ? 16 : 32;
+    Geom g;
+    if ((st = plan_geom(c, p, job.n, job.m, counter_bits, &g)) != DSES_OK) return st;
+
+    if ((st = c->ys.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
+    if ((st = c->yt.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
+    if ((st = c->rec.ensure((size_t)job.k * sizeof(dses_record))) != DSES_OK) return st;
+    if ((st = c->res.ensure(sizeof(DevResult))) != DSES_OK) return st;
+    if ((st = c->status.ensure(64)) != DSES_OK) return st;
+    uint32_t *bad = static_cast<uint32_t *>(c->status.ptr);
+
+    SweepArgs a{};
+    a.src = job.src;
+    a.rot = job.rot;
+    a.ys = static_cast<float *>(c->ys.ptr);
+    a.yt = static_cast<float *>(c->yt.ptr);
+    a.rec = static_cast<dses_record *>(c->rec.ptr);
+    a.k = job.k;
+    a.g = g;
+
+    if (scorer == DSES_SCORER_GRID) {
+        const TargetRes *t = job.target;
+        if (t) {
+            auto *tm = const_cast<TargetRes *>(t);
+            std::lock_guard<std::mutex> lk(tm->grid_mu);
+            if (tm->grid_r != p.r) {
+                HostGrid hg;
+                if ((st = build_grid(tm->host_aos.data(), tm->m, p.r, &hg)) != DSES_OK) return st;
+                if (tm->grid_pts) (void)hipFree(tm->grid_pts);
+                if (tm->grid_start) (void)hipFree(tm->grid_start);
+                tm->grid_pts = nullptr;
+                tm->grid_start = nullptr;
+                DSES_HIP(hipMalloc(&tm->grid_pts, hg.pts.size() * sizeof(float)));
+                DSES_HIP(hipMalloc(&tm->grid_start, hg.start.size() * sizeof(int32_t)));
+                DSES_HIP(hipMemcpy(tm->grid_pts, hg.pts.data(), hg.pts.size() * sizeof(float),
+                                   hipMemcpyHostToDevice));
+                DSES_HIP(hipMemcpy(tm->grid_start, hg.start.data(),
+                                   hg.start.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+                hg.pts.clear();
+                hg.start.clear();
+                tm->grid_meta = hg;
+                tm->grid_r = p.r;
+            }
+            a.grid.pts = tm->grid_pts;
+            a.grid.start = tm->grid_start;
+            for (int q = 0; q < 3; ++q) {
+                a.grid.lo[q] = tm->grid_meta.lo[q];
+                a.grid.dim[q] = tm->grid_meta.dim[q];
+            }
+            a.grid.inv = tm->grid_meta.inv;
+        } else {
+            HostGrid hg;
+            if ((st = build_grid(ht, job.m, p.r, &hg)) != DSES_OK) return st;
+            if ((st = c->grid_pts.ensure(hg.pts.size() * sizeof(float))) != DSES_OK) return st;
+            if ((st = c->grid_start.ensure(hg.start.size() * sizeof(int32_t))) != DSES_OK)
+                return st;
+            DSES_HIP(hipMemcpyAsync(c->grid_pts.ptr, hg.pts.data(), hg.pts.size() * sizeof(float),
+                                    hipMemcpyHostToDevice, stream));
+            DSES_HIP(hipMemcpyAsync(c->grid_start.ptr, hg.start.data(),
+                                    hg.start.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                    stream));
+            DSES_HIP(hipStreamSynchronize(stream));     // host vectors go out of scope
+            a.grid.pts = static_cast<float *>(c->grid_pts.ptr);
+            a.grid.start = static_cast<int32_t *>(c->grid_start.ptr);
+            for (int q = 0; q < 3; ++q) { a.grid.lo[q] = hg.lo[q]; a.grid.dim[q] = hg.dim[q]; }
+            a.grid.inv = hg.inv;
+        }
+    } else if (scorer == DSES_SCORER_DF) {
+        const TargetRes *t = job.target;
+        a.field.val = t->df;
+        a.field.res = t->df_res;
+        a.field.r = t->df_r;
+        for (int q = 0; q < 3; ++q) { a.field.lo[q] = t->df_lo[q]; a.field.inv[q] = t->df_inv[q]; }
+    }
+
+    const bool timing = c->timing_enabled;
+    hipEvent_t ev[4] = {};
+    if (timing)
+        for (auto &e : ev) DSES_HIP(hipEventCreate(&e));
+    auto rec_ev = [&](int i) { if (timing) (void)hipEventRecord(ev[i], stream); };
+
+    rec_ev(0);
+    DSES_HIP(launch_clear(bad, 16, stream));
+    if (check_inputs) {
+        CheckArgs ca{job.src, job.n, job.tgt, job.m, job.rot, job.k, coord_limit(p), bad};
+        DSES_HIP(launch_check(ca, stream));
+    }
+    DSES_HIP(launch_stage(job.tgt, job.m, g.s, p.klo, static_cast<float *>(c->ys.ptr),
+                          static_cast<float *>(c->yt.ptr), stream));
+    rec_ev(1);
+    DSES_HIP(launch_sweep(a, scorer, stream));
+    rec_ev(2);
+    DSES_HIP(launch_select(a.rec, job.k, job.rot, p.delta, static_cast<DevResult *>(c->res.ptr),
+                           bad, stream));
+    rec_ev(3);
+    DSES_HIP(hipMemcpyAsync(c->host_res, c->res.ptr, sizeof(DevResult), hipMemcpyDeviceToHost,
+                            stream));
+    DSES_HIP(hipStreamSynchronize(stream));
+    const DevResult r = *c->host_res;
+    if (timing) {
+        float t01 = 0, t12 = 0, t23 = 0;
+        (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
+        (void)hipEventElapsedTime(&t23, ev[2], ev[3]);
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        const int64_t pairs = (int64_t)job.n * job.m * job.k;
+        add_stats(c, t12, 0.0, t23, t01, 1, pairs, scorer == DSES_SCORER_BRUTE ? pairs : 0, job.k);
+    }
+    if (r.bad_input) {
+        set_error("non-finite or out-of-range coordinate, or non-orthonormal rotation");
+        return DSES_E_INVAL;
+    }
+    if (r.rot_index < 0) {
+        set_error("no rotation received a vote inside the translation box");
+        return DSES_E_NOCANDIDATE;
+    }
+    if (records) {
+        DSES_HIP(hipMemcpyAsync(records, a.rec, (size_t)job.k * sizeof(dses_record),
+                                records_on_device ? hipMemcpyDeviceToDevice
+                                                  : hipMemcpyDeviceToHost,
+                                stream));
+        DSES_HIP(hipStreamSynchronize(stream));
+    }
+    if (out) {
+        std::memcpy(out->R, r.R, sizeof(out->R));
+        std::memcpy(out->t, r.t, sizeof(out->t));
+        out->rot_index = r.rot_index;
+        out->inliers = r.inliers;
+        out->error = r.error;
+        out->votes = r.votes;
+        out->n_valid = r.n_valid;
+    }
+    return DSES_OK;
+}
+
+}  // namespace dses
+
+using namespace dses;
+
+extern "C" {
+
+const char *dses_last_error(void) { return g_err.c_str(); }
+
+const char *dses_version(void) { return "dses-mi355x 0.1"; }
+
+dses_status dses_init(int32_t device) { return init_device(device); }
+
+dses_status dses_kernel_stats(dses_kstats *out, int32_t reset)
+{
+    Context *c = ctx();
+    if (!c) return DSES_E_DEVICE;
+    std::lock_guard<std::mutex> lk(c->stats_mu);
+    if (out) *out = c->stats;
+    if (reset) c->stats = dses_kstats{};
+    return DSES_OK;
+}
+
+dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t m,
+                          const float *rotations, int64_t k, float eps, dses_metric metric,
+                          const dses_options *opt, dses_result *out)
+{
+    set_error("");
+    if (!src || !tgt || !rotations || !out) {
+        set_error("NULL pointer argument");
+        return DSES_E_INVAL;
+    }
+    if (n <= 0 || m <= 0 || k <= 0 || k > INT32_MAX || n * m >= ((int64_t)1 << 31)) {
+        set_error("n, m, k must be positive with n*m < 2^31 and k < 2^31");
+        return DSES_E_INVAL;
+    }
+    dses_options o{};
+    if (opt) {
+        if (opt->struct_size != 0 && opt->struct_size < sizeof(dses_options)) {
+            set_error("dses_options.struct_size too small");
+            return DSES_E_INVAL;
+        }
+        o = *opt;
+    }
+    Params p;
+    dses_status st = resolve_params(eps, metric, o.delta_t, o.tau, o.t_min, o.t_max, o.scorer, &p);
+    if (st != DSES_OK) return st;
+    if (p.scorer == DSES_SCORER_DF) {
+        set_error("the DF scorer needs a resident target (dses_register_resident)");
+        return DSES_E_INVAL;
+    }
+    const bool dev = (o.flags & DSES_DEVICE_PTRS) != 0;
+    if (!dev) {
+        st = check_host_inputs(src, n, tgt, m, rotations, k, coord_limit(p));
+        if (st != DSES_OK) return st;
+    }
+    Context *c = ctx();
+    if (!c) return DSES_E_DEVICE;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timing_enabled = (o.flags & DSES_TIMING) != 0;
+    hipStream_t stream = o.stream ? static_cast<hipStream_t>(o.stream) : c->stream;
+    Job job;
+    job.n = (int32_t)n;
+    job.m = (int32_t)m;
+    job.k = (int32_t)k;
+    job.p = p;
+    if (dev) {
+        job.src = src;
+        job.tgt = tgt;
+        job.rot = rotations;
+    } else {
+        if ((st = c->in_src.ensure(3 * n * sizeof(float))) != DSES_OK) return st;
+        if ((st = c->in_tgt.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
+        if ((st = c->in_rot.ensure(9 * k * sizeof(float))) != DSES_OK) return st;
+        DSES_HIP(hipMemcpyAsync(c->in_src.ptr, src, 3 * n * sizeof(float), hipMemcpyHostToDevice,
+                                stream));
+        DSES_HIP(hipMemcpyAsync(c->in_tgt.ptr, tgt, 3 * m * sizeof(float), hipMemcpyHostToDevice,
+                                stream));
+        DSES_HIP(hipMemcpyAsync(c->in_rot.ptr, rotations, 9 * k * sizeof(float),
+                                hipMemcpyHostToDevice, stream));
+        job.src = static_cast<float *>(c->in_src.ptr);
+        job.tgt = static_cast<float *>(c->in_tgt.ptr);
+        job.rot = static_cast<float *>(c->in_rot.ptr);
+        job.host_tgt = tgt;
+    }
+    return run_plain(c, job, stream, dev, out, o.records, dev);
+}
+
+}  // extern "C"

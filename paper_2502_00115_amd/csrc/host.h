@@ -1,0 +1,136 @@
+// Host-side internals of the DSES library: device context, workspace, argument
+// resolution and the registration driver shared by the plain, resident, batched
+// and serving entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dses.h"
+#include "internal.h"
+
+namespace dses {
+
+void set_error(const std::string &msg);
+
+#define DSES_HIP(expr)                                                                      \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess) {                                                             \
+            ::dses::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));           \
+            return DSES_E_DEVICE;                                                           \
+        }                                                                                   \
+    } while (0)
+
+// A device allocation that grows on demand (never shrinks while in use).
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    dses_status ensure(size_t want);
+    void release();
+    ~DevBuf() { release(); }
+};
+
+struct Context {
+    int device = -1;
+    int n_cu = 0;
+    int lds_max = 0;
+    std::string arch;
+    hipStream_t stream = nullptr;
+    std::mutex mu;                       // serialises the plain entry points
+    // workspace of the plain path
+    DevBuf in_src, in_tgt, in_rot, ys, yt, rec, res, status, grid_pts, grid_start;
+    DevResult *host_res = nullptr;       // pinned
+    // timing
+    bool timing_enabled = false;
+    std::mutex stats_mu;
+    dses_kstats stats{};
+};
+
+// Returns the initialised context or nullptr (error set).
+Context *ctx();
+
+// Resolved numeric parameters of one registration.
+struct Params {
+    float eps, delta, tau, r;
+    int32_t klo[3], size[3];
+    int metric;
+    int scorer;
+};
+
+dses_status resolve_params(float eps, int metric, float delta_t, float tau, const float *t_min,
+                           const float *t_max, int scorer, Params *p);
+// Largest |coordinate| accepted for a registration with these parameters.
+float coord_limit(const Params &p);
+
+dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, int counter_bits,
+                      Geom *g);
+// Upper bound on any bin's vote count (decides 16- vs 32-bit LDS counters).
+int64_t counter_bound(const float *tgt_aos, int32_t m, int32_t n, const Params &p);
+
+// Exact cell grid for the GRID scorer, built on the host from reference points.
+struct HostGrid {
+    std::vector<float> pts;      // SoA, cell order
+    std::vector<int32_t> start;  // ncell + 1
+    float lo[3];
+    float inv;
+    int32_t dim[3];
+};
+dses_status build_grid(const float *tgt_aos, int32_t m, float r, HostGrid *out);
+
+// Resident reference cloud.
+struct TargetRes {
+    int32_t m = 0;
+    float *aos = nullptr;            // m x 3 device copy
+    float *yt = nullptr;             // SoA device copy
+    std::vector<float> host_aos;     // host copy (grid builds)
+    // distance field
+    float *df = nullptr;
+    int32_t df_res = 0;
+    float df_r = 0.0f;
+    float df_lo[3] = {0, 0, 0}, df_h[3] = {0, 0, 0}, df_inv[3] = {0, 0, 0};
+    // cached cell grid (for one r)
+    std::mutex grid_mu;
+    float grid_r = -1.0f;
+    float *grid_pts = nullptr;
+    int32_t *grid_start = nullptr;
+    HostGrid grid_meta;
+};
+
+struct RotRes {
+    int64_t k = 0;
+    float *rot = nullptr;            // k x 9 device copy
+};
+
+// Everything the driver needs about one registration, with device pointers.
+struct Job {
+    const float *src = nullptr;      // n x 3, device
+    int32_t n = 0;
+    const float *tgt = nullptr;      // m x 3, device (AoS)
+    int32_t m = 0;
+    const float *rot = nullptr;      // k x 9, device
+    int32_t k = 0;
+    Params p{};
+    const TargetRes *target = nullptr;   // resident reference (grid / field source)
+    const float *host_tgt = nullptr;     // host AoS copy of the reference, if known
+};
+
+// Run one registration on `stream` using the context workspace (caller holds c->mu).
+dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check_inputs,
+                      dses_result *out, void *records, bool records_on_device);
+
+void add_stats(Context *c, double vote_ms, double score_ms, double select_ms, double stage_ms,
+               int64_t launches, int64_t pairs_voted, int64_t pairs_scored, int64_t cands);
+
+// Distance field build (device), defined in field.hip.
+hipError_t launch_df_build(const float *pts_soa, const int32_t *start, const HostGrid &grid,
+                           int32_t res, const float *lo, const float *h, float r, float *out,
+                           hipStream_t stream);
+
+}  // namespace dses

@@ -1,0 +1,93 @@
+// Internal declarations shared by the DSES device kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dses.h"
+
+namespace dses {
+
+constexpr int kBlock = 1024;            // threads per sweep workgroup (16 wave64s)
+constexpr int kWaves = kBlock / 64;
+constexpr int kLdsWords = 40960;        // 160 KB of LDS per workgroup on gfx950
+constexpr int kScratchWords = 256;      // LDS words reserved after the vote array
+constexpr int kHistWordsMax = kLdsWords - kScratchWords;
+
+// Per-registration constants of the sweep.
+struct Geom {
+    int32_t n, m;          // source / reference sizes
+    float s;               // 1/delta (float division)
+    float delta;           // lattice pitch
+    float eps, tau;        // inlier threshold, truncation
+    float r;               // max(eps, tau): the only neighbourhood that matters
+    int32_t klo[3];        // lattice index of bin 0 per axis
+    int32_t size[3];       // bins per axis
+    int32_t metric;        // dses_metric
+    int32_t counter_bits;  // 16: two counters per LDS word (z rows padded to even), 32: one
+    int32_t row_words;     // LDS words per z row: (size_z + 1) / 2 or size_z
+    int32_t pps;           // x-planes per LDS slab
+    int32_t nslabs;        // slabs covering size[0]
+    int32_t slab_words;    // LDS words of one full slab (<= kHistWordsMax)
+};
+
+// Uniform cell grid over the reference for the exact GRID scorer.
+struct CellGrid {
+    const float *pts;      // reference points in cell order, SoA (3 * m floats)
+    const int32_t *start;  // cell start offsets, ncell + 1 entries
+    float lo[3];           // grid origin
+    float inv;             // 1 / cell pitch
+    int32_t dim[3];        // cells per axis
+};
+
+// Voxel distance field for the DF scorer.
+struct Field {
+    const float *val;      // res^3 values, x slowest
+    float lo[3];
+    float inv[3];          // 1 / voxel pitch per axis
+    int32_t res;
+    float r;               // value outside the grid
+};
+
+struct SweepArgs {
+    const float *src;      // n x 3 AoS
+    const float *rot;      // K x 9
+    const float *ys;       // scaled + offset reference, SoA (3 * m)
+    const float *yt;       // reference, SoA (3 * m)
+    Geom g;
+    CellGrid grid;
+    Field field;
+    dses_record *rec;      // one record per rotation index
+    int32_t k;             // rotations
+};
+
+// Result written on the device by the select kernel.
+struct DevResult {
+    int32_t rot_index;
+    uint32_t votes;
+    int32_t inliers;
+    float error;
+    float t[3];
+    float R[9];
+    int32_t n_valid;
+    uint32_t bad_input;
+};
+
+struct CheckArgs {
+    const float *src; int32_t n;
+    const float *tgt; int32_t m;
+    const float *rot; int32_t k;
+    float coord_limit;     // max |coordinate| accepted
+    uint32_t *bad;         // set to non-zero on invalid input
+};
+
+// Launchers (defined in kernels.hip); all enqueue on `stream`.
+hipError_t launch_check(const CheckArgs &a, hipStream_t stream);
+hipError_t launch_stage(const float *tgt, int32_t m, float s, const int32_t *klo, float *ys,
+                        float *yt, hipStream_t stream);
+hipError_t launch_sweep(const SweepArgs &a, int scorer, hipStream_t stream);
+hipError_t launch_select(const dses_record *rec, int32_t k, const float *rot, float delta,
+                         DevResult *res, const uint32_t *status, hipStream_t stream);
+hipError_t launch_clear(uint32_t *p, int32_t words, hipStream_t stream);
+
+}  // namespace dses

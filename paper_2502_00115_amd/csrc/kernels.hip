@@ -1,0 +1,613 @@
+// DSES device kernels for CDNA4 (gfx950): input staging, the fused per-rotation
+// sweep (vote -> mode -> score) and candidate selection.
+//
+// Sweep design (one workgroup of 16 wave64s per rotation):
+//  * Source points live in registers, one per lane; the rotation is applied once
+//    per point (FMA chain of the header's ROUND definition).
+//  * Reference points are wave-uniform: every lane of a wave walks the same
+//    reference index, so the compiler loads them through the scalar unit into
+//    SGPRs and the vector ALU only does pair arithmetic.
+//  * The vote array of Alg. 2 lives in LDS as 16-bit counters packed two per
+//    32-bit word (incremented with ds_add_u32 of 1 or 1<<16), so the 41^3 box of
+//    delta = 0.05 fits one 160 KB LDS allocation.  Larger boxes are swept in
+//    x-slabs that each fit LDS.  16-bit counters are used only when the host has
+//    proven that no bin can reach 2^16 votes (see counter_bound in api.hip);
+//    otherwise every counter is 32-bit.
+//  * The mode is an LDS scan (count, then lowest linear index) reduced with
+//    wave64 shuffles.
+//  * Scoring reuses the lanes' source points; the error sum is a fixed-order tree,
+//    so a rotation's record does not depend on what else runs on the GPU.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace dses {
+
+// floor to int32 in one VALU op (v_cvt_flr_i32_f32: D = (int)floor(S0)).
+__device__ __forceinline__ int cvt_flr(float x)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// 24-bit multiply-add (v_mad_u32_u24: D = a[23:0] * b[23:0] + c, 32-bit wrap);
+// written as asm so the compiler keeps one instruction instead of mul + add3.
+__device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
+// (a << 2) + b in one instruction (v_lshl_add_u32); b is wave-uniform.
+__device__ __forceinline__ uint32_t lshl2_add(uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, %1, 2, %2" : "=v"(r) : "v"(a), "s"(b));
+    return r;
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// p = R x with the header's FMA chain (float).
+__device__ __forceinline__ void rotate(const float *R, float x, float y, float z, float &px,
+                                       float &py, float &pz)
+{
+    px = fmaf(R[2], z, fmaf(R[1], y, __fmul_rn(R[0], x)));
+    py = fmaf(R[5], z, fmaf(R[4], y, __fmul_rn(R[3], x)));
+    pz = fmaf(R[8], z, fmaf(R[7], y, __fmul_rn(R[6], x)));
+}
+
+// (count desc, lin asc) reduction step.
+__device__ __forceinline__ void better(uint32_t &c, uint32_t &l, uint32_t oc, uint32_t ol)
+{
+    if (oc > c || (oc == c && ol < l)) { c = oc; l = ol; }
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_isum(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// --------------------------------------------------------------------------
+// input checks (device-pointer inputs): finiteness, coordinate range, rotations
+// --------------------------------------------------------------------------
+__global__ void k_check(CheckArgs a)
+{
+    const int64_t total = (int64_t)a.n * 3 + (int64_t)a.m * 3 + a.k;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        bool bad = false;
+        if (e < (int64_t)a.n * 3) {
+            float v = a.src[e];
+            bad = !(fabsf(v) <= a.coord_limit);
+        } else if (e < (int64_t)a.n * 3 + (int64_t)a.m * 3) {
+            float v = a.tgt[e - (int64_t)a.n * 3];
+            bad = !(fabsf(v) <= a.coord_limit);
+        } else {
+            const float *R = a.rot + 9 * (e - (int64_t)a.n * 3 - (int64_t)a.m * 3);
+            float worst = 0.0f;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    float d = R[i] * R[j] + R[3 + i] * R[3 + j] + R[6 + i] * R[6 + j];
+                    d -= (i == j) ? 1.0f : 0.0f;
+                    worst = fmaxf(worst, fabsf(d));
+                }
+            bad = !(worst <= 1e-4f);
+        }
+        if (bad) atomicOr(a.bad, 1u);
+    }
+}
+
+hipError_t launch_check(const CheckArgs &a, hipStream_t stream)
+{
+    const int64_t total = (int64_t)a.n * 3 + (int64_t)a.m * 3 + a.k;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_check, dim3(blocks), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// staging: reference AoS -> SoA, plus the scaled/offset copy used for binning
+//   ys_a = (y_a * s) + (0.5 - k_lo_a)   (two float roundings, as in the header)
+// --------------------------------------------------------------------------
+__global__ void k_stage(const float *tgt, int32_t m, float s, int32_t klo0, int32_t klo1,
+                        int32_t klo2, float *ys, float *yt)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int klo[3] = {klo0, klo1, klo2};
+    for (int a = 0; a < 3; ++a) {
+        float y = tgt[3 * j + a];
+        float ofs = 0.5f - (float)klo[a];
+        ys[a * m + j] = __fadd_rn(__fmul_rn(y, s), ofs);
+        yt[a * m + j] = y;
+    }
+}
+
+hipError_t launch_stage(const float *tgt, int32_t m, float s, const int32_t *klo, float *ys,
+                        float *yt, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_stage, dim3((m + 255) / 256), dim3(256), 0, stream, tgt, m, s, klo[0],
+                       klo[1], klo[2], ys, yt);
+    return hipGetLastError();
+}
+
+__global__ void k_clear(uint32_t *p, int32_t words)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_clear(uint32_t *p, int32_t words, hipStream_t stream)
+{
+    int blocks = (words + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_clear, dim3(blocks), dim3(256), 0, stream, p, words);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// the fused sweep
+// --------------------------------------------------------------------------
+
+// Read-only inputs are read through the constant address space so that
+// wave-uniform indices compile to scalar loads (s_load) into SGPRs.
+typedef const float __attribute__((address_space(4))) *kfloat;
+typedef const int32_t __attribute__((address_space(4))) *kint;
+__device__ __forceinline__ kfloat kc(const float *p) { return (kfloat)p; }
+__device__ __forceinline__ kint kc(const int32_t *p) { return (kint)p; }
+
+// Lane layout for a chunk of up to 1024 source points: `sw` waves hold the chunk
+// (one point per lane) and the reference is split into G partitions, one per
+// group of sw waves, when the chunk is small.
+struct ChunkLayout {
+    int sw, G, part, i;
+    bool active;
+};
+
+__device__ __forceinline__ ChunkLayout chunk_layout(int c0, int n, int wave, int lane)
+{
+    ChunkLayout L;
+    const int nc = min(kBlock, n - c0);
+    L.sw = (nc + 63) >> 6;
+    L.G = max(1, kWaves / L.sw);
+    L.part = wave / L.sw;
+    L.active = L.part < L.G;
+    L.i = c0 + (wave % L.sw) * 64 + lane;
+    return L;
+}
+
+// One pair's vote.  c* are the box-relative bin coordinates; the x range check is
+// against the current slab [x0, x0 + np).  Byte address in LDS:
+//   16-bit: ((cx - x0) * Sy + cy) * row_words * 4 + (cz >> 1) * 4, half = cz & 1
+//   32-bit: ((cx - x0) * Sy + cy) * Sz * 4 + cz * 4
+template <int CW>
+__device__ __forceinline__ void vote_pair(uint32_t *hist, int cx, int cy, int cz, int x0,
+                                          uint32_t np, uint32_t Sy, uint32_t Sz, uint32_t sx4,
+                                          uint32_t sy4, uint32_t negc)
+{
+    if ((uint32_t)(cx - x0) < np && (uint32_t)cy < Sy && (uint32_t)cz < Sz) {
+        if (CW == 16) {
+            const uint32_t zb = lshl2_add((uint32_t)cz >> 1, negc);
+            const uint32_t addr = mad24((uint32_t)cx, sx4, mad24((uint32_t)cy, sy4, zb));
+            atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(hist) + addr),
+                      1u << (((uint32_t)cz << 4) & 31u));
+        } else {
+            const uint32_t zb = lshl2_add((uint32_t)cz, negc);
+            const uint32_t addr = mad24((uint32_t)cx, sx4, mad24((uint32_t)cy, sy4, zb));
+            atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(hist) + addr), 1u);
+        }
+    }
+}
+
+template <int CW>
+__device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, uint32_t *hist)
+{
+    const Geom &g = a.g;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t Sy = g.size[1], Sz = g.size[2];
+    const uint32_t sy4 = 4u * (uint32_t)g.row_words, sx4 = sy4 * Sy;
+    const uint32_t negc = 0u - (uint32_t)x0 * sx4;
+    const int m = g.m;
+    const kfloat ysx = kc(a.ys), ysy = kc(a.ys + m), ysz = kc(a.ys + 2 * m);
+    for (int c0 = 0; c0 < g.n; c0 += kBlock) {
+        const ChunkLayout L = chunk_layout(c0, g.n, wave, lane);
+        if (!L.active) continue;
+        float Px = 1.0e7f, Py = 1.0e7f, Pz = 1.0e7f;      // padding lanes never vote
+        if (L.i < g.n) {
+            float px, py, pz;
+            rotate(R, a.src[3 * L.i], a.src[3 * L.i + 1], a.src[3 * L.i + 2], px, py, pz);
+            Px = __fmul_rn(px, g.s);
+            Py = __fmul_rn(py, g.s);
+            Pz = __fmul_rn(pz, g.s);
+        }
+        const int j0 = uni((int)((int64_t)m * L.part / L.G));
+        const int j1 = uni((int)((int64_t)m * (L.part + 1) / L.G));
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+            int cx[4], cy[4], cz[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                cx[u] = cvt_flr(ysx[j + u] - Px);
+                cy[u] = cvt_flr(ysy[j + u] - Py);
+                cz[u] = cvt_flr(ysz[j + u] - Pz);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                vote_pair<CW>(hist, cx[u], cy[u], cz[u], x0, (uint32_t)np, Sy, Sz, sx4, sy4, negc);
+        }
+        for (; j < j1; ++j)
+            vote_pair<CW>(hist, cvt_flr(ysx[j] - Px), cvt_flr(ysy[j] - Py), cvt_flr(ysz[j] - Pz),
+                          x0, (uint32_t)np, Sy, Sz, sx4, sy4, negc);
+    }
+}
+
+// Scan one slab: per-thread best (count, lowest position).  Positions are word
+// index * 2 + half, which orders bins exactly as their linear index does.
+template <int CW>
+__device__ void scan_slab(const uint32_t *hist, int words, uint32_t pos0, uint32_t &bc,
+                          uint32_t &bp)
+{
+    for (int w = threadIdx.x; w < words; w += kBlock) {
+        const uint32_t v = hist[w];
+        if (CW == 16) {
+            const uint32_t lo = v & 0xFFFFu, hi = v >> 16;
+            if (lo > bc) { bc = lo; bp = pos0 + 2u * w; }
+            if (hi > bc) { bc = hi; bp = pos0 + 2u * w + 1u; }
+        } else {
+            if (v > bc) { bc = v; bp = pos0 + (uint32_t)w; }
+        }
+    }
+}
+
+__device__ __forceinline__ float rho(int metric, float d, float dmetric, float d2, float eps,
+                                     float tau)
+{
+    switch (metric) {
+    case DSES_TRUNC_L2: return fminf(d, tau);
+    case DSES_TLS: return fminf(d2, tau * tau);
+    case DSES_INLIERS: return d < eps ? 0.0f : 1.0f;
+    default: return fminf(dmetric, tau);          // DSES_TRUNC_L1
+    }
+}
+
+// Nearest-neighbour terms for one query point.
+struct NN {
+    float d2;   // squared Euclidean distance to the nearest reference point
+    float l1;   // L1 distance to the L1-nearest reference point (TRUNC_L1 only)
+};
+
+__device__ __forceinline__ float d2_of(float qx, float qy, float qz, float yx, float yy, float yz)
+{
+    const float dx = qx - yx, dy = qy - yy, dz = qz - yz;
+    return fmaf(dz, dz, fmaf(dy, dy, __fmul_rn(dx, dx)));
+}
+
+__device__ __forceinline__ void nn_brute(const float *yt, int m, int j0, int j1, float qx,
+                                         float qy, float qz, bool want_l1, NN &nn)
+{
+    const kfloat yx = kc(yt), yy = kc(yt + m), yz = kc(yt + 2 * m);
+    float best = INFINITY, bl1 = INFINITY;
+    int j = j0;
+    if (!want_l1) {
+        float b2 = INFINITY, b3 = INFINITY, b4 = INFINITY;
+        for (; j + 4 <= j1; j += 4) {
+            best = fminf(best, d2_of(qx, qy, qz, yx[j], yy[j], yz[j]));
+            b2 = fminf(b2, d2_of(qx, qy, qz, yx[j + 1], yy[j + 1], yz[j + 1]));
+            b3 = fminf(b3, d2_of(qx, qy, qz, yx[j + 2], yy[j + 2], yz[j + 2]));
+            b4 = fminf(b4, d2_of(qx, qy, qz, yx[j + 3], yy[j + 3], yz[j + 3]));
+        }
+        best = fminf(fminf(best, b2), fminf(b3, b4));
+        for (; j < j1; ++j) best = fminf(best, d2_of(qx, qy, qz, yx[j], yy[j], yz[j]));
+    } else {
+        for (; j < j1; ++j) {
+            const float dx = qx - yx[j], dy = qy - yy[j], dz = qz - yz[j];
+            best = fminf(best, fmaf(dz, dz, fmaf(dy, dy, __fmul_rn(dx, dx))));
+            bl1 = fminf(bl1, fabsf(dx) + fabsf(dy) + fabsf(dz));
+        }
+    }
+    nn.d2 = best;
+    nn.l1 = bl1;
+}
+
+// Exact truncated NN through the cell grid: every reference point within the
+// cell pitch (>= r) of q lies in the 3x3x3 cells around q's cell.  Beyond r the
+// robust terms saturate, so the result equals brute force.
+__device__ __forceinline__ void nn_grid(const CellGrid &cg, float qx, float qy, float qz,
+                                        bool want_l1, NN &nn)
+{
+    const int cx = cvt_flr(__fmul_rn(qx - cg.lo[0], cg.inv));
+    const int cy = cvt_flr(__fmul_rn(qy - cg.lo[1], cg.inv));
+    const int cz = cvt_flr(__fmul_rn(qz - cg.lo[2], cg.inv));
+    float best = INFINITY, bl1 = INFINITY;
+    const int m = cg.start[cg.dim[0] * cg.dim[1] * cg.dim[2]];
+    const float *yx = cg.pts, *yy = cg.pts + m, *yz = cg.pts + 2 * m;
+    const int zlo = max(cz - 1, 0), zhi = min(cz + 1, cg.dim[2] - 1);
+    if (zlo <= zhi) {
+        for (int ix = max(cx - 1, 0); ix <= min(cx + 1, cg.dim[0] - 1); ++ix)
+            for (int iy = max(cy - 1, 0); iy <= min(cy + 1, cg.dim[1] - 1); ++iy) {
+                const int row = (ix * cg.dim[1] + iy) * cg.dim[2];
+                const int b = cg.start[row + zlo], e = cg.start[row + zhi + 1];
+                for (int j = b; j < e; ++j) {
+                    const float dx = qx - yx[j], dy = qy - yy[j], dz = qz - yz[j];
+                    best = fminf(best, fmaf(dz, dz, fmaf(dy, dy, __fmul_rn(dx, dx))));
+                    if (want_l1) bl1 = fminf(bl1, fabsf(dx) + fabsf(dy) + fabsf(dz));
+                }
+            }
+    }
+    nn.d2 = best;
+    nn.l1 = bl1;
+}
+
+// Distance-field lookup: idx_a = floor((q_a - lo_a) * inv_a); r outside the grid.
+__device__ __forceinline__ float df_lookup(const Field &f, float qx, float qy, float qz)
+{
+    const int ix = cvt_flr(__fmul_rn(qx - f.lo[0], f.inv[0]));
+    const int iy = cvt_flr(__fmul_rn(qy - f.lo[1], f.inv[1]));
+    const int iz = cvt_flr(__fmul_rn(qz - f.lo[2], f.inv[2]));
+    const uint32_t R = (uint32_t)f.res;
+    if ((uint32_t)ix < R && (uint32_t)iy < R && (uint32_t)iz < R)
+        return f.val[((size_t)ix * R + iy) * R + iz];
+    return f.r;
+}
+
+template <int CW, int SCORER>
+__global__ void __launch_bounds__(kBlock) k_sweep(SweepArgs a)
+{
+    __shared__ __align__(16) uint32_t lds[kLdsWords];
+    const Geom &g = a.g;
+    uint32_t *hist = lds;
+    uint32_t *scr = lds + kHistWordsMax;          // kScratchWords words
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t Sy = g.size[1];
+    const uint32_t RW = (uint32_t)g.row_words;
+    const int k = blockIdx.x;
+    float R[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) R[e] = kc(a.rot)[9 * k + e];
+
+    // ---------------- vote + mode over the slabs ----------------
+    uint32_t best_c = 0, best_p = 0xFFFFFFFFu;
+    for (int slab = 0; slab < g.nslabs; ++slab) {
+        const int x0 = slab * g.pps;
+        const int np = min(g.pps, g.size[0] - x0);
+        const int words = np * (int)Sy * (int)RW;
+        const int words4 = (words + 3) >> 2;
+        uint4 *h4 = reinterpret_cast<uint4 *>(hist);
+        for (int w = tid; w < words4; w += kBlock) h4[w] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        vote_slab<CW>(a, R, x0, np, hist);
+        __syncthreads();
+        uint32_t bc = 0, bp = 0xFFFFFFFFu;
+        const uint32_t pos0 = (uint32_t)x0 * Sy * RW * (CW == 16 ? 2u : 1u);
+        scan_slab<CW>(hist, words, pos0, bc, bp);
+        for (int off = 32; off > 0; off >>= 1)
+            better(bc, bp, __shfl_xor(bc, off, 64), __shfl_xor(bp, off, 64));
+        if (lane == 0) { scr[8 + 2 * wave] = bc; scr[9 + 2 * wave] = bp; }
+        __syncthreads();
+        if (wave == 0) {
+            uint32_t c = lane < kWaves ? scr[8 + 2 * lane] : 0u;
+            uint32_t l = lane < kWaves ? scr[9 + 2 * lane] : 0xFFFFFFFFu;
+            for (int off = 32; off > 0; off >>= 1)
+                better(c, l, __shfl_xor(c, off, 64), __shfl_xor(l, off, 64));
+            if (lane == 0) { scr[2] = c; scr[3] = l; }
+        }
+        __syncthreads();
+        const uint32_t sc = scr[2], sp = scr[3];
+        if (sc > best_c) { best_c = sc; best_p = sp; }
+        __syncthreads();                      // scr / hist reused by the next slab
+    }
+
+    dses_record rec;
+    if (best_c == 0) {
+        if (tid == 0) {
+            rec.bin[0] = rec.bin[1] = rec.bin[2] = 0;
+            rec.votes = 0;
+            rec.inliers = 0;
+            rec.error = INFINITY;
+            a.rec[k] = rec;
+        }
+        return;
+    }
+    // position -> box-relative bin
+    const uint32_t w = CW == 16 ? best_p >> 1 : best_p;
+    const uint32_t row = w / RW;
+    const int cz = (int)((w - row * RW) * (CW == 16 ? 2u : 1u) + (CW == 16 ? (best_p & 1u) : 0u));
+    const int cy = (int)(row % Sy), cx = (int)(row / Sy);
+    const int bx = cx + g.klo[0], by = cy + g.klo[1], bz = cz + g.klo[2];
+    const float tx = __fmul_rn((float)bx, g.delta);
+    const float ty = __fmul_rn((float)by, g.delta);
+    const float tz = __fmul_rn((float)bz, g.delta);
+
+    // ---------------- score the candidate {R, t*} ----------------
+    const bool want_l1 = g.metric == DSES_TRUNC_L1;
+    float err = 0.0f;
+    int inl = 0;
+    float *part = reinterpret_cast<float *>(hist);
+    for (int c0 = 0; c0 < g.n; c0 += kBlock) {
+        const ChunkLayout L = (SCORER == DSES_SCORER_BRUTE)
+                                  ? chunk_layout(c0, g.n, wave, lane)
+                                  : ChunkLayout{kWaves, 1, 0, c0 + tid, true};
+        NN nn;
+        nn.d2 = INFINITY;
+        nn.l1 = INFINITY;
+        float D = 0.0f;
+        const bool valid = L.active && L.i < g.n;
+        if (SCORER == DSES_SCORER_BRUTE) {
+            if (L.active) {
+                float qx = 1.0e7f, qy = 1.0e7f, qz = 1.0e7f;
+                if (valid) {
+                    float px, py, pz;
+                    rotate(R, a.src[3 * L.i], a.src[3 * L.i + 1], a.src[3 * L.i + 2], px, py, pz);
+                    qx = px + tx;
+                    qy = py + ty;
+                    qz = pz + tz;
+                }
+                const int j0 = uni((int)((int64_t)g.m * L.part / L.G));
+                const int j1 = uni((int)((int64_t)g.m * (L.part + 1) / L.G));
+                nn_brute(a.yt, g.m, j0, j1, qx, qy, qz, want_l1, nn);
+            }
+        } else if (valid) {
+            float px, py, pz;
+            rotate(R, a.src[3 * L.i], a.src[3 * L.i + 1], a.src[3 * L.i + 2], px, py, pz);
+            const float qx = px + tx, qy = py + ty, qz = pz + tz;
+            if (SCORER == DSES_SCORER_GRID)
+                nn_grid(a.grid, qx, qy, qz, want_l1, nn);
+            else
+                D = df_lookup(a.field, qx, qy, qz);
+        }
+        if (SCORER == DSES_SCORER_BRUTE && L.G > 1) {
+            // combine the reference partitions of each source point
+            const int slot = L.part * L.sw * 64 + (wave % L.sw) * 64 + lane;
+            if (L.active) {
+                part[slot] = nn.d2;
+                if (want_l1) part[kBlock + slot] = nn.l1;
+            }
+            __syncthreads();
+            if (L.active && L.part == 0) {
+                for (int p = 1; p < L.G; ++p) {
+                    const int o = p * L.sw * 64 + (wave % L.sw) * 64 + lane;
+                    nn.d2 = fminf(nn.d2, part[o]);
+                    if (want_l1) nn.l1 = fminf(nn.l1, part[kBlock + o]);
+                }
+            }
+            __syncthreads();
+        }
+        if (valid && L.part == 0) {
+            if (SCORER == DSES_SCORER_DF) {
+                err += rho(g.metric, D, D, D * D, g.eps, g.tau);
+                inl += D < g.eps ? 1 : 0;
+            } else {
+                const float d = sqrtf(nn.d2);
+                const float dm = want_l1 ? nn.l1 : d;
+                err += rho(g.metric, d, dm, nn.d2, g.eps, g.tau);
+                inl += d < g.eps ? 1 : 0;
+            }
+        }
+    }
+    // fixed-order workgroup reduction
+    err = wave_sum(err);
+    inl = wave_isum(inl);
+    float *fscr = reinterpret_cast<float *>(scr);
+    if (lane == 0) { fscr[64 + wave] = err; scr[96 + wave] = (uint32_t)inl; }
+    __syncthreads();
+    if (tid == 0) {
+        float e = 0.0f;
+        int c = 0;
+        for (int q = 0; q < kWaves; ++q) { e += fscr[64 + q]; c += (int)scr[96 + q]; }
+        rec.bin[0] = bx;
+        rec.bin[1] = by;
+        rec.bin[2] = bz;
+        rec.votes = best_c;
+        rec.inliers = c;
+        rec.error = e;
+        a.rec[k] = rec;
+    }
+}
+
+template <int CW, int SC>
+static hipError_t launch_one(const SweepArgs &a, hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_sweep<CW, SC>), dim3(a.k), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const SweepArgs &a, int scorer, hipStream_t stream)
+{
+    if (a.k <= 0) return hipSuccess;
+    if (a.g.counter_bits == 16) {
+        switch (scorer) {
+        case DSES_SCORER_BRUTE: return launch_one<16, DSES_SCORER_BRUTE>(a, stream);
+        case DSES_SCORER_GRID: return launch_one<16, DSES_SCORER_GRID>(a, stream);
+        default: return launch_one<16, DSES_SCORER_DF>(a, stream);
+        }
+    }
+    switch (scorer) {
+    case DSES_SCORER_BRUTE: return launch_one<32, DSES_SCORER_BRUTE>(a, stream);
+    case DSES_SCORER_GRID: return launch_one<32, DSES_SCORER_GRID>(a, stream);
+    default: return launch_one<32, DSES_SCORER_DF>(a, stream);
+    }
+}
+
+// --------------------------------------------------------------------------
+// selection: argmin over records of (error, -inliers, index)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ bool sel_better(float e, int i, int k, float oe, int oi, int ok)
+{
+    // true if (oe, oi, ok) beats (e, i, k); k < 0 means "none"
+    if (ok < 0) return false;
+    if (k < 0) return true;
+    if (oe < e) return true;
+    if (oe > e) return false;
+    if (oi > i) return true;
+    if (oi < i) return false;
+    return ok < k;
+}
+
+__global__ void __launch_bounds__(1024) k_select(const dses_record *rec, int32_t K,
+                                                 const float *rot, float delta, DevResult *res,
+                                                 const uint32_t *status)
+{
+    __shared__ float se[16];
+    __shared__ int si[16], sk[16], sv[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float be = INFINITY;
+    int bi = 0, bk = -1, nvalid = 0;
+    for (int k = tid; k < K; k += blockDim.x) {
+        const dses_record r = rec[k];
+        if (r.votes == 0) continue;
+        ++nvalid;
+        if (sel_better(be, bi, bk, r.error, r.inliers, k)) { be = r.error; bi = r.inliers; bk = k; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const float oe = __shfl_xor(be, off, 64);
+        const int oi = __shfl_xor(bi, off, 64), ok = __shfl_xor(bk, off, 64);
+        if (sel_better(be, bi, bk, oe, oi, ok)) { be = oe; bi = oi; bk = ok; }
+        nvalid += __shfl_xor(nvalid, off, 64);
+    }
+    if (lane == 0) { se[wave] = be; si[wave] = bi; sk[wave] = bk; sv[wave] = nvalid; }
+    __syncthreads();
+    if (tid == 0) {
+        float e = INFINITY;
+        int i = 0, k = -1, nv = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            nv += sv[w];
+            if (sel_better(e, i, k, se[w], si[w], sk[w])) { e = se[w]; i = si[w]; k = sk[w]; }
+        }
+        res->rot_index = k;
+        res->n_valid = nv;
+        res->bad_input = status ? status[0] : 0u;
+        if (k >= 0) {
+            const dses_record r = rec[k];
+            res->votes = r.votes;
+            res->inliers = r.inliers;
+            res->error = r.error;
+            for (int a2 = 0; a2 < 3; ++a2) res->t[a2] = __fmul_rn((float)r.bin[a2], delta);
+            for (int e2 = 0; e2 < 9; ++e2) res->R[e2] = rot[9 * (size_t)k + e2];
+        }
+    }
+}
+
+hipError_t launch_select(const dses_record *rec, int32_t k, const float *rot, float delta,
+                         DevResult *res, const uint32_t *status, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, stream, rec, k, rot, delta, res,
+                       status);
+    return hipGetLastError();
+}
+
+}  // namespace dses

@@ -1,0 +1,260 @@
+// Resident reference clouds (with optional distance field) and rotation lists.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "host.h"
+
+struct dses_target {
+    dses::TargetRes res;
+};
+
+struct dses_rotset {
+    dses::RotRes res;
+};
+
+namespace dses {
+
+static dses_status copy_to_host(const float *p, size_t count, bool dev, std::vector<float> *out)
+{
+    out->resize(count);
+    if (dev) {
+        DSES_HIP(hipMemcpy(out->data(), p, count * sizeof(float), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(out->data(), p, count * sizeof(float));
+    }
+    return DSES_OK;
+}
+
+}  // namespace dses
+
+using namespace dses;
+
+extern "C" {
+
+dses_status dses_target_create(const float *tgt, int64_t m, const dses_target_opts *opt,
+                               dses_target **out)
+{
+    set_error("");
+    if (!tgt || !out || m <= 0 || m >= ((int64_t)1 << 31)) {
+        set_error("invalid reference cloud");
+        return DSES_E_INVAL;
+    }
+    dses_target_opts o{};
+    if (opt) o = *opt;
+    if (!(o.df_trunc >= 0.0f) || !std::isfinite(o.df_trunc) || o.df_res < 0 || o.df_res > 1024) {
+        set_error("invalid distance-field options");
+        return DSES_E_INVAL;
+    }
+    Context *c = ctx();
+    if (!c) return DSES_E_DEVICE;
+    auto *t = new dses_target();
+    TargetRes &T = t->res;
+    T.m = (int32_t)m;
+    dses_status st = copy_to_host(tgt, 3 * (size_t)m, (o.flags & DSES_DEVICE_PTRS) != 0,
+                                  &T.host_aos);
+    if (st != DSES_OK) { delete t; return st; }
+    for (float v : T.host_aos)
+        if (!std::isfinite(v) || std::fabs(v) > 1e4f) {
+            delete t;
+            set_error("reference coordinate is non-finite or larger than 1e4");
+            return DSES_E_INVAL;
+        }
+    auto fail = [&](dses_status s) {
+        dses_target_destroy(t);
+        return s;
+    };
+    if (hipMalloc(&T.aos, 3 * (size_t)m * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("device allocation failed");
+        return fail(DSES_E_NOMEM);
+    }
+    if (hipMemcpy(T.aos, T.host_aos.data(), 3 * (size_t)m * sizeof(float),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("upload of the reference failed");
+        return fail(DSES_E_DEVICE);
+    }
+    if (o.df_trunc > 0.0f) {
+        const int32_t res = o.df_res ? o.df_res : 128;
+        const float r = o.df_trunc;
+        // field box: reference AABB padded by r (float arithmetic, see dses.h)
+        for (int a = 0; a < 3; ++a) {
+            float mn = T.host_aos[a], mx = T.host_aos[a];
+            for (int64_t j = 1; j < m; ++j) {
+                const float v = T.host_aos[3 * j + a];
+                if (v < mn) mn = v;
+                if (v > mx) mx = v;
+            }
+            const float l = mn - r, u = mx + r;
+            const float ext = u - l;
+            T.df_lo[a] = l;
+            T.df_h[a] = ext / (float)res;
+            T.df_inv[a] = 1.0f / T.df_h[a];
+        }
+        HostGrid hg;
+        if ((st = build_grid(T.host_aos.data(), T.m, r, &hg)) != DSES_OK) return fail(st);
+        float *gp = nullptr;
+        int32_t *gs = nullptr;
+        const size_t nvox = (size_t)res * res * res;
+        if (hipMalloc(&gp, hg.pts.size() * sizeof(float)) != hipSuccess ||
+            hipMalloc(&gs, hg.start.size() * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&T.df, nvox * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            if (gp) (void)hipFree(gp);
+            if (gs) (void)hipFree(gs);
+            set_error("device allocation for the distance field failed");
+            return fail(DSES_E_NOMEM);
+        }
+        hipError_t e = hipMemcpy(gp, hg.pts.data(), hg.pts.size() * sizeof(float),
+                                 hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(gs, hg.start.data(), hg.start.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_df_build(gp, gs, hg, res, T.df_lo, T.df_h, r, T.df, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(gp);
+        (void)hipFree(gs);
+        if (e != hipSuccess) {
+            set_error(std::string("distance field build failed: ") + hipGetErrorString(e));
+            return fail(DSES_E_DEVICE);
+        }
+        T.df_res = res;
+        T.df_r = r;
+    }
+    *out = t;
+    return DSES_OK;
+}
+
+dses_status dses_target_destroy(dses_target *t)
+{
+    if (!t) return DSES_E_INVAL;
+    TargetRes &T = t->res;
+    if (T.aos) (void)hipFree(T.aos);
+    if (T.yt) (void)hipFree(T.yt);
+    if (T.df) (void)hipFree(T.df);
+    if (T.grid_pts) (void)hipFree(T.grid_pts);
+    if (T.grid_start) (void)hipFree(T.grid_start);
+    delete t;
+    return DSES_OK;
+}
+
+dses_status dses_target_field(const dses_target *t, float *field, float *lo, float *h)
+{
+    if (!t) return DSES_E_INVAL;
+    const TargetRes &T = t->res;
+    if (!T.df) {
+        set_error("target has no distance field");
+        return DSES_E_STATE;
+    }
+    if (field) {
+        const size_t nvox = (size_t)T.df_res * T.df_res * T.df_res;
+        DSES_HIP(hipMemcpy(field, T.df, nvox * sizeof(float), hipMemcpyDeviceToHost));
+    }
+    if (lo) std::memcpy(lo, T.df_lo, sizeof(T.df_lo));
+    if (h) std::memcpy(h, T.df_h, sizeof(T.df_h));
+    return DSES_OK;
+}
+
+dses_status dses_rotations_create(const float *rotations, int64_t k, uint32_t flags,
+                                  dses_rotset **out)
+{
+    set_error("");
+    if (!rotations || !out || k <= 0 || k > INT32_MAX) {
+        set_error("invalid rotation list");
+        return DSES_E_INVAL;
+    }
+    Context *c = ctx();
+    if (!c) return DSES_E_DEVICE;
+    std::vector<float> host;
+    dses_status st = copy_to_host(rotations, 9 * (size_t)k, (flags & DSES_DEVICE_PTRS) != 0, &host);
+    if (st != DSES_OK) return st;
+    for (int64_t q = 0; q < k; ++q) {
+        const float *R = host.data() + 9 * q;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                float d = R[i] * R[j] + R[3 + i] * R[3 + j] + R[6 + i] * R[6 + j];
+                d -= (i == j) ? 1.0f : 0.0f;
+                if (!(std::fabs(d) <= 1e-4f)) {
+                    set_error("rotation " + std::to_string(q) + " is not orthonormal");
+                    return DSES_E_INVAL;
+                }
+            }
+    }
+    auto *r = new dses_rotset();
+    r->res.k = k;
+    if (hipMalloc(&r->res.rot, 9 * (size_t)k * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete r;
+        set_error("device allocation failed");
+        return DSES_E_NOMEM;
+    }
+    if (hipMemcpy(r->res.rot, host.data(), 9 * (size_t)k * sizeof(float),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(r->res.rot);
+        delete r;
+        set_error("upload of the rotation list failed");
+        return DSES_E_DEVICE;
+    }
+    *out = r;
+    return DSES_OK;
+}
+
+dses_status dses_rotations_destroy(dses_rotset *r)
+{
+    if (!r) return DSES_E_INVAL;
+    if (r->res.rot) (void)hipFree(r->res.rot);
+    delete r;
+    return DSES_OK;
+}
+
+dses_status dses_register_resident(const dses_target *tgt, const dses_rotset *rots,
+                                   const float *src, int64_t n, float eps, dses_metric metric,
+                                   const dses_options *opt, dses_result *out)
+{
+    set_error("");
+    if (!tgt || !rots || !src || !out || n <= 0 || n * (int64_t)tgt->res.m >= ((int64_t)1 << 31)) {
+        set_error("invalid arguments");
+        return DSES_E_INVAL;
+    }
+    dses_options o{};
+    if (opt) o = *opt;
+    Params p;
+    dses_status st = resolve_params(eps, metric, o.delta_t, o.tau, o.t_min, o.t_max, o.scorer, &p);
+    if (st != DSES_OK) return st;
+    const bool dev = (o.flags & DSES_DEVICE_PTRS) != 0;
+    Context *c = ctx();
+    if (!c) return DSES_E_DEVICE;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timing_enabled = (o.flags & DSES_TIMING) != 0;
+    hipStream_t stream = o.stream ? static_cast<hipStream_t>(o.stream) : c->stream;
+    Job job;
+    job.n = (int32_t)n;
+    job.m = tgt->res.m;
+    job.k = (int32_t)rots->res.k;
+    job.p = p;
+    job.tgt = tgt->res.aos;
+    job.rot = rots->res.rot;
+    job.target = &tgt->res;
+    job.host_tgt = tgt->res.host_aos.data();
+    if (dev) {
+        job.src = src;
+    } else {
+        const float lim = coord_limit(p);
+        for (int64_t e = 0; e < 3 * n; ++e)
+            if (!(std::fabs(src[e]) <= lim)) {
+                set_error("source coordinate is non-finite or too large for the lattice");
+                return DSES_E_INVAL;
+            }
+        if ((st = c->in_src.ensure(3 * n * sizeof(float))) != DSES_OK) return st;
+        DSES_HIP(hipMemcpyAsync(c->in_src.ptr, src, 3 * n * sizeof(float), hipMemcpyHostToDevice,
+                                stream));
+        job.src = static_cast<float *>(c->in_src.ptr);
+    }
+    return run_plain(c, job, stream, dev, out, o.records, dev);
+}
+
+}  // extern "C"

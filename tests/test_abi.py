@@ -1,0 +1,80 @@
+"""The C ABI library builds, loads, and exports what include/dses.h declares (CPU only)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dses.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dses_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    from paper_2502_00115_amd import dses
+    if not os.path.exists(dses.LIB_PATH):
+        from paper_2502_00115_amd import build_lib
+        build_lib.build()
+    return dses.LIB_PATH
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ["dses_register", "dses_register_batch", "dses_target_create",
+                 "dses_rotations_create", "dses_server_create", "dses_server_submit",
+                 "dses_server_wait", "dses_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(libpath):
+    out = subprocess.check_output(["nm", "-D", "--defined-only", libpath]).decode()
+    exported = set(re.findall(r"\bT (dses_[a-z_]+)\b", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+
+
+def test_binding_lists_match_header():
+    from paper_2502_00115_amd import dses
+    assert sorted(dses.EXPORTED) == _declared()
+
+
+def test_library_is_gfx950_code_object(libpath):
+    out = subprocess.check_output(["strings", libpath]).decode(errors="replace")
+    assert "gfx950" in out
+
+
+def test_argument_errors_need_no_gpu(libpath):
+    import numpy as np
+    from paper_2502_00115_amd import dses
+    cases = [
+        (np.zeros((0, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05, {}),
+        (np.zeros((3, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.0, {}),
+        (np.zeros((3, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), float("nan"), {}),
+        (np.zeros((3, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05,
+         {"t_min": 1.0, "t_max": -1.0}),
+        (np.zeros((3, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05,
+         {"scorer": "df"}),
+    ]
+    for s, t, r, eps, kw in cases:
+        with pytest.raises(dses.DsesError) as e:
+            dses.register(s, t, r, eps, **kw)
+        assert e.value.status == dses.DSES_E_INVAL, (kw, e.value)
+    with pytest.raises(ValueError):
+        dses.register(np.zeros((4, 2)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05)
+
+
+def test_no_device_is_a_loud_error(libpath):
+    import numpy as np
+    import torch
+    from paper_2502_00115_amd import dses
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(dses.DsesError) as e:
+        dses.register(np.zeros((3, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05)
+    assert e.value.status == dses.DSES_E_DEVICE

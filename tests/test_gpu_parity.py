@@ -1,0 +1,184 @@
+"""Parity of the HIP path (called through the C ABI) with the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_00115_amd import synth
+from parity import check_selection, compare_records
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2502_00115_amd import dses  # noqa: E402
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_both(p, metric="trunc_l2", scorer="auto", device=True, **kw):
+    if device:
+        got = dses.register(_dev(p.src), _dev(p.tgt), _dev(p.rotations), p.eps, metric,
+                            scorer=scorer, records=True, **kw)
+    else:
+        got = dses.register(p.src, p.tgt, p.rotations, p.eps, metric, scorer=scorer,
+                            records=True, **kw)
+    ref = oracle.records(p.src, p.tgt, p.rotations, p.eps, metric=metric,
+                         delta=kw.get("delta_t"), tau=kw.get("tau"), t_min=kw.get("t_min"),
+                         t_max=kw.get("t_max"))
+    return got, ref
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_c1_records_and_selection(seed):
+    p = synth.make_c1(seed)
+    got, ref = run_both(p)
+    rep = compare_records(got.records, ref, len(p.src), label=p.name)
+    check_selection(got, ref, len(p.src), p.eps, label=p.name)
+    print(p.name, rep)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_exact_recovery(seed):
+    p = synth.make_c1_exact(seed)
+    got = dses.register(_dev(p.src), _dev(p.tgt), _dev(p.rotations), p.eps)
+    assert got.rot_index == p.true_index
+    np.testing.assert_allclose(got.t, p.t_true, atol=1e-6)
+    assert got.inliers == len(p.src)
+    assert got.error <= len(p.src) * 1e-6
+
+
+@pytest.mark.parametrize("metric", ["trunc_l2", "tls", "inliers", "trunc_l1"])
+@pytest.mark.parametrize("scorer", ["brute", "grid"])
+def test_metrics_and_scorers(metric, scorer):
+    p = synth.make_c1(21)
+    got, ref = run_both(p, metric=metric, scorer=scorer, tau=0.04)
+    compare_records(got.records, ref, len(p.src), metric=metric, label=f"{metric}/{scorer}")
+    check_selection(got, ref, len(p.src), p.eps, metric=metric)
+
+
+def test_brute_and_grid_scorers_are_bitwise_equal():
+    p = synth.make_c1(3)
+    a = dses.register(p.src, p.tgt, p.rotations, p.eps, scorer="brute", records=True)
+    b = dses.register(p.src, p.tgt, p.rotations, p.eps, scorer="grid", records=True)
+    assert a.records.tobytes() == b.records.tobytes()
+
+
+def test_host_and_device_pointers_agree():
+    p = synth.make_c1(4)
+    a = dses.register(p.src, p.tgt, p.rotations, p.eps, records=True)
+    b = dses.register(_dev(p.src), _dev(p.tgt), _dev(p.rotations), p.eps, records=True)
+    assert a.records.tobytes() == b.records.tobytes()
+    assert a.rot_index == b.rot_index and a.error == b.error
+
+
+def test_deterministic_repeat():
+    p = synth.make_c1(5)
+    a = dses.register(p.src, p.tgt, p.rotations, p.eps, records=True)
+    b = dses.register(p.src, p.tgt, p.rotations, p.eps, records=True)
+    assert a.records.tobytes() == b.records.tobytes()
+
+
+def test_runs_on_a_side_stream():
+    p = synth.make_c1(6)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a = dses.register(_dev(p.src), _dev(p.tgt), _dev(p.rotations), p.eps, records=True)
+    b = dses.register(p.src, p.tgt, p.rotations, p.eps, records=True)
+    assert a.records.tobytes() == b.records.tobytes()
+
+
+# ---------------------------------------------------------------------------
+# ragged sizes, boxes and counter widths
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,m,k", [(1, 1, 1), (1, 300, 7), (65, 1, 5), (65, 1023, 33),
+                                   (130, 77, 9), (1025, 40, 3), (2100, 260, 4)])
+def test_ragged_sizes(n, m, k):
+    rng = np.random.default_rng(n * 7 + m)
+    tgt = rng.uniform(-0.8, 0.8, (m, 3)).astype(np.float32)
+    src = (tgt[rng.integers(0, m, n)] + rng.normal(0, 0.01, (n, 3))).astype(np.float32)
+    rots = synth.random_rotations(rng, k).reshape(-1, 9).astype(np.float32)
+    rots[0] = np.eye(3, dtype=np.float32).reshape(9)
+    p = synth.Problem(src, tgt, rots, 0.05, np.eye(3), np.zeros(3))
+    got, ref = run_both(p)
+    compare_records(got.records, ref, n, label=f"{n}x{m}x{k}")
+    check_selection(got, ref, n, p.eps)
+
+
+@pytest.mark.parametrize("delta,box", [(0.02, 1.0), (0.011, 0.6), (0.05, 2.5), (0.1, 0.05)])
+def test_multi_slab_and_small_boxes(delta, box):
+    """Boxes from a single bin up to 227^3 bins (many LDS slabs)."""
+    p = synth.make_c1(7)
+    which = slice(0, 96)
+    p.rotations = p.rotations[which].copy()
+    got, ref = run_both(p, delta_t=delta, t_min=-box, t_max=box)
+    compare_records(got.records, ref, len(p.src), label=f"delta {delta} box {box}")
+
+
+def test_asymmetric_box():
+    p = synth.make_c1(8)
+    got, ref = run_both(p, t_min=[-0.3, -1.0, 0.0], t_max=[0.9, 0.2, 0.75])
+    compare_records(got.records, ref, len(p.src))
+
+
+def test_32bit_counters_when_16bit_could_overflow():
+    """300 source points on one spot and 400 reference points on another: one bin gets
+    300*400 = 120,000 > 2^16 votes, so the library must use 32-bit counters."""
+    rng = np.random.default_rng(9)
+    src = np.tile(np.float32([[0.1, 0.2, 0.3]]), (300, 1))
+    tgt = np.vstack([np.tile(np.float32([[0.4, -0.1, 0.2]]), (400, 1)),
+                     rng.uniform(-1, 1, (50, 3)).astype(np.float32)])
+    rots = np.vstack([np.eye(3).reshape(1, 9), synth.random_rotations(rng, 3).reshape(-1, 9)])
+    p = synth.Problem(src, tgt, rots.astype(np.float32), 0.05, np.eye(3), np.zeros(3))
+    got, ref = run_both(p)
+    assert ref["votes"][0] == 120000
+    compare_records(got.records, ref, len(src))
+
+
+def test_no_vote_in_box_is_nocandidate():
+    src = np.zeros((4, 3), np.float32)
+    tgt = np.full((5, 3), 0.9, np.float32)
+    with pytest.raises(dses.DsesError) as e:
+        dses.register(src, tgt, np.eye(3, dtype=np.float32).reshape(1, 9), 0.05,
+                      t_min=-0.2, t_max=0.2)
+    assert e.value.status == dses.DSES_E_NOCANDIDATE
+
+
+@pytest.mark.parametrize("device", [False, True])
+def test_invalid_inputs_are_rejected(device):
+    p = synth.make_c1(1)
+    bad = p.src.copy()
+    bad[3, 1] = np.nan
+    rots = p.rotations.copy()
+    rots[2, 0] = 2.0
+    f = _dev if device else (lambda a: a)
+    for s, t, r in [(bad, p.tgt, p.rotations), (p.src, p.tgt, rots)]:
+        with pytest.raises(dses.DsesError) as e:
+            dses.register(f(s), f(t), f(r), p.eps)
+        assert e.value.status == dses.DSES_E_INVAL
+    with pytest.raises(dses.DsesError):
+        dses.register(p.src, p.tgt, p.rotations, -1.0)
+
+
+# ---------------------------------------------------------------------------
+# full-size object-scale registration (36,864-rotation grid)
+# ---------------------------------------------------------------------------
+def test_c2_sampled_records_and_selection():
+    p = synth.make_c2(0)
+    got = dses.register(_dev(p.src), _dev(p.tgt), _dev(p.rotations), p.eps, records=True)
+    rng = np.random.default_rng(0)
+    recs = got.records
+    top = np.argsort(np.where(recs["votes"] > 0, recs["error"], np.inf))[:16]
+    which = np.unique(np.concatenate([rng.choice(len(p.rotations), 384, replace=False), top]))
+    ref = oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which)
+    compare_records(recs[which], ref, len(p.src), label="c2 sample")
+    # the oracle's best among the GPU's 16 best candidates is the GPU's choice
+    pos = np.isin(which, top)
+    check_selection(got, ref[pos], len(p.src), p.eps, which=which[pos], label="c2 top16")
+    # accuracy context: the chosen rotation is near the truth
+    ang = np.degrees(np.arccos(np.clip((np.trace(got.R.astype(float).T @ p.R_true) - 1) / 2,
+                                       -1, 1)))
+    print(f"c2: rot {got.rot_index} angle to truth {ang:.2f} deg, t {got.t} vs {p.t_true}")

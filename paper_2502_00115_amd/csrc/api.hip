@@ -327,6 +327,40 @@ void add_stats(Context *c, double vote_ms, double score_ms, double select_ms, do
     c->stats.candidates += cands;
 }
 
+void sort_by_x(const float *tgt, int32_t m, std::vector<int32_t> *perm)
+{
+    perm->resize(m);
+    for (int32_t j = 0; j < m; ++j) (*perm)[j] = j;
+    std::stable_sort(perm->begin(), perm->end(),
+                     [tgt](int32_t a, int32_t b) { return tgt[3 * a] < tgt[3 * b]; });
+}
+
+bool build_x_table(const float *tgt, const std::vector<int32_t> &perm, float s, int32_t klo_x,
+                   std::vector<int32_t> *tab, int32_t *tab_lo)
+{
+    const size_t m = perm.size();
+    const float ofs = 0.5f - (float)klo_x;
+    std::vector<float> ysx(m);
+    for (size_t q = 0; q < m; ++q) {
+        const float y = tgt[3 * (size_t)perm[q]];
+        const float scaled = y * s;
+        ysx[q] = scaled + ofs;
+    }
+    const double lo = std::floor((double)ysx.front());
+    const double hi = std::floor((double)ysx.back());
+    if (!(hi - lo < (double)(1 << 20))) return false;
+    *tab_lo = (int32_t)lo;
+    const size_t n = (size_t)(hi - lo) + 2;
+    tab->resize(n);
+    size_t j = 0;
+    for (size_t q = 0; q < n; ++q) {
+        const float v = (float)(lo + (double)q);
+        while (j < m && ysx[j] < v) ++j;
+        (*tab)[q] = (int32_t)j;
+    }
+    return true;
+}
+
 static int effective_scorer(const Job &job)
 {
     int s = job.p.scorer;
@@ -381,6 +415,35 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     Geom g;
     if ((st = plan_geom(c, p, job.n, job.m, counter_bits, &g)) != DSES_OK) return st;
 
+    // Reference sorted by x, and a table over its scaled x coordinate
+    // (ys_x = y_x * s + (0.5 - k_lo_x), the same float arithmetic as the staging
+    // kernel) so each wave can restrict its vote loop to reachable points.
+    std::vector<int32_t> perm_local;
+    const std::vector<int32_t> *perm = nullptr;
+    if (job.target) {
+        auto *tm = const_cast<TargetRes *>(job.target);
+        std::lock_guard<std::mutex> lk(tm->grid_mu);
+        if (tm->perm_x.empty()) sort_by_x(ht, job.m, &tm->perm_x);
+        perm = &tm->perm_x;
+    } else {
+        sort_by_x(ht, job.m, &perm_local);
+        perm = &perm_local;
+    }
+    std::vector<int32_t> tab;
+    int32_t tab_lo = 0;
+    const bool sorted = job.n <= kSortMax &&
+                        build_x_table(ht, *perm, g.s, p.klo[0], &tab, &tab_lo);
+    const int grid = std::max(1, std::min(job.k, c->n_cu));
+    if ((st = c->perm.ensure(m * sizeof(int32_t))) != DSES_OK) return st;
+    DSES_HIP(hipMemcpyAsync(c->perm.ptr, perm->data(), m * sizeof(int32_t),
+                            hipMemcpyHostToDevice, stream));
+    if (sorted) {
+        if ((st = c->tab.ensure(tab.size() * sizeof(int32_t))) != DSES_OK) return st;
+        if ((st = c->scratch.ensure((size_t)grid * job.n * sizeof(float4))) != DSES_OK) return st;
+        DSES_HIP(hipMemcpyAsync(c->tab.ptr, tab.data(), tab.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, stream));
+    }
+
     if ((st = c->ys.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
     if ((st = c->yt.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
     if ((st = c->rec.ensure((size_t)job.k * sizeof(dses_record))) != DSES_OK) return st;
@@ -396,6 +459,11 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     a.rec = static_cast<dses_record *>(c->rec.ptr);
     a.k = job.k;
     a.g = g;
+    a.tab = sorted ? static_cast<int32_t *>(c->tab.ptr) : nullptr;
+    a.tab_lo = tab_lo;
+    a.tab_n = sorted ? (int32_t)tab.size() : 0;
+    a.scratch = sorted ? static_cast<float4 *>(c->scratch.ptr) : nullptr;
+    a.scratch_stride = job.n;
 
     if (scorer == DSES_SCORER_GRID) {
         const TargetRes *t = job.target;
@@ -464,10 +532,11 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
         CheckArgs ca{job.src, job.n, job.tgt, job.m, job.rot, job.k, coord_limit(p), bad};
         DSES_HIP(launch_check(ca, stream));
     }
-    DSES_HIP(launch_stage(job.tgt, job.m, g.s, p.klo, static_cast<float *>(c->ys.ptr),
-                          static_cast<float *>(c->yt.ptr), stream));
+    DSES_HIP(launch_stage(job.tgt, static_cast<int32_t *>(c->perm.ptr), job.m, g.s, p.klo,
+                          static_cast<float *>(c->ys.ptr), static_cast<float *>(c->yt.ptr),
+                          stream));
     rec_ev(1);
-    DSES_HIP(launch_sweep(a, scorer, stream));
+    DSES_HIP(launch_sweep(a, scorer, grid, stream));
     rec_ev(2);
     DSES_HIP(launch_select(a.rec, job.k, job.rot, p.delta, static_cast<DevResult *>(c->res.ptr),
                            bad, stream));

@@ -45,7 +45,7 @@ struct Context {
     hipStream_t stream = nullptr;
     std::mutex mu;                       // serialises the plain entry points
     // workspace of the plain path
-    DevBuf in_src, in_tgt, in_rot, ys, yt, rec, res, status, grid_pts, grid_start;
+    DevBuf in_src, in_tgt, in_rot, ys, yt, rec, res, status, grid_pts, grid_start, perm, tab, scratch;
     DevResult *host_res = nullptr;       // pinned
     // timing
     bool timing_enabled = false;
@@ -74,6 +74,12 @@ dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, i
 // Upper bound on any bin's vote count (decides 16- vs 32-bit LDS counters).
 int64_t counter_bound(const float *tgt_aos, int32_t m, int32_t n, const Params &p);
 
+// Reference order sorted by x, and the table tab[q] = first sorted index whose scaled
+// x coordinate is >= tab_lo + q (false if the coordinate range is too wide).
+void sort_by_x(const float *tgt_aos, int32_t m, std::vector<int32_t> *perm);
+bool build_x_table(const float *tgt_aos, const std::vector<int32_t> &perm, float s, int32_t klo_x,
+                   std::vector<int32_t> *tab, int32_t *tab_lo);
+
 // Exact cell grid for the GRID scorer, built on the host from reference points.
 struct HostGrid {
     std::vector<float> pts;      // SoA, cell order
@@ -95,8 +101,15 @@ struct TargetRes {
     int32_t df_res = 0;
     float df_r = 0.0f;
     float df_lo[3] = {0, 0, 0}, df_h[3] = {0, 0, 0}, df_inv[3] = {0, 0, 0};
-    // cached cell grid (for one r)
+    // cached x-sorted order and cell grid (for one r)
     std::mutex grid_mu;
+    std::vector<int32_t> perm_x;
+    // cached staged copy for one (delta, box) -- used by the serving loop
+    float st_delta = -1.0f;
+    int32_t st_klo[3] = {0, 0, 0};
+    float *st_ys = nullptr, *st_yt = nullptr;
+    int32_t *st_perm = nullptr, *st_tab = nullptr;
+    int32_t st_tab_lo = 0, st_tab_n = 0;
     float grid_r = -1.0f;
     float *grid_pts = nullptr;
     int32_t *grid_start = nullptr;
@@ -128,9 +141,23 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
 void add_stats(Context *c, double vote_ms, double score_ms, double select_ms, double stage_ms,
                int64_t launches, int64_t pairs_voted, int64_t pairs_scored, int64_t cands);
 
+// Stage a resident target for lattice pitch p.delta / box p.klo (cached; holds
+// tm->grid_mu while building; synchronous on `stream`).
+dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stream);
+// Build (or reuse) the resident target's cell grid for radius r; fills cg.
+dses_status ensure_target_grid(TargetRes *tm, float r, CellGrid *cg);
+
 // Distance field build (device), defined in field.hip.
 hipError_t launch_df_build(const float *pts_soa, const int32_t *start, const HostGrid &grid,
                            int32_t res, const float *lo, const float *h, float r, float *out,
                            hipStream_t stream);
 
 }  // namespace dses
+
+struct dses_target {
+    dses::TargetRes res;
+};
+
+struct dses_rotset {
+    dses::RotRes res;
+};

@@ -49,16 +49,56 @@ struct Field {
     float r;               // value outside the grid
 };
 
+constexpr int kSortBuckets = 1024;      // per-rotation source buckets (1 bin unit wide)
+constexpr int kSortMax = 16384;         // largest source cloud that is bucket-sorted
+
 struct SweepArgs {
     const float *src;      // n x 3 AoS
     const float *rot;      // K x 9
-    const float *ys;       // scaled + offset reference, SoA (3 * m)
-    const float *yt;       // reference, SoA (3 * m)
+    const float *ys;       // scaled + offset reference, SoA (3 * m), sorted by x
+    const float *yt;       // reference, SoA (3 * m), same order
+    const int32_t *tab;    // tab[q] = first j with ys_x[j] >= tab_lo + q, q < tab_n
+    int32_t tab_lo, tab_n;
+    float4 *scratch;       // per workgroup slot: n rotated scaled sources, bucket-sorted by x
+    int64_t scratch_stride;   // float4 entries per slot (>= n)
     Geom g;
     CellGrid grid;
     Field field;
     dses_record *rec;      // one record per rotation index
     int32_t k;             // rotations
+};
+
+// Batched registration.
+struct BatchItem {
+    int32_t inst;          // instance index
+    int32_t k0, k1;        // rotation range [k0, k1)
+    int32_t pad;
+};
+
+struct BatchArgs {
+    const SweepArgs *inst;     // per-instance sweep arguments (device)
+    const BatchItem *items;    // work list, most expensive first
+    const int32_t *header;     // header[0] = items, header[1] = instances
+    uint32_t *cursor;          // work-list cursor, cleared before each launch
+};
+
+struct StageDesc {
+    const float *tgt;
+    const int32_t *perm;
+    int32_t m;
+    float s;
+    int32_t klo[3];
+    float *ys, *yt;
+};
+
+struct DevResult;
+struct SelectDesc {
+    const dses_record *rec;
+    int32_t k;
+    float delta;
+    const float *rot;
+    DevResult *res;
+    const uint32_t *status;
 };
 
 // Result written on the device by the select kernel.
@@ -83,11 +123,15 @@ struct CheckArgs {
 
 // Launchers (defined in kernels.hip); all enqueue on `stream`.
 hipError_t launch_check(const CheckArgs &a, hipStream_t stream);
-hipError_t launch_stage(const float *tgt, int32_t m, float s, const int32_t *klo, float *ys,
-                        float *yt, hipStream_t stream);
-hipError_t launch_sweep(const SweepArgs &a, int scorer, hipStream_t stream);
+hipError_t launch_stage(const float *tgt, const int32_t *perm, int32_t m, float s,
+                        const int32_t *klo, float *ys, float *yt, hipStream_t stream);
+hipError_t launch_sweep(const SweepArgs &a, int scorer, int grid, hipStream_t stream);
 hipError_t launch_select(const dses_record *rec, int32_t k, const float *rot, float delta,
                          DevResult *res, const uint32_t *status, hipStream_t stream);
 hipError_t launch_clear(uint32_t *p, int32_t words, hipStream_t stream);
+hipError_t launch_sweep_batch(const BatchArgs &b, int scorer, int grid, hipStream_t stream);
+// which = 0: batched staging, 1: batched selection
+hipError_t launch_batch_aux(const StageDesc *stage, const SelectDesc *sel, const int32_t *header,
+                            int max_count, int which, hipStream_t stream);
 
 }  // namespace dses

@@ -123,25 +123,26 @@ hipError_t launch_check(const CheckArgs &a, hipStream_t stream)
 // staging: reference AoS -> SoA, plus the scaled/offset copy used for binning
 //   ys_a = (y_a * s) + (0.5 - k_lo_a)   (two float roundings, as in the header)
 // --------------------------------------------------------------------------
-__global__ void k_stage(const float *tgt, int32_t m, float s, int32_t klo0, int32_t klo1,
-                        int32_t klo2, float *ys, float *yt)
+__global__ void k_stage(const float *tgt, const int32_t *perm, int32_t m, float s, int32_t klo0,
+                        int32_t klo1, int32_t klo2, float *ys, float *yt)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     const int klo[3] = {klo0, klo1, klo2};
+    const int src = perm ? perm[j] : j;
     for (int a = 0; a < 3; ++a) {
-        float y = tgt[3 * j + a];
+        float y = tgt[3 * src + a];
         float ofs = 0.5f - (float)klo[a];
         ys[a * m + j] = __fadd_rn(__fmul_rn(y, s), ofs);
         yt[a * m + j] = y;
     }
 }
 
-hipError_t launch_stage(const float *tgt, int32_t m, float s, const int32_t *klo, float *ys,
-                        float *yt, hipStream_t stream)
+hipError_t launch_stage(const float *tgt, const int32_t *perm, int32_t m, float s,
+                        const int32_t *klo, float *ys, float *yt, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_stage, dim3((m + 255) / 256), dim3(256), 0, stream, tgt, m, s, klo[0],
-                       klo[1], klo[2], ys, yt);
+    hipLaunchKernelGGL(k_stage, dim3((m + 255) / 256), dim3(256), 0, stream, tgt, perm, m, s,
+                       klo[0], klo[1], klo[2], ys, yt);
     return hipGetLastError();
 }
 
@@ -170,6 +171,20 @@ typedef const float __attribute__((address_space(4))) *kfloat;
 typedef const int32_t __attribute__((address_space(4))) *kint;
 __device__ __forceinline__ kfloat kc(const float *p) { return (kfloat)p; }
 __device__ __forceinline__ kint kc(const int32_t *p) { return (kint)p; }
+
+// Copy a wave-uniform struct from device memory through the constant address
+// space (scalar loads into SGPRs).
+template <class T>
+__device__ __forceinline__ T kload(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
+    T v;
+    const kint src = kc(reinterpret_cast<const int32_t *>(p));
+    int32_t *dst = reinterpret_cast<int32_t *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+    return v;
+}
 
 // Lane layout for a chunk of up to 1024 source points: `sw` waves hold the chunk
 // (one point per lane) and the reference is split into G partitions, one per
@@ -214,8 +229,35 @@ __device__ __forceinline__ void vote_pair(uint32_t *hist, int cx, int cy, int cz
     }
 }
 
+__device__ __forceinline__ float wave_min(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Reference index range [lo, hi) of the x-sorted reference whose pairs with any
+// source of x coordinate in [pmin, pmax] can fall in box x-planes [x0, x1):
+// floor(Y - P) in [x0, x1) implies Y in [P + x0, P + x1), widened by one bin on
+// each side for float rounding.  The per-pair x test stays exact.
+__device__ __forceinline__ void ref_window(const SweepArgs &a, float pmin, float pmax, int x0,
+                                           int x1, int &lo, int &hi)
+{
+    const kint tab = kc(a.tab);
+    const int qlo = cvt_flr(pmin + (float)(x0 - 1)) - a.tab_lo;
+    const int qhi = cvt_flr(pmax + (float)(x1 + 1)) + 1 - a.tab_lo;
+    lo = qlo <= 0 ? 0 : (qlo >= a.tab_n ? a.g.m : tab[qlo]);
+    hi = qhi <= 0 ? 0 : (qhi >= a.tab_n ? a.g.m : tab[qhi]);
+}
+
 template <int CW>
-__device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, uint32_t *hist)
+__device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, uint32_t *hist,
+                          bool sorted, int slot)
 {
     const Geom &g = a.g;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -224,19 +266,36 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
     const uint32_t negc = 0u - (uint32_t)x0 * sx4;
     const int m = g.m;
     const kfloat ysx = kc(a.ys), ysy = kc(a.ys + m), ysz = kc(a.ys + 2 * m);
+    const float4 *mine = a.scratch + (size_t)slot * a.scratch_stride;
     for (int c0 = 0; c0 < g.n; c0 += kBlock) {
         const ChunkLayout L = chunk_layout(c0, g.n, wave, lane);
         if (!L.active) continue;
         float Px = 1.0e7f, Py = 1.0e7f, Pz = 1.0e7f;      // padding lanes never vote
         if (L.i < g.n) {
-            float px, py, pz;
-            rotate(R, a.src[3 * L.i], a.src[3 * L.i + 1], a.src[3 * L.i + 2], px, py, pz);
-            Px = __fmul_rn(px, g.s);
-            Py = __fmul_rn(py, g.s);
-            Pz = __fmul_rn(pz, g.s);
+            if (sorted) {
+                const float4 P = mine[L.i];
+                Px = P.x;
+                Py = P.y;
+                Pz = P.z;
+            } else {
+                float px, py, pz;
+                rotate(R, a.src[3 * L.i], a.src[3 * L.i + 1], a.src[3 * L.i + 2], px, py, pz);
+                Px = __fmul_rn(px, g.s);
+                Py = __fmul_rn(py, g.s);
+                Pz = __fmul_rn(pz, g.s);
+            }
         }
-        const int j0 = uni((int)((int64_t)m * L.part / L.G));
-        const int j1 = uni((int)((int64_t)m * (L.part + 1) / L.G));
+        int j0 = uni((int)((int64_t)m * L.part / L.G));
+        int j1 = uni((int)((int64_t)m * (L.part + 1) / L.G));
+        if (sorted) {
+            const bool real = L.i < g.n;
+            const float pmin = wave_min(real ? Px : INFINITY);
+            const float pmax = wave_max(real ? Px : -INFINITY);
+            int lo, hi;
+            ref_window(a, pmin, pmax, x0, x0 + np, lo, hi);
+            j0 = max(j0, uni(lo));
+            j1 = min(j1, uni(hi));
+        }
         int j = j0;
         for (; j + 4 <= j1; j += 4) {
             int cx[4], cy[4], cz[4];
@@ -254,6 +313,52 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             vote_pair<CW>(hist, cvt_flr(ysx[j] - Px), cvt_flr(ysy[j] - Py), cvt_flr(ysz[j] - Pz),
                           x0, (uint32_t)np, Sy, Sz, sx4, sy4, negc);
     }
+}
+
+// Bucket-sort the rotated, scaled source points of one rotation by x into this
+// workgroup's scratch slot (buckets one bin unit wide), so that each wave's 64
+// consecutive points span a narrow x range and can skip reference points whose
+// pairs cannot land in the current slab.
+__device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, uint32_t *scr,
+                             int slot)
+{
+    const Geom &g = a.g;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t *cnt = lds;                       // kSortBuckets counters
+    uint32_t *key = lds + kSortBuckets;        // per source: bucket << 20 | rank
+    float4 *out = a.scratch + (size_t)slot * a.scratch_stride;
+    for (int b = tid; b < kSortBuckets; b += kBlock) cnt[b] = 0u;
+    __syncthreads();
+    for (int i = tid; i < g.n; i += kBlock) {
+        float px, py, pz;
+        rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
+        const float Px = __fmul_rn(px, g.s);
+        const int b = min(max(cvt_flr(Px) + kSortBuckets / 2, 0), kSortBuckets - 1);
+        const uint32_t rank = atomicAdd(&cnt[b], 1u);
+        key[i] = ((uint32_t)b << 20) | rank;
+    }
+    __syncthreads();
+    // exclusive prefix sum of the bucket counts (one bucket per thread)
+    const uint32_t v = tid < kSortBuckets ? cnt[tid] : 0u;
+    uint32_t incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) scr[160 + wave] = incl;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += scr[160 + w];
+    if (tid < kSortBuckets) cnt[tid] = base + incl - v;
+    __syncthreads();
+    for (int i = tid; i < g.n; i += kBlock) {
+        float px, py, pz;
+        rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
+        const uint32_t kk = key[i];
+        const uint32_t pos = cnt[kk >> 20] + (kk & 0xFFFFFu);
+        out[pos] = make_float4(__fmul_rn(px, g.s), __fmul_rn(py, g.s), __fmul_rn(pz, g.s), 0.0f);
+    }
+    __syncthreads();
 }
 
 // Scan one slab: per-thread best (count, lowest position).  Positions are word
@@ -365,20 +470,23 @@ __device__ __forceinline__ float df_lookup(const Field &f, float qx, float qy, f
     return f.r;
 }
 
+// Vote, mode and score one rotation k with the whole workgroup; `slot` selects
+// the workgroup's source-sort scratch.  Writes a.rec[k].
 template <int CW, int SCORER>
-__global__ void __launch_bounds__(kBlock) k_sweep(SweepArgs a)
+__device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
 {
-    __shared__ __align__(16) uint32_t lds[kLdsWords];
     const Geom &g = a.g;
     uint32_t *hist = lds;
     uint32_t *scr = lds + kHistWordsMax;          // kScratchWords words
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t Sy = g.size[1];
     const uint32_t RW = (uint32_t)g.row_words;
-    const int k = blockIdx.x;
+    const bool sorted = a.scratch != nullptr;
+  {
     float R[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) R[e] = kc(a.rot)[9 * k + e];
+    if (sorted) sort_sources(a, R, lds, scr, slot);
 
     // ---------------- vote + mode over the slabs ----------------
     uint32_t best_c = 0, best_p = 0xFFFFFFFFu;
@@ -390,7 +498,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(SweepArgs a)
         uint4 *h4 = reinterpret_cast<uint4 *>(hist);
         for (int w = tid; w < words4; w += kBlock) h4[w] = make_uint4(0, 0, 0, 0);
         __syncthreads();
-        vote_slab<CW>(a, R, x0, np, hist);
+        vote_slab<CW>(a, R, x0, np, hist, sorted, slot);
         __syncthreads();
         uint32_t bc = 0, bp = 0xFFFFFFFFu;
         const uint32_t pos0 = (uint32_t)x0 * Sy * RW * (CW == 16 ? 2u : 1u);
@@ -517,29 +625,41 @@ __global__ void __launch_bounds__(kBlock) k_sweep(SweepArgs a)
         rec.error = e;
         a.rec[k] = rec;
     }
+    __syncthreads();                          // LDS scratch reused by the next rotation
+  }
+}
+
+template <int CW, int SCORER>
+__global__ void __launch_bounds__(kBlock) k_sweep(SweepArgs a)
+{
+    __shared__ __align__(16) uint32_t lds[kLdsWords];
+    for (int k = blockIdx.x; k < a.k; k += gridDim.x) sweep_one<CW, SCORER>(a, k, lds, blockIdx.x);
 }
 
 template <int CW, int SC>
-static hipError_t launch_one(const SweepArgs &a, hipStream_t stream)
+static hipError_t launch_one(const SweepArgs &a, int grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_sweep<CW, SC>), dim3(a.k), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL((k_sweep<CW, SC>), dim3(grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const SweepArgs &a, int scorer, hipStream_t stream)
+// grid: persistent workgroups (each sweeps rotations blockIdx.x, +gridDim.x, ...);
+// with a.scratch set it must not exceed the number of scratch slots.
+hipError_t launch_sweep(const SweepArgs &a, int scorer, int grid, hipStream_t stream)
 {
     if (a.k <= 0) return hipSuccess;
+    if (grid > a.k) grid = a.k;
     if (a.g.counter_bits == 16) {
         switch (scorer) {
-        case DSES_SCORER_BRUTE: return launch_one<16, DSES_SCORER_BRUTE>(a, stream);
-        case DSES_SCORER_GRID: return launch_one<16, DSES_SCORER_GRID>(a, stream);
-        default: return launch_one<16, DSES_SCORER_DF>(a, stream);
+        case DSES_SCORER_BRUTE: return launch_one<16, DSES_SCORER_BRUTE>(a, grid, stream);
+        case DSES_SCORER_GRID: return launch_one<16, DSES_SCORER_GRID>(a, grid, stream);
+        default: return launch_one<16, DSES_SCORER_DF>(a, grid, stream);
         }
     }
     switch (scorer) {
-    case DSES_SCORER_BRUTE: return launch_one<32, DSES_SCORER_BRUTE>(a, stream);
-    case DSES_SCORER_GRID: return launch_one<32, DSES_SCORER_GRID>(a, stream);
-    default: return launch_one<32, DSES_SCORER_DF>(a, stream);
+    case DSES_SCORER_BRUTE: return launch_one<32, DSES_SCORER_BRUTE>(a, grid, stream);
+    case DSES_SCORER_GRID: return launch_one<32, DSES_SCORER_GRID>(a, grid, stream);
+    default: return launch_one<32, DSES_SCORER_DF>(a, grid, stream);
     }
 }
 
@@ -558,12 +678,10 @@ __device__ __forceinline__ bool sel_better(float e, int i, int k, float oe, int 
     return ok < k;
 }
 
-__global__ void __launch_bounds__(1024) k_select(const dses_record *rec, int32_t K,
-                                                 const float *rot, float delta, DevResult *res,
-                                                 const uint32_t *status)
+__device__ void select_body(const dses_record *rec, int32_t K, const float *rot, float delta,
+                            DevResult *res, const uint32_t *status, float *se, int *si, int *sk,
+                            int *sv)
 {
-    __shared__ float se[16];
-    __shared__ int si[16], sk[16], sv[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     float be = INFINITY;
     int bi = 0, bk = -1, nvalid = 0;
@@ -602,11 +720,104 @@ __global__ void __launch_bounds__(1024) k_select(const dses_record *rec, int32_t
     }
 }
 
+__global__ void __launch_bounds__(1024) k_select(const dses_record *rec, int32_t K,
+                                                 const float *rot, float delta, DevResult *res,
+                                                 const uint32_t *status)
+{
+    __shared__ float se[16];
+    __shared__ int si[16], sk[16], sv[16];
+    select_body(rec, K, rot, delta, res, status, se, si, sk, sv);
+}
+
 hipError_t launch_select(const dses_record *rec, int32_t k, const float *rot, float delta,
                          DevResult *res, const uint32_t *status, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, stream, rec, k, rot, delta, res,
                        status);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// batched registration: one persistent launch over a work list of
+// (instance, rotation tile) items, most expensive first, fetched dynamically.
+// Each rotation runs the same sweep_one() as the single-registration kernel, so
+// a registration's records do not depend on what it is batched with.
+// --------------------------------------------------------------------------
+template <int SCORER>
+__global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchArgs b)
+{
+    __shared__ __align__(16) uint32_t lds[kLdsWords];
+    const int n_items = __builtin_amdgcn_readfirstlane(*(kint)(const int32_t *)b.header);
+    for (;;) {
+        if (threadIdx.x == 0) lds[kLdsWords - 1] = atomicAdd(b.cursor, 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane((int)lds[kLdsWords - 1]);
+        __syncthreads();
+        if (it >= n_items) break;
+        const BatchItem w = kload(b.items + it);
+        const SweepArgs a = kload(b.inst + w.inst);
+        for (int k = w.k0; k < w.k1; ++k) {
+            if (a.g.counter_bits == 16)
+                sweep_one<16, SCORER>(a, k, lds, blockIdx.x);
+            else
+                sweep_one<32, SCORER>(a, k, lds, blockIdx.x);
+        }
+    }
+}
+
+hipError_t launch_sweep_batch(const BatchArgs &b, int scorer, int grid, hipStream_t stream)
+{
+    switch (scorer) {
+    case DSES_SCORER_BRUTE:
+        hipLaunchKernelGGL(k_sweep_batch<DSES_SCORER_BRUTE>, dim3(grid), dim3(kBlock), 0, stream, b);
+        break;
+    case DSES_SCORER_GRID:
+        hipLaunchKernelGGL(k_sweep_batch<DSES_SCORER_GRID>, dim3(grid), dim3(kBlock), 0, stream, b);
+        break;
+    default:
+        hipLaunchKernelGGL(k_sweep_batch<DSES_SCORER_DF>, dim3(grid), dim3(kBlock), 0, stream, b);
+        break;
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_stage_batch(const StageDesc *d, const int32_t *header)
+{
+    const int count = header[1];
+    for (int inst = blockIdx.y; inst < count; inst += gridDim.y) {
+        const StageDesc sd = d[inst];
+        for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < sd.m; j += gridDim.x * blockDim.x) {
+            const int src = sd.perm ? sd.perm[j] : j;
+            for (int a = 0; a < 3; ++a) {
+                const float y = sd.tgt[3 * src + a];
+                const float ofs = 0.5f - (float)sd.klo[a];
+                sd.ys[a * sd.m + j] = __fadd_rn(__fmul_rn(y, sd.s), ofs);
+                sd.yt[a * sd.m + j] = y;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_select_batch(const SelectDesc *d, const int32_t *header)
+{
+    __shared__ float se[16];
+    __shared__ int si[16], sk[16], sv[16];
+    const int count = header[1];
+    for (int inst = blockIdx.x; inst < count; inst += gridDim.x) {
+        const SelectDesc sd = d[inst];
+        select_body(sd.rec, sd.k, sd.rot, sd.delta, sd.res, sd.status, se, si, sk, sv);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch_aux(const StageDesc *stage, const SelectDesc *sel, const int32_t *header,
+                            int max_count, int which, hipStream_t stream)
+{
+    const int gy = max_count < 1 ? 1 : (max_count > 65535 ? 65535 : max_count);
+    if (which == 0)
+        hipLaunchKernelGGL(k_stage_batch, dim3(16, gy), dim3(256), 0, stream, stage, header);
+    else
+        hipLaunchKernelGGL(k_select_batch, dim3(gy), dim3(1024), 0, stream, sel, header);
     return hipGetLastError();
 }
 

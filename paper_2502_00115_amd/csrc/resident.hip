@@ -8,14 +8,6 @@
 
 #include "host.h"
 
-struct dses_target {
-    dses::TargetRes res;
-};
-
-struct dses_rotset {
-    dses::RotRes res;
-};
-
 namespace dses {
 
 static dses_status copy_to_host(const float *p, size_t count, bool dev, std::vector<float> *out)
@@ -26,6 +18,75 @@ static dses_status copy_to_host(const float *p, size_t count, bool dev, std::vec
     } else {
         std::memcpy(out->data(), p, count * sizeof(float));
     }
+    return DSES_OK;
+}
+
+dses_status ensure_target_grid(TargetRes *tm, float r, CellGrid *cg)
+{
+    std::lock_guard<std::mutex> gl(tm->grid_mu);
+    if (tm->grid_r != r) {
+        HostGrid hg;
+        dses_status st = build_grid(tm->host_aos.data(), tm->m, r, &hg);
+        if (st != DSES_OK) return st;
+        if (tm->grid_pts) (void)hipFree(tm->grid_pts);
+        if (tm->grid_start) (void)hipFree(tm->grid_start);
+        tm->grid_pts = nullptr;
+        tm->grid_start = nullptr;
+        tm->grid_r = -1.0f;
+        DSES_HIP(hipMalloc(&tm->grid_pts, hg.pts.size() * sizeof(float)));
+        DSES_HIP(hipMalloc(&tm->grid_start, hg.start.size() * sizeof(int32_t)));
+        DSES_HIP(hipMemcpy(tm->grid_pts, hg.pts.data(), hg.pts.size() * sizeof(float),
+                           hipMemcpyHostToDevice));
+        DSES_HIP(hipMemcpy(tm->grid_start, hg.start.data(), hg.start.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice));
+        hg.pts.clear();
+        hg.start.clear();
+        tm->grid_meta = hg;
+        tm->grid_r = r;
+    }
+    if (cg) {
+        cg->pts = tm->grid_pts;
+        cg->start = tm->grid_start;
+        for (int q = 0; q < 3; ++q) {
+            cg->lo[q] = tm->grid_meta.lo[q];
+            cg->dim[q] = tm->grid_meta.dim[q];
+        }
+        cg->inv = tm->grid_meta.inv;
+    }
+    return DSES_OK;
+}
+
+dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> gl(tm->grid_mu);
+    if (tm->st_delta == p.delta && tm->st_klo[0] == p.klo[0] && tm->st_klo[1] == p.klo[1] &&
+        tm->st_klo[2] == p.klo[2])
+        return DSES_OK;
+    const size_t m = (size_t)tm->m;
+    if (tm->perm_x.empty()) sort_by_x(tm->host_aos.data(), tm->m, &tm->perm_x);
+    std::vector<int32_t> tab;
+    int32_t tab_lo = 0;
+    const float s = 1.0f / p.delta;
+    const bool sorted = build_x_table(tm->host_aos.data(), tm->perm_x, s, p.klo[0], &tab, &tab_lo);
+    for (void *q : {(void *)tm->st_ys, (void *)tm->st_yt, (void *)tm->st_perm, (void *)tm->st_tab})
+        if (q) (void)hipFree(q);
+    tm->st_ys = tm->st_yt = nullptr;
+    tm->st_perm = tm->st_tab = nullptr;
+    tm->st_delta = -1.0f;
+    DSES_HIP(hipMalloc(&tm->st_ys, 12 * m));
+    DSES_HIP(hipMalloc(&tm->st_yt, 12 * m));
+    DSES_HIP(hipMalloc(&tm->st_perm, 4 * m));
+    DSES_HIP(hipMemcpy(tm->st_perm, tm->perm_x.data(), 4 * m, hipMemcpyHostToDevice));
+    if (sorted) {
+        DSES_HIP(hipMalloc(&tm->st_tab, 4 * tab.size()));
+        DSES_HIP(hipMemcpy(tm->st_tab, tab.data(), 4 * tab.size(), hipMemcpyHostToDevice));
+    }
+    DSES_HIP(launch_stage(tm->aos, tm->st_perm, tm->m, s, p.klo, tm->st_ys, tm->st_yt, stream));
+    DSES_HIP(hipStreamSynchronize(stream));
+    tm->st_tab_lo = tab_lo;
+    tm->st_tab_n = sorted ? (int32_t)tab.size() : 0;
+    for (int a = 0; a < 3; ++a) tm->st_klo[a] = p.klo[a];
+    tm->st_delta = p.delta;
     return DSES_OK;
 }
 
@@ -133,6 +194,8 @@ dses_status dses_target_destroy(dses_target *t)
 {
     if (!t) return DSES_E_INVAL;
     TargetRes &T = t->res;
+    for (void *q : {(void *)T.st_ys, (void *)T.st_yt, (void *)T.st_perm, (void *)T.st_tab})
+        if (q) (void)hipFree(q);
     if (T.aos) (void)hipFree(T.aos);
     if (T.yt) (void)hipFree(T.yt);
     if (T.df) (void)hipFree(T.df);

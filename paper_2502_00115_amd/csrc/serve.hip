@@ -1,0 +1,609 @@
+// Serving: a request loop with memory-based admission and continuous batching.
+//
+// Clients submit registrations against resident reference clouds and rotation
+// lists.  A scheduler thread owns all device work of the server:
+//  * admission: FIFO, a request enters the device when its buffers fit the
+//    memory budget (a first-fit pool carved from one allocation made at create
+//    time, so admission never calls hipMalloc/hipFree) and an instance slot is
+//    free;
+//  * continuous batching: the GPU runs a sequence of short persistent launches
+//    ("slices") of the batched sweep kernel.  Each slice's work list takes
+//    rotation tiles from every request on the device, shortest remaining work
+//    first, so requests that arrive while others run join the next slice and
+//    their rotations overlap on the device with the older requests';
+//  * a request whose last tile is in a slice is selected at the end of that
+//    slice; its result is copied back and its memory returned to the pool.
+// Each rotation runs the same sweep_one() as a lone registration, so a request's
+// result does not depend on what it was served with.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "host.h"
+
+namespace dses {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr int kSliceSets = 3;               // slices in flight + one being filled
+constexpr int kMaxSliceItems = 8192;
+constexpr int32_t kServeMaxSrc = 16384;     // largest source a request may carry
+// pinned staging per slot: the source, then its SweepArgs
+constexpr size_t kSlotStageBytes = ((12 * (size_t)kServeMaxSrc + sizeof(SweepArgs)) + 255) & ~size_t(255);
+
+// First-fit allocator over one device allocation (offsets in bytes).
+struct Pool {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;         // offset -> length
+    void init(size_t n) { size = n; free_.clear(); free_[0] = n; }
+    bool alloc(size_t n, size_t *off)
+    {
+        n = (n + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n;
+                const size_t at = it->first + n;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        n = (n + 255) & ~size_t(255);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Request {
+    uint64_t id = 0;
+    const TargetRes *target = nullptr;
+    const RotRes *rots = nullptr;
+    std::vector<float> src;
+    int32_t n = 0, m = 0, k = 0;
+    Params p{};
+    int scorer = DSES_SCORER_GRID;
+    // lifecycle
+    enum State { QUEUED, ADMITTED, DONE } state = QUEUED;
+    dses_status status = DSES_OK;
+    dses_result out{};
+    Clock::time_point t_submit, t_admit, t_done;
+    // device residency
+    size_t off = 0, bytes = 0;
+    int slot = -1;
+    int32_t next_k = 0;                      // rotations handed to slices so far
+    double pair_cost = 0.0;                  // n * m per rotation
+    dses_record *d_rec = nullptr;            // records inside the request's pool range
+};
+
+struct SliceSet {
+    BatchItem *h_items = nullptr;            // pinned
+    SelectDesc *h_sel = nullptr;             // pinned
+    int32_t *h_header = nullptr;             // pinned
+    void *d_items = nullptr, *d_sel = nullptr, *d_header = nullptr, *d_cursor = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<Request *> finishing;
+};
+
+}  // namespace
+
+struct ServerImpl {
+    Context *c = nullptr;
+    dses_server_opts opt{};
+    hipStream_t stream = nullptr;
+    void *pool_mem = nullptr;
+    Pool pool;
+    int max_slots = 0;
+    SweepArgs *d_args = nullptr;             // one per slot
+    DevResult *d_res = nullptr, *h_res = nullptr;
+    uint32_t *d_status = nullptr;
+    float4 *d_scratch = nullptr;
+    float *h_stage = nullptr;                // pinned per-slot source staging
+    SliceSet sets[kSliceSets];
+    int grid = 0;
+    double slice_pairs = 0.0;
+    // shared state
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::vector<Request *> active;           // admitted, not finished
+    std::map<uint64_t, Request *> all;
+    std::vector<int> free_slots;
+    uint64_t next_id = 1;
+    bool stop = false;
+    std::thread worker;
+    std::string fatal;
+
+    dses_status init(Context *ctx, const dses_server_opts &o);
+    void run();
+    bool admit_locked();
+    bool launch_slice();
+    void poll_slices();
+    size_t need_bytes(const Request &r) const;
+    dses_status prepare(Request *r);
+    ~ServerImpl();
+};
+
+size_t ServerImpl::need_bytes(const Request &r) const
+{
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return al(12 * (size_t)r.n) + al(24 * (size_t)r.k);
+}
+
+dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
+{
+    c = ctx;
+    opt = o;
+    if (opt.memory_budget <= 0) opt.memory_budget = (int64_t)1 << 30;
+    if (opt.max_inflight <= 0) opt.max_inflight = 64;
+    max_slots = opt.max_inflight;
+    grid = std::max(1, c->n_cu);
+    slice_pairs = 6.0e9;            // about 2-6 ms of sweep work per slice
+    DSES_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    if (hipMalloc(&pool_mem, (size_t)opt.memory_budget) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("cannot reserve the serving memory budget on the device");
+        return DSES_E_NOMEM;
+    }
+    pool.init((size_t)opt.memory_budget);
+    DSES_HIP(hipMalloc(&d_args, max_slots * sizeof(SweepArgs)));
+    DSES_HIP(hipMalloc(&d_res, max_slots * sizeof(DevResult)));
+    DSES_HIP(hipMalloc(&d_status, max_slots * sizeof(uint32_t)));
+    DSES_HIP(hipMemset(d_status, 0, max_slots * sizeof(uint32_t)));
+    DSES_HIP(hipMalloc(&d_scratch, (size_t)grid * kServeMaxSrc * sizeof(float4)));
+    void *p = nullptr;
+    DSES_HIP(hipHostMalloc(&p, max_slots * sizeof(DevResult), hipHostMallocDefault));
+    h_res = static_cast<DevResult *>(p);
+    DSES_HIP(hipHostMalloc(&p, (size_t)max_slots * kSlotStageBytes, hipHostMallocDefault));
+    h_stage = static_cast<float *>(p);
+    for (auto &s : sets) {
+        DSES_HIP(hipHostMalloc(&p, kMaxSliceItems * sizeof(BatchItem), hipHostMallocDefault));
+        s.h_items = static_cast<BatchItem *>(p);
+        DSES_HIP(hipHostMalloc(&p, max_slots * sizeof(SelectDesc), hipHostMallocDefault));
+        s.h_sel = static_cast<SelectDesc *>(p);
+        DSES_HIP(hipHostMalloc(&p, 64, hipHostMallocDefault));
+        s.h_header = static_cast<int32_t *>(p);
+        DSES_HIP(hipMalloc(&s.d_items, kMaxSliceItems * sizeof(BatchItem)));
+        DSES_HIP(hipMalloc(&s.d_sel, max_slots * sizeof(SelectDesc)));
+        DSES_HIP(hipMalloc(&s.d_header, 64));
+        DSES_HIP(hipMalloc(&s.d_cursor, 64));
+        DSES_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+    }
+    for (int i = max_slots - 1; i >= 0; --i) free_slots.push_back(i);
+    worker = std::thread([this] { run(); });
+    return DSES_OK;
+}
+
+ServerImpl::~ServerImpl()
+{
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        stop = true;
+    }
+    cv_work.notify_all();
+    if (worker.joinable()) worker.join();
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto &s : sets) {
+        if (s.h_items) (void)hipHostFree(s.h_items);
+        if (s.h_sel) (void)hipHostFree(s.h_sel);
+        if (s.h_header) (void)hipHostFree(s.h_header);
+        if (s.d_items) (void)hipFree(s.d_items);
+        if (s.d_sel) (void)hipFree(s.d_sel);
+        if (s.d_header) (void)hipFree(s.d_header);
+        if (s.d_cursor) (void)hipFree(s.d_cursor);
+        if (s.done) (void)hipEventDestroy(s.done);
+    }
+    if (h_res) (void)hipHostFree(h_res);
+    if (h_stage) (void)hipHostFree(h_stage);
+    if (d_args) (void)hipFree(d_args);
+    if (d_res) (void)hipFree(d_res);
+    if (d_status) (void)hipFree(d_status);
+    if (d_scratch) (void)hipFree(d_scratch);
+    if (pool_mem) (void)hipFree(pool_mem);
+    if (stream) (void)hipStreamDestroy(stream);
+    for (auto &kv : all) delete kv.second;
+}
+
+// Device preparation of an admitted request (scheduler thread; the request owns
+// its pool range and slot): the reference is staged once per target and pitch
+// (cached), so a request only uploads its source and its sweep arguments, both
+// from the slot's pinned staging area, asynchronously on the server stream ahead
+// of any slice that carries the request's tiles.
+dses_status ServerImpl::prepare(Request *r)
+{
+    auto *tm = const_cast<TargetRes *>(r->target);
+    const int bits = counter_bound(tm->host_aos.data(), r->m, r->n, r->p) <= 65535 ? 16 : 32;
+    Geom g;
+    dses_status st = plan_geom(c, r->p, r->n, r->m, bits, &g);
+    if (st != DSES_OK) return st;
+    if ((st = ensure_target_stage(tm, r->p, stream)) != DSES_OK) return st;
+    CellGrid cg{};
+    if (r->scorer == DSES_SCORER_GRID && (st = ensure_target_grid(tm, r->p.r, &cg)) != DSES_OK)
+        return st;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    char *base = static_cast<char *>(pool_mem) + r->off;
+    float *d_src = reinterpret_cast<float *>(base);
+    r->d_rec = reinterpret_cast<dses_record *>(base + al(12 * (size_t)r->n));
+    char *stage = reinterpret_cast<char *>(h_stage) + (size_t)r->slot * kSlotStageBytes;
+    std::memcpy(stage, r->src.data(), 12 * (size_t)r->n);
+    SweepArgs &a = *reinterpret_cast<SweepArgs *>(stage + 12 * (size_t)kServeMaxSrc);
+    a = SweepArgs{};
+    a.src = d_src;
+    a.rot = r->rots->rot;
+    a.ys = tm->st_ys;
+    a.yt = tm->st_yt;
+    const bool sorted = r->n <= kSortMax && tm->st_tab_n > 0;
+    a.tab = sorted ? tm->st_tab : nullptr;
+    a.tab_lo = tm->st_tab_lo;
+    a.tab_n = sorted ? tm->st_tab_n : 0;
+    a.scratch = sorted ? d_scratch : nullptr;
+    a.scratch_stride = kServeMaxSrc;
+    a.g = g;
+    a.grid = cg;
+    if (r->scorer == DSES_SCORER_DF) {
+        a.field.val = tm->df;
+        a.field.res = tm->df_res;
+        a.field.r = tm->df_r;
+        for (int q = 0; q < 3; ++q) { a.field.lo[q] = tm->df_lo[q]; a.field.inv[q] = tm->df_inv[q]; }
+    }
+    a.rec = r->d_rec;
+    a.k = r->k;
+    DSES_HIP(hipMemcpyAsync(d_src, stage, 12 * (size_t)r->n, hipMemcpyHostToDevice, stream));
+    DSES_HIP(hipMemcpyAsync(d_args + r->slot, &a, sizeof(SweepArgs), hipMemcpyHostToDevice,
+                            stream));
+    return DSES_OK;
+}
+
+bool ServerImpl::admit_locked()
+{
+    bool any = false;
+    while (!queue.empty()) {
+        Request *r = queue.front();
+        if (free_slots.empty()) break;
+        size_t off = 0;
+        if (!pool.alloc(r->bytes, &off)) break;      // wait for memory to be returned
+        queue.pop_front();
+        r->off = off;
+        r->slot = free_slots.back();
+        free_slots.pop_back();
+        r->t_admit = Clock::now();
+        mu.unlock();
+        dses_status st = prepare(r);
+        mu.lock();
+        if (st != DSES_OK) {
+            r->status = st;
+            r->state = Request::DONE;
+            r->t_done = Clock::now();
+            pool.release(r->off, r->bytes);
+            free_slots.push_back(r->slot);
+            cv_done.notify_all();
+            continue;
+        }
+        r->state = Request::ADMITTED;
+        active.push_back(r);
+        any = true;
+    }
+    return any;
+}
+
+// Fill and launch one slice from the active requests (scheduler thread, mu held).
+bool ServerImpl::launch_slice()
+{
+    SliceSet *s = nullptr;
+    for (auto &cand : sets)
+        if (!cand.busy) { s = &cand; break; }
+    if (!s) return false;
+    std::vector<Request *> order;
+    for (Request *r : active)
+        if (r->next_k < r->k) order.push_back(r);
+    if (order.empty()) return false;
+    std::stable_sort(order.begin(), order.end(), [](const Request *a, const Request *b) {
+        return (a->k - a->next_k) * a->pair_cost < (b->k - b->next_k) * b->pair_cost;
+    });
+    const int scorer = order.front()->scorer;      // one kernel instantiation per slice
+    int n_items = 0, n_sel = 0;
+    double budget = slice_pairs;
+    s->finishing.clear();
+    for (Request *r : order) {
+        if (budget <= 0.0 || n_items >= kMaxSliceItems) break;
+        if (r->scorer != scorer) continue;
+        const double per_tile_target = std::max(1.0, slice_pairs / (4.0 * grid));
+        const int32_t tile =
+            (int32_t)std::max(1.0, std::min((double)r->k, per_tile_target / r->pair_cost));
+        while (r->next_k < r->k && budget > 0.0 && n_items < kMaxSliceItems) {
+            const int32_t k0 = r->next_k, k1 = std::min(r->k, k0 + tile);
+            s->h_items[n_items++] = BatchItem{r->slot, k0, k1, 0};
+            r->next_k = k1;
+            budget -= (k1 - k0) * r->pair_cost;
+        }
+        if (r->next_k == r->k) {
+            const int slot = r->slot;
+            s->h_sel[n_sel++] = SelectDesc{r->d_rec, r->k, r->p.delta, r->rots->rot,
+                                           d_res + slot, d_status + slot};
+            s->finishing.push_back(r);
+        }
+    }
+    s->h_header[0] = n_items;
+    s->h_header[1] = n_sel;
+    mu.unlock();
+    bool ok = true;
+    auto chk = [&](hipError_t e) { if (e != hipSuccess) { ok = false; fatal = hipGetErrorString(e); } };
+    chk(hipMemcpyAsync(s->d_items, s->h_items, n_items * sizeof(BatchItem), hipMemcpyHostToDevice, stream));
+    chk(hipMemcpyAsync(s->d_sel, s->h_sel, std::max(1, n_sel) * sizeof(SelectDesc), hipMemcpyHostToDevice, stream));
+    chk(hipMemcpyAsync(s->d_header, s->h_header, 8, hipMemcpyHostToDevice, stream));
+    chk(launch_clear(static_cast<uint32_t *>(s->d_cursor), 1, stream));
+    BatchArgs ba{d_args, static_cast<BatchItem *>(s->d_items),
+                 static_cast<int32_t *>(s->d_header), static_cast<uint32_t *>(s->d_cursor)};
+    chk(launch_sweep_batch(ba, scorer, grid, stream));
+    if (n_sel > 0) {
+        chk(launch_batch_aux(nullptr, static_cast<SelectDesc *>(s->d_sel),
+                             static_cast<int32_t *>(s->d_header), n_sel, 1, stream));
+        for (Request *r : s->finishing)
+            chk(hipMemcpyAsync(h_res + r->slot, d_res + r->slot, sizeof(DevResult),
+                               hipMemcpyDeviceToHost, stream));
+    }
+    chk(hipEventRecord(s->done, stream));
+    mu.lock();
+    s->busy = true;
+    return ok;
+}
+
+void ServerImpl::poll_slices()
+{
+    // slices complete in stream order; finish requests of completed ones
+    for (auto &s : sets) {
+        if (!s.busy) continue;
+        if (hipEventQuery(s.done) != hipSuccess) continue;
+        for (Request *r : s.finishing) {
+            const DevResult &d = h_res[r->slot];
+            if (d.bad_input) {
+                r->status = DSES_E_INVAL;
+            } else if (d.rot_index < 0) {
+                r->status = DSES_E_NOCANDIDATE;
+            } else {
+                std::memcpy(r->out.R, d.R, sizeof(r->out.R));
+                std::memcpy(r->out.t, d.t, sizeof(r->out.t));
+                r->out.rot_index = d.rot_index;
+                r->out.inliers = d.inliers;
+                r->out.error = d.error;
+                r->out.votes = d.votes;
+                r->out.n_valid = d.n_valid;
+            }
+            r->state = Request::DONE;
+            r->t_done = Clock::now();
+            pool.release(r->off, r->bytes);
+            free_slots.push_back(r->slot);
+            active.erase(std::remove(active.begin(), active.end(), r), active.end());
+            r->src.clear();
+            r->src.shrink_to_fit();
+        }
+        s.finishing.clear();
+        s.busy = false;
+        cv_done.notify_all();
+    }
+}
+
+void ServerImpl::run()
+{
+    (void)hipSetDevice(c->device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        poll_slices();
+        admit_locked();
+        bool launched = false;
+        int busy = 0;
+        for (auto &s : sets) busy += s.busy ? 1 : 0;
+        if (busy < kSliceSets - 1) launched = launch_slice();
+        if (!fatal.empty()) {
+            // a HIP failure poisons the server: fail everything still pending
+            for (auto &kv : all)
+                if (kv.second->state != Request::DONE) {
+                    kv.second->status = DSES_E_DEVICE;
+                    kv.second->state = Request::DONE;
+                }
+            queue.clear();
+            active.clear();
+            cv_done.notify_all();
+            if (stop) break;
+            cv_work.wait_for(lk, std::chrono::milliseconds(50));
+            continue;
+        }
+        busy = 0;
+        for (auto &s : sets) busy += s.busy ? 1 : 0;
+        if (stop && queue.empty() && active.empty() && busy == 0) break;
+        if (!launched) {
+            if (busy > 0)
+                cv_work.wait_for(lk, std::chrono::microseconds(100));
+            else
+                cv_work.wait_for(lk, std::chrono::milliseconds(20));
+        }
+    }
+}
+
+}  // namespace dses
+
+struct dses_server {
+    dses::ServerImpl impl;
+};
+
+using namespace dses;
+
+extern "C" {
+
+dses_status dses_server_create(const dses_server_opts *opt, dses_server **out)
+{
+    set_error("");
+    if (!out) {
+        set_error("NULL output handle");
+        return DSES_E_INVAL;
+    }
+    dses_server_opts o{};
+    if (opt) o = *opt;
+    if (o.memory_budget < 0 || o.max_inflight < 0 || o.max_inflight > 4096 ||
+        o.scorer < DSES_SCORER_AUTO || o.scorer > DSES_SCORER_DF) {
+        set_error("invalid server options");
+        return DSES_E_INVAL;
+    }
+    Context *c = ctx();
+    if (!c) return DSES_E_DEVICE;
+    auto *s = new dses_server();
+    dses_status st = s->impl.init(c, o);
+    if (st != DSES_OK) {
+        delete s;
+        return st;
+    }
+    *out = s;
+    return DSES_OK;
+}
+
+dses_status dses_server_submit(dses_server *srv, const dses_target *tgt, const dses_rotset *rots,
+                               const float *src, int64_t n, float eps, dses_metric metric,
+                               uint64_t *req_id)
+{
+    set_error("");
+    if (!srv || !tgt || !rots || !src || !req_id || n <= 0 || n > kServeMaxSrc ||
+        n * (int64_t)tgt->res.m >= ((int64_t)1 << 31)) {
+        set_error("invalid request");
+        return DSES_E_INVAL;
+    }
+    ServerImpl &S = srv->impl;
+    auto *r = new Request();
+    dses_status st = resolve_params(eps, metric, 0.0f, 0.0f, nullptr, nullptr, S.opt.scorer, &r->p);
+    if (st != DSES_OK) {
+        delete r;
+        return st;
+    }
+    const float lim = coord_limit(r->p);
+    for (int64_t e = 0; e < 3 * n; ++e)
+        if (!(std::fabs(src[e]) <= lim)) {
+            delete r;
+            set_error("source coordinate is non-finite or too large for the lattice");
+            return DSES_E_INVAL;
+        }
+    r->target = &tgt->res;
+    r->rots = &rots->res;
+    r->n = (int32_t)n;
+    r->m = tgt->res.m;
+    r->k = (int32_t)rots->res.k;
+    r->scorer = r->p.scorer;
+    if (r->scorer == DSES_SCORER_AUTO)
+        r->scorer = (tgt->res.df && tgt->res.df_r == r->p.r && metric != DSES_TRUNC_L1)
+                        ? DSES_SCORER_DF
+                        : DSES_SCORER_GRID;
+    if (r->scorer == DSES_SCORER_DF &&
+        (!tgt->res.df || tgt->res.df_r != r->p.r || metric == DSES_TRUNC_L1)) {
+        delete r;
+        set_error("DF scorer needs a target field truncated at max(eps, tau)");
+        return DSES_E_INVAL;
+    }
+    r->src.assign(src, src + 3 * n);
+    r->pair_cost = (double)r->n * r->m + 1.0;
+    r->bytes = S.need_bytes(*r);
+    if (r->bytes > (size_t)S.opt.memory_budget) {
+        delete r;
+        set_error("request needs more device memory than the whole serving budget");
+        return DSES_E_NOMEM;
+    }
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        if (!S.fatal.empty()) {
+            delete r;
+            set_error("server failed: " + S.fatal);
+            return DSES_E_DEVICE;
+        }
+        r->id = S.next_id++;
+        r->t_submit = Clock::now();
+        S.all[r->id] = r;
+        S.queue.push_back(r);
+        *req_id = r->id;
+    }
+    S.cv_work.notify_all();
+    return DSES_OK;
+}
+
+dses_status dses_server_wait(dses_server *srv, uint64_t req_id, int32_t timeout_ms,
+                             dses_result *out, dses_status *req_status)
+{
+    if (!srv || !out || !req_status) return DSES_E_INVAL;
+    ServerImpl &S = srv->impl;
+    std::unique_lock<std::mutex> lk(S.mu);
+    auto it = S.all.find(req_id);
+    if (it == S.all.end()) {
+        set_error("unknown or already consumed request id");
+        return DSES_E_STATE;
+    }
+    Request *r = it->second;
+    auto done = [&] { return r->state == Request::DONE; };
+    if (timeout_ms < 0)
+        S.cv_done.wait(lk, done);
+    else if (!S.cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done)) {
+        set_error("request not finished within the timeout");
+        return DSES_E_TIMEOUT;
+    }
+    *out = r->out;
+    *req_status = r->status;
+    return DSES_OK;
+}
+
+int32_t dses_server_poll(dses_server *srv, uint64_t req_id)
+{
+    if (!srv) return DSES_E_INVAL;
+    ServerImpl &S = srv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(req_id);
+    if (it == S.all.end()) return DSES_E_STATE;
+    return it->second->state == Request::DONE ? 1 : 0;
+}
+
+dses_status dses_server_timing(dses_server *srv, uint64_t req_id, double *queue_s,
+                               double *total_s)
+{
+    if (!srv) return DSES_E_INVAL;
+    ServerImpl &S = srv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(req_id);
+    if (it == S.all.end() || it->second->state != Request::DONE) {
+        set_error("request unknown or not finished");
+        return DSES_E_STATE;
+    }
+    Request *r = it->second;
+    if (queue_s)
+        *queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
+    if (total_s)
+        *total_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    return DSES_OK;
+}
+
+dses_status dses_server_destroy(dses_server *srv)
+{
+    if (!srv) return DSES_E_INVAL;
+    delete srv;
+    return DSES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+"""Batched registration and the serving loop: identical results alone and in the mix,
+graph replays, admission by memory, and oracle parity on sampled rotations."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_00115_amd import synth
+from parity import compare_records
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2502_00115_amd import dses  # noqa: E402
+
+
+def _small_c3(count=6, k=384, seed=0):
+    probs = synth.make_c3(seed, count=count)
+    for p in probs:
+        p.rotations = p.rotations[:k].copy()
+    return probs
+
+
+def _as_dict(p, **kw):
+    d = {"src": p.src, "tgt": p.tgt, "rotations": p.rotations, "eps": p.eps}
+    d.update(kw)
+    return d
+
+
+def _same(a, b):
+    assert a.rot_index == b.rot_index
+    assert a.error == b.error and a.inliers == b.inliers and a.votes == b.votes
+    np.testing.assert_array_equal(a.t, b.t)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_alone_bitwise(use_graph):
+    probs = _small_c3()
+    alone = [dses.register(p.src, p.tgt, p.rotations, p.eps, records=True) for p in probs]
+    got, st = dses.register_batch([_as_dict(p) for p in probs], use_graph=use_graph,
+                                  records=True)
+    assert st == [0] * len(probs)
+    for a, b in zip(alone, got):
+        _same(a, b)
+        assert a.records.tobytes() == b.records.tobytes()
+
+
+def test_graph_replays_match_eager_every_time():
+    probs = _small_c3(count=5, k=256, seed=1)
+    eager = [dses.register(p.src, p.tgt, p.rotations, p.eps, records=True) for p in probs]
+    for rep in range(4):
+        got, st = dses.register_batch([_as_dict(p) for p in probs], use_graph=True, records=True)
+        assert st == [0] * len(probs)
+        for a, b in zip(eager, got):
+            assert a.records.tobytes() == b.records.tobytes(), f"replay {rep}"
+        # the program's own eager work between replays
+        x = dses.register(probs[rep].src, probs[rep].tgt, probs[rep].rotations, probs[rep].eps)
+        _same(x, eager[rep])
+        torch.cuda.synchronize()
+
+
+def test_batch_with_different_shapes_between_replays():
+    a = _small_c3(count=3, k=200, seed=2)
+    b = _small_c3(count=7, k=300, seed=3)
+    for probs in (a, b, a):
+        eager = [dses.register(p.src, p.tgt, p.rotations, p.eps) for p in probs]
+        got, st = dses.register_batch([_as_dict(p) for p in probs], use_graph=True)
+        assert st == [0] * len(probs)
+        for x, y in zip(eager, got):
+            _same(x, y)
+
+
+def test_batch_resident_and_device_inputs():
+    probs = _small_c3(count=4, k=256, seed=4)
+    T = [dses.Target(p.tgt) for p in probs]
+    S = [dses.RotationSet(p.rotations) for p in probs]
+    alone = [dses.register(p.src, p.tgt, p.rotations, p.eps) for p in probs]
+    got, st = dses.register_batch([{"src": p.src, "target": t, "rotset": s, "eps": p.eps}
+                                   for p, t, s in zip(probs, T, S)])
+    assert st == [0] * len(probs)
+    for x, y in zip(alone, got):
+        _same(x, y)
+    dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    got2, st2 = dses.register_batch([{"src": dev(p.src), "tgt": dev(p.tgt),
+                                      "rotations": dev(p.rotations), "eps": p.eps}
+                                     for p in probs])
+    assert st2 == [0] * len(probs)
+    for x, y in zip(alone, got2):
+        _same(x, y)
+
+
+def test_batch_reports_bad_problem_and_runs_the_rest():
+    probs = _small_c3(count=3, k=128, seed=5)
+    bad = probs[1].src.copy()
+    bad[0, 0] = np.nan
+    items = [_as_dict(probs[0]), _as_dict(probs[1], src=bad), _as_dict(probs[2])]
+    got, st = dses.register_batch(items)
+    assert st[0] == 0 and st[2] == 0 and st[1] == dses.DSES_E_INVAL
+    _same(got[0], dses.register(probs[0].src, probs[0].tgt, probs[0].rotations, probs[0].eps))
+    _same(got[2], dses.register(probs[2].src, probs[2].tgt, probs[2].rotations, probs[2].eps))
+
+
+def test_batch_parity_with_oracle_on_sampled_rotations():
+    probs = synth.make_c3(6, count=4)
+    got, st = dses.register_batch([_as_dict(p) for p in probs], records=True)
+    assert st == [0] * len(probs)
+    rng = np.random.default_rng(1)
+    for p, g in zip(probs, got):
+        which = np.sort(rng.choice(len(p.rotations), 48, replace=False))
+        ref = oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which)
+        compare_records(g.records[which], ref, len(p.src), label=p.name)
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+def _serving_setup(n_targets=2, n_req=6, k=512, seed=0):
+    rng = np.random.default_rng(seed)
+    tg = synth.make_c4_targets(seed, count=n_targets)
+    rots = synth.hopf_grid(3)[rng.permutation(36864)[:k]].reshape(-1, 9).astype(np.float32)
+    targets = [dses.Target(t) for t, _ in tg]
+    rotset = dses.RotationSet(rots)
+    reqs = []
+    for i in range(n_req):
+        tid, src = synth.make_c4_request(100 + i, tg)
+        reqs.append((tid, src[: 300 + 97 * i]))
+    return targets, rotset, rots, reqs
+
+
+def test_server_results_equal_alone():
+    targets, rotset, rots, reqs = _serving_setup()
+    alone = [dses.register_resident(targets[t], rotset, src, 0.03) for t, src in reqs]
+    srv = dses.Server()
+    ids = [srv.submit(targets[t], rotset, src, 0.03) for t, src in reqs]
+    for rid, a in zip(ids, alone):
+        _same(srv.wait(rid, timeout_ms=60000), a)
+    # a second wave arriving while the first is still on the device
+    ids = [srv.submit(targets[t], rotset, src, 0.03) for t, src in reqs[:3]]
+    ids += [srv.submit(targets[t], rotset, src, 0.03) for t, src in reqs[3:]]
+    for rid, a in zip(ids, alone):
+        _same(srv.wait(rid, timeout_ms=60000), a)
+    srv.close()
+
+
+def test_server_memory_admission_serialises_when_budget_fits_one():
+    targets, rotset, rots, reqs = _serving_setup(n_req=3, k=256, seed=1)
+    # a request needs 12 N + 24 K bytes (rounded); budget fits exactly one at a time
+    need = max(((12 * len(s) + 255) // 256) * 256 + ((24 * 256 + 255) // 256) * 256
+               for _, s in reqs)
+    srv = dses.Server(memory_budget=need + 256)
+    ids = [srv.submit(targets[t], rotset, src, 0.03) for t, src in reqs]
+    res = [srv.wait(r, timeout_ms=60000) for r in ids]
+    for (t, src), got in zip(reqs, res):
+        _same(got, dses.register_resident(targets[t], rotset, src, 0.03))
+    timing = [srv.timing(r) for r in ids]
+    # requests were admitted one after another: each later one waited in the queue
+    for (q0, tot0), (q1, _) in zip(timing, timing[1:]):
+        assert q1 >= q0
+    assert timing[-1][0] > 0.0
+    srv.close()
+
+
+def test_server_rejects_requests_larger_than_the_budget():
+    targets, rotset, _, reqs = _serving_setup(n_req=1, k=256, seed=2)
+    srv = dses.Server(memory_budget=4096)
+    with pytest.raises(dses.DsesError) as e:
+        srv.submit(targets[0], rotset, reqs[0][1], 0.03)
+    assert e.value.status == dses.DSES_E_NOMEM
+    with pytest.raises(dses.DsesError) as e:
+        srv.wait(12345, timeout_ms=0)
+    assert e.value.status == dses.DSES_E_STATE
+    srv.close()
+
+
+def test_server_poll_and_timeout():
+    targets, rotset, _, reqs = _serving_setup(n_req=1, k=2048, seed=3)
+    srv = dses.Server()
+    rid = srv.submit(targets[0], rotset, reqs[0][1], 0.03)
+    assert srv.poll(rid) in (0, 1)
+    got = srv.wait(rid, timeout_ms=60000)
+    assert srv.poll(rid) == 1
+    assert got.rot_index >= 0
+    q, tot = srv.timing(rid)
+    assert 0.0 <= q <= tot
+    srv.close()
+
+
+def test_server_many_concurrent_clients():
+    import threading
+    targets, rotset, _, reqs = _serving_setup(n_targets=2, n_req=8, k=384, seed=4)
+    alone = [dses.register_resident(targets[t], rotset, src, 0.03) for t, src in reqs]
+    srv = dses.Server()
+    out = [None] * len(reqs)
+
+    def client(i):
+        t, src = reqs[i]
+        time.sleep(0.002 * i)
+        out[i] = srv.wait(srv.submit(targets[t], rotset, src, 0.03), timeout_ms=60000)
+
+    th = [threading.Thread(target=client, args=(i,)) for i in range(len(reqs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for a, b in zip(alone, out):
+        _same(a, b)
+    srv.close()

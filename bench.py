@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3          # MI355X published FP32 vector peak
-WORKLOADS = ("c2", "c1", "c5")
+WORKLOADS = ("c2", "c1", "c5", "c3", "c4")
 
 
 def kernel_source_sha():
@@ -72,6 +72,117 @@ def cpu_baseline(p, sample, threads):
                       f"(seeded), full vote + brute-force FP64 scoring, {dt:.1f} s wall"}
 
 
+def bench_batch(args):
+    """64 registrations of uneven sizes: one batched persistent launch (HIP graph)
+    versus 64 plain single-registration launches, same device-resident inputs."""
+    import numpy as np
+    import torch
+    from paper_2502_00115_amd import dses, synth
+
+    probs = synth.make_c3(0, count=64)
+    dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    items = [{"src": dev(p.src), "tgt": dev(p.tgt), "rotations": dev(p.rotations), "eps": p.eps}
+             for p in probs]
+    cands = sum(len(p.rotations) for p in probs)
+    for _ in range(max(1, args.warmup)):
+        dses.register_batch(items, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res, st = dses.register_batch(items, use_graph=True)
+    torch.cuda.synchronize()
+    batched = (time.perf_counter() - t0) / args.steps
+    assert all(v == 0 for v in st)
+    t0 = time.perf_counter()
+    plain = [dses.register(it["src"], it["tgt"], it["rotations"], it["eps"]) for it in items]
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    same = all(a.rot_index == b.rot_index and a.error == b.error for a, b in zip(plain, res))
+    return {"metric": "candidate poses {R,t} scored/sec (1 GPU), batched",
+            "value": cands / batched, "unit": "candidates/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": batched * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "64 registrations, M 512-4096 log-uniform, N 30-80% cut, "
+                                   "K 4,608-36,864 rotations, one persistent launch replayed "
+                                   "from a HIP graph", "candidates": cands},
+            "plain": {"value": cands / plain_s, "ms_total": plain_s * 1e3,
+                      "path": "64 sequential dses_register calls"},
+            "identical_to_plain": bool(same)}
+
+
+def bench_serve(args):
+    """Poisson arrivals against 8 resident references (with 128^3 distance fields):
+    served (continuous batching) versus one launch per request in FIFO order."""
+    import threading
+
+    import numpy as np
+    import torch
+    from paper_2502_00115_amd import dses, synth
+
+    n_req = args.requests
+    targets = synth.make_c4_targets(0, count=8)
+    T = [dses.Target(t, df_trunc=0.03, df_res=128) for t, _ in targets]
+    R = dses.RotationSet(synth.hopf_grid(3).reshape(-1, 9).astype(np.float32))
+    reqs = [synth.make_c4_request(i, targets) for i in range(n_req + 8)]
+    for tid, src in reqs[:8]:                       # warm-up (staging caches, code objects)
+        dses.register_resident(T[tid], R, src, 0.03)
+    reqs = reqs[8:]
+    # capacity of the plain path fixes the arrival rate
+    t0 = time.perf_counter()
+    for tid, src in reqs[:16]:
+        dses.register_resident(T[tid], R, src, 0.03)
+    mean_service = (time.perf_counter() - t0) / 16
+    rate = 0.8 / mean_service
+    rng = np.random.default_rng(0)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+
+    # plain: one launch per request, FIFO, same arrival times
+    lat_plain = []
+    start = time.perf_counter()
+    for (tid, src), at in zip(reqs, arrivals):
+        now = time.perf_counter() - start
+        if now < at:
+            time.sleep(at - now)
+        dses.register_resident(T[tid], R, src, 0.03)
+        lat_plain.append(time.perf_counter() - start - at)
+    plain_wall = time.perf_counter() - start
+
+    # served
+    srv = dses.Server()
+    ids = [None] * n_req
+    start = time.perf_counter()
+
+    def producer():
+        for i, ((tid, src), at) in enumerate(zip(reqs, arrivals)):
+            now = time.perf_counter() - start
+            if now < at:
+                time.sleep(at - now)
+            ids[i] = srv.submit(T[tid], R, src, 0.03)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    for rid in ids:
+        srv.wait(rid, timeout_ms=600000)
+    served_wall = time.perf_counter() - start
+    lat_served = [srv.timing(rid)[1] for rid in ids]
+    srv.close()
+    cands = 36864 * n_req
+    pct = lambda a, q: float(np.percentile(np.array(a) * 1e3, q))  # noqa: E731
+    return {"metric": "registration latency p50/p99, served vs plain (1 GPU)",
+            "value": cands / served_wall, "unit": "candidates/s", "n_gpus": 1,
+            "steps": n_req, "warmup": 8, "ms_per_step": served_wall / n_req * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"{n_req} Poisson requests (rate 0.8x plain capacity = "
+                                   f"{rate:.2f}/s) vs 8 resident references with 128^3 "
+                                   "distance fields, 36,864 rotations each, DF scoring"},
+            "served": {"p50_ms": pct(lat_served, 50), "p99_ms": pct(lat_served, 99),
+                       "throughput": cands / served_wall},
+            "plain": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
+                      "throughput": cands / plain_wall, "path": "one launch per request, FIFO"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,11 +192,30 @@ def main():
     ap.add_argument("--scorer", default="auto")
     ap.add_argument("--cpu-sample", type=int, default=6144,
                     help="rotations the CPU oracle sweeps for the baseline (0: skip)")
+    ap.add_argument("--requests", type=int, default=200, help="c4: measured requests")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain elementwise copy of 256 MiB (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.add(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "torch.add(a, 1.0, out=b)", "bytes_read": 4 * a.numel(),
+                          "bytes_written": 4 * b.numel()}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the sweep shards by rotation, see DESIGN.md.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c3":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
+    if args.workload == "c4":
+        print(json.dumps(bench_serve(args)), flush=True)
+        return
 
     import numpy as np
     import torch

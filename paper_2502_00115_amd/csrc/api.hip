@@ -468,33 +468,8 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     if (scorer == DSES_SCORER_GRID) {
         const TargetRes *t = job.target;
         if (t) {
-            auto *tm = const_cast<TargetRes *>(t);
-            std::lock_guard<std::mutex> lk(tm->grid_mu);
-            if (tm->grid_r != p.r) {
-                HostGrid hg;
-                if ((st = build_grid(tm->host_aos.data(), tm->m, p.r, &hg)) != DSES_OK) return st;
-                if (tm->grid_pts) (void)hipFree(tm->grid_pts);
-                if (tm->grid_start) (void)hipFree(tm->grid_start);
-                tm->grid_pts = nullptr;
-                tm->grid_start = nullptr;
-                DSES_HIP(hipMalloc(&tm->grid_pts, hg.pts.size() * sizeof(float)));
-                DSES_HIP(hipMalloc(&tm->grid_start, hg.start.size() * sizeof(int32_t)));
-                DSES_HIP(hipMemcpy(tm->grid_pts, hg.pts.data(), hg.pts.size() * sizeof(float),
-                                   hipMemcpyHostToDevice));
-                DSES_HIP(hipMemcpy(tm->grid_start, hg.start.data(),
-                                   hg.start.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-                hg.pts.clear();
-                hg.start.clear();
-                tm->grid_meta = hg;
-                tm->grid_r = p.r;
-            }
-            a.grid.pts = tm->grid_pts;
-            a.grid.start = tm->grid_start;
-            for (int q = 0; q < 3; ++q) {
-                a.grid.lo[q] = tm->grid_meta.lo[q];
-                a.grid.dim[q] = tm->grid_meta.dim[q];
-            }
-            a.grid.inv = tm->grid_meta.inv;
+            if ((st = ensure_target_grid(const_cast<TargetRes *>(t), p.r, &a.grid)) != DSES_OK)
+                return st;
         } else {
             HostGrid hg;
             if ((st = build_grid(ht, job.m, p.r, &hg)) != DSES_OK) return st;

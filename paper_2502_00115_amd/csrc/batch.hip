@@ -284,34 +284,15 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
                                                     &x.tab_lo);
         if (x.scorer == DSES_SCORER_GRID) {
             if (T) {
-                auto *tm = const_cast<TargetRes *>(T);
-                std::lock_guard<std::mutex> gl(tm->grid_mu);
-                if (tm->grid_r != x.p.r) {
-                    HostGrid hg;
-                    if ((st = build_grid(ht, x.m, x.p.r, &hg)) != DSES_OK) { x.status = st; continue; }
-                    if (tm->grid_pts) (void)hipFree(tm->grid_pts);
-                    if (tm->grid_start) (void)hipFree(tm->grid_start);
-                    tm->grid_pts = nullptr;
-                    tm->grid_start = nullptr;
-                    if (hipMalloc(&tm->grid_pts, hg.pts.size() * sizeof(float)) != hipSuccess ||
-                        hipMalloc(&tm->grid_start, hg.start.size() * sizeof(int32_t)) != hipSuccess ||
-                        hipMemcpy(tm->grid_pts, hg.pts.data(), hg.pts.size() * sizeof(float),
-                                  hipMemcpyHostToDevice) != hipSuccess ||
-                        hipMemcpy(tm->grid_start, hg.start.data(),
-                                  hg.start.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice) != hipSuccess) {
-                        (void)hipGetLastError();
-                        fail(DSES_E_NOMEM, "cell grid upload failed");
-                        continue;
-                    }
-                    hg.pts.clear();
-                    hg.start.clear();
-                    tm->grid_meta = hg;
-                    tm->grid_r = x.p.r;
+                CellGrid cg{};
+                if ((st = ensure_target_grid(const_cast<TargetRes *>(T), x.p.r, &cg)) != DSES_OK) {
+                    x.status = st;
+                    continue;
                 }
-                x.grid = tm->grid_meta;
-                x.grid_pts = tm->grid_pts;
-                x.grid_start = tm->grid_start;
+                x.grid_pts = cg.pts;
+                x.grid_start = cg.start;
+                for (int q = 0; q < 3; ++q) { x.grid.lo[q] = cg.lo[q]; x.grid.dim[q] = cg.dim[q]; }
+                x.grid.inv = cg.inv;
             } else if ((st = build_grid(ht, x.m, x.p.r, &x.grid)) != DSES_OK) {
                 x.status = st;
                 continue;

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <deque>
 #include <cstdint>
 #include <memory>
 #include <mutex>
@@ -101,19 +102,26 @@ struct TargetRes {
     int32_t df_res = 0;
     float df_r = 0.0f;
     float df_lo[3] = {0, 0, 0}, df_h[3] = {0, 0, 0}, df_inv[3] = {0, 0, 0};
-    // cached x-sorted order and cell grid (for one r)
+    // Caches, guarded by grid_mu.  Entries are never freed before the target is
+    // destroyed: kernels of the serving loop may still read an older entry.
     std::mutex grid_mu;
-    std::vector<int32_t> perm_x;
-    // cached staged copy for one (delta, box) -- used by the serving loop
-    float st_delta = -1.0f;
-    int32_t st_klo[3] = {0, 0, 0};
-    float *st_ys = nullptr, *st_yt = nullptr;
-    int32_t *st_perm = nullptr, *st_tab = nullptr;
-    int32_t st_tab_lo = 0, st_tab_n = 0;
-    float grid_r = -1.0f;
-    float *grid_pts = nullptr;
-    int32_t *grid_start = nullptr;
-    HostGrid grid_meta;
+    std::vector<int32_t> perm_x;             // reference order sorted by x
+    int32_t *d_perm = nullptr;
+    struct Stage {                           // staged copy for one (delta, box)
+        float delta;
+        int32_t klo[3];
+        float *ys, *yt;
+        int32_t *tab;
+        int32_t tab_lo, tab_n;
+    };
+    std::deque<Stage> stages;                // deque: references survive push_back
+    struct Grid {                            // cell grid for one radius
+        float r;
+        float *pts;
+        int32_t *start;
+        HostGrid meta;
+    };
+    std::deque<Grid> grids;
 };
 
 struct RotRes {
@@ -143,7 +151,8 @@ void add_stats(Context *c, double vote_ms, double score_ms, double select_ms, do
 
 // Stage a resident target for lattice pitch p.delta / box p.klo (cached; holds
 // tm->grid_mu while building; synchronous on `stream`).
-dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stream);
+dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stream,
+                                const TargetRes::Stage **out);
 // Build (or reuse) the resident target's cell grid for radius r; fills cg.
 dses_status ensure_target_grid(TargetRes *tm, float r, CellGrid *cg);
 

@@ -24,69 +24,76 @@ static dses_status copy_to_host(const float *p, size_t count, bool dev, std::vec
 dses_status ensure_target_grid(TargetRes *tm, float r, CellGrid *cg)
 {
     std::lock_guard<std::mutex> gl(tm->grid_mu);
-    if (tm->grid_r != r) {
-        HostGrid hg;
-        dses_status st = build_grid(tm->host_aos.data(), tm->m, r, &hg);
+    const TargetRes::Grid *hit = nullptr;
+    for (const auto &g : tm->grids)
+        if (g.r == r) hit = &g;
+    if (!hit) {
+        TargetRes::Grid g{r, nullptr, nullptr, HostGrid{}};
+        dses_status st = build_grid(tm->host_aos.data(), tm->m, r, &g.meta);
         if (st != DSES_OK) return st;
-        if (tm->grid_pts) (void)hipFree(tm->grid_pts);
-        if (tm->grid_start) (void)hipFree(tm->grid_start);
-        tm->grid_pts = nullptr;
-        tm->grid_start = nullptr;
-        tm->grid_r = -1.0f;
-        DSES_HIP(hipMalloc(&tm->grid_pts, hg.pts.size() * sizeof(float)));
-        DSES_HIP(hipMalloc(&tm->grid_start, hg.start.size() * sizeof(int32_t)));
-        DSES_HIP(hipMemcpy(tm->grid_pts, hg.pts.data(), hg.pts.size() * sizeof(float),
-                           hipMemcpyHostToDevice));
-        DSES_HIP(hipMemcpy(tm->grid_start, hg.start.data(), hg.start.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice));
-        hg.pts.clear();
-        hg.start.clear();
-        tm->grid_meta = hg;
-        tm->grid_r = r;
+        if (hipMalloc(&g.pts, g.meta.pts.size() * sizeof(float)) != hipSuccess ||
+            hipMalloc(&g.start, g.meta.start.size() * sizeof(int32_t)) != hipSuccess ||
+            hipMemcpy(g.pts, g.meta.pts.data(), g.meta.pts.size() * sizeof(float),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(g.start, g.meta.start.data(), g.meta.start.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            if (g.pts) (void)hipFree(g.pts);
+            if (g.start) (void)hipFree(g.start);
+            set_error("cell grid upload failed");
+            return DSES_E_NOMEM;
+        }
+        g.meta.pts.clear();
+        g.meta.pts.shrink_to_fit();
+        g.meta.start.clear();
+        g.meta.start.shrink_to_fit();
+        tm->grids.push_back(g);
+        hit = &tm->grids.back();
     }
     if (cg) {
-        cg->pts = tm->grid_pts;
-        cg->start = tm->grid_start;
+        cg->pts = hit->pts;
+        cg->start = hit->start;
         for (int q = 0; q < 3; ++q) {
-            cg->lo[q] = tm->grid_meta.lo[q];
-            cg->dim[q] = tm->grid_meta.dim[q];
+            cg->lo[q] = hit->meta.lo[q];
+            cg->dim[q] = hit->meta.dim[q];
         }
-        cg->inv = tm->grid_meta.inv;
+        cg->inv = hit->meta.inv;
     }
     return DSES_OK;
 }
 
-dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stream)
+dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stream,
+                                const TargetRes::Stage **out)
 {
     std::lock_guard<std::mutex> gl(tm->grid_mu);
-    if (tm->st_delta == p.delta && tm->st_klo[0] == p.klo[0] && tm->st_klo[1] == p.klo[1] &&
-        tm->st_klo[2] == p.klo[2])
-        return DSES_OK;
+    for (const auto &st : tm->stages)
+        if (st.delta == p.delta && st.klo[0] == p.klo[0] && st.klo[1] == p.klo[1] &&
+            st.klo[2] == p.klo[2]) {
+            *out = &st;
+            return DSES_OK;
+        }
     const size_t m = (size_t)tm->m;
     if (tm->perm_x.empty()) sort_by_x(tm->host_aos.data(), tm->m, &tm->perm_x);
+    if (!tm->d_perm) {
+        DSES_HIP(hipMalloc(&tm->d_perm, 4 * m));
+        DSES_HIP(hipMemcpy(tm->d_perm, tm->perm_x.data(), 4 * m, hipMemcpyHostToDevice));
+    }
     std::vector<int32_t> tab;
     int32_t tab_lo = 0;
     const float s = 1.0f / p.delta;
     const bool sorted = build_x_table(tm->host_aos.data(), tm->perm_x, s, p.klo[0], &tab, &tab_lo);
-    for (void *q : {(void *)tm->st_ys, (void *)tm->st_yt, (void *)tm->st_perm, (void *)tm->st_tab})
-        if (q) (void)hipFree(q);
-    tm->st_ys = tm->st_yt = nullptr;
-    tm->st_perm = tm->st_tab = nullptr;
-    tm->st_delta = -1.0f;
-    DSES_HIP(hipMalloc(&tm->st_ys, 12 * m));
-    DSES_HIP(hipMalloc(&tm->st_yt, 12 * m));
-    DSES_HIP(hipMalloc(&tm->st_perm, 4 * m));
-    DSES_HIP(hipMemcpy(tm->st_perm, tm->perm_x.data(), 4 * m, hipMemcpyHostToDevice));
+    TargetRes::Stage st{p.delta, {p.klo[0], p.klo[1], p.klo[2]}, nullptr, nullptr, nullptr,
+                        tab_lo, sorted ? (int32_t)tab.size() : 0};
+    DSES_HIP(hipMalloc(&st.ys, 12 * m));
+    DSES_HIP(hipMalloc(&st.yt, 12 * m));
     if (sorted) {
-        DSES_HIP(hipMalloc(&tm->st_tab, 4 * tab.size()));
-        DSES_HIP(hipMemcpy(tm->st_tab, tab.data(), 4 * tab.size(), hipMemcpyHostToDevice));
+        DSES_HIP(hipMalloc(&st.tab, 4 * tab.size()));
+        DSES_HIP(hipMemcpy(st.tab, tab.data(), 4 * tab.size(), hipMemcpyHostToDevice));
     }
-    DSES_HIP(launch_stage(tm->aos, tm->st_perm, tm->m, s, p.klo, tm->st_ys, tm->st_yt, stream));
+    DSES_HIP(launch_stage(tm->aos, tm->d_perm, tm->m, s, p.klo, st.ys, st.yt, stream));
     DSES_HIP(hipStreamSynchronize(stream));
-    tm->st_tab_lo = tab_lo;
-    tm->st_tab_n = sorted ? (int32_t)tab.size() : 0;
-    for (int a = 0; a < 3; ++a) tm->st_klo[a] = p.klo[a];
-    tm->st_delta = p.delta;
+    tm->stages.push_back(st);
+    *out = &tm->stages.back();
     return DSES_OK;
 }
 
@@ -194,13 +201,17 @@ dses_status dses_target_destroy(dses_target *t)
 {
     if (!t) return DSES_E_INVAL;
     TargetRes &T = t->res;
-    for (void *q : {(void *)T.st_ys, (void *)T.st_yt, (void *)T.st_perm, (void *)T.st_tab})
-        if (q) (void)hipFree(q);
+    for (auto &st : T.stages)
+        for (void *q : {(void *)st.ys, (void *)st.yt, (void *)st.tab})
+            if (q) (void)hipFree(q);
+    for (auto &g : T.grids) {
+        if (g.pts) (void)hipFree(g.pts);
+        if (g.start) (void)hipFree(g.start);
+    }
+    if (T.d_perm) (void)hipFree(T.d_perm);
     if (T.aos) (void)hipFree(T.aos);
     if (T.yt) (void)hipFree(T.yt);
     if (T.df) (void)hipFree(T.df);
-    if (T.grid_pts) (void)hipFree(T.grid_pts);
-    if (T.grid_start) (void)hipFree(T.grid_start);
     delete t;
     return DSES_OK;
 }

@@ -241,7 +241,8 @@ dses_status ServerImpl::prepare(Request *r)
     Geom g;
     dses_status st = plan_geom(c, r->p, r->n, r->m, bits, &g);
     if (st != DSES_OK) return st;
-    if ((st = ensure_target_stage(tm, r->p, stream)) != DSES_OK) return st;
+    const TargetRes::Stage *stg = nullptr;
+    if ((st = ensure_target_stage(tm, r->p, stream, &stg)) != DSES_OK) return st;
     CellGrid cg{};
     if (r->scorer == DSES_SCORER_GRID && (st = ensure_target_grid(tm, r->p.r, &cg)) != DSES_OK)
         return st;
@@ -255,12 +256,12 @@ dses_status ServerImpl::prepare(Request *r)
     a = SweepArgs{};
     a.src = d_src;
     a.rot = r->rots->rot;
-    a.ys = tm->st_ys;
-    a.yt = tm->st_yt;
-    const bool sorted = r->n <= kSortMax && tm->st_tab_n > 0;
-    a.tab = sorted ? tm->st_tab : nullptr;
-    a.tab_lo = tm->st_tab_lo;
-    a.tab_n = sorted ? tm->st_tab_n : 0;
+    a.ys = stg->ys;
+    a.yt = stg->yt;
+    const bool sorted = r->n <= kSortMax && stg->tab_n > 0;
+    a.tab = sorted ? stg->tab : nullptr;
+    a.tab_lo = stg->tab_lo;
+    a.tab_n = sorted ? stg->tab_n : 0;
     a.scratch = sorted ? d_scratch : nullptr;
     a.scratch_stride = kServeMaxSrc;
     a.g = g;

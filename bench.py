@@ -148,7 +148,7 @@ def bench_serve(args):
     plain_wall = time.perf_counter() - start
 
     # served
-    srv = dses.Server()
+    srv = dses.Server(aging=args.aging)
     ids = [None] * n_req
     start = time.perf_counter()
 
@@ -176,7 +176,8 @@ def bench_serve(args):
             "data": "synthetic",
             "config": {"workload": f"{n_req} Poisson requests (rate 0.8x plain capacity = "
                                    f"{rate:.2f}/s) vs 8 resident references with 128^3 "
-                                   "distance fields, 36,864 rotations each, DF scoring"},
+                                   "distance fields, 36,864 rotations each, DF scoring",
+                       "aging": args.aging},
             "served": {"p50_ms": pct(lat_served, 50), "p99_ms": pct(lat_served, 99),
                        "throughput": cands / served_wall},
             "plain": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
@@ -193,6 +194,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6144,
                     help="rotations the CPU oracle sweeps for the baseline (0: skip)")
     ap.add_argument("--requests", type=int, default=200, help="c4: measured requests")
+    ap.add_argument("--aging", type=float, default=0.0,
+                    help="c4: server priority aging (0: library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain elementwise copy of 256 MiB (counter calibration)")
     args = ap.parse_args()

@@ -260,6 +260,11 @@ typedef struct {
     int64_t memory_budget;    /* bytes of per-request device memory in flight (0: 1 GiB) */
     int32_t max_inflight;     /* requests on the device at once (0: 64)               */
     int32_t scorer;           /* dses_scorer for every request                         */
+    float aging;              /* scheduling: a request's priority is its estimated
+                                 remaining GPU time minus aging x its age (smallest
+                                 first); 0 -> 1.0, < 0 -> 0 (shortest remaining work
+                                 first), very large -> first come first served        */
+    int32_t reserved;
 } dses_server_opts;
 
 dses_status dses_server_create(const dses_server_opts *opt, dses_server **out);

@@ -122,7 +122,7 @@ static dses_status enqueue_batch(BatchState *b, int scorer, int grid, hipStream_
     DSES_HIP(launch_batch_aux(static_cast<StageDesc *>(b->stage.ptr), nullptr, header,
                               b->cap_count, 0, stream));
     BatchArgs ba{static_cast<SweepArgs *>(b->inst.ptr), static_cast<BatchItem *>(b->items.ptr),
-                 header, cursor};
+                 header, cursor, nullptr};
     DSES_HIP(launch_sweep_batch(ba, scorer, grid, stream));
     DSES_HIP(launch_batch_aux(nullptr, static_cast<SelectDesc *>(b->sel.ptr), header,
                               b->cap_count, 1, stream));

@@ -80,6 +80,8 @@ struct BatchArgs {
     const BatchItem *items;    // work list, most expensive first
     const int32_t *header;     // header[0] = items, header[1] = instances
     uint32_t *cursor;          // work-list cursor, cleared before each launch
+    float4 *scratch;           // if set: this launch's source-sort scratch (overrides
+                               // the instances' own, so concurrent launches never share)
 };
 
 struct StageDesc {

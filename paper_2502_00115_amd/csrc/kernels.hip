@@ -755,7 +755,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchArgs b)
         __syncthreads();
         if (it >= n_items) break;
         const BatchItem w = kload(b.items + it);
-        const SweepArgs a = kload(b.inst + w.inst);
+        SweepArgs a = kload(b.inst + w.inst);
+        if (b.scratch && a.scratch) a.scratch = b.scratch;
         for (int k = w.k0; k < w.k1; ++k) {
             if (a.g.counter_bits == 16)
                 sweep_one<16, SCORER>(a, k, lds, blockIdx.x);

@@ -7,10 +7,12 @@
 //    time, so admission never calls hipMalloc/hipFree) and an instance slot is
 //    free;
 //  * continuous batching: the GPU runs a sequence of short persistent launches
-//    ("slices") of the batched sweep kernel.  Each slice's work list takes
-//    rotation tiles from every request on the device, shortest remaining work
-//    first, so requests that arrive while others run join the next slice and
-//    their rotations overlap on the device with the older requests';
+//    ("slices") of the batched sweep kernel, alternating between two streams so
+//    one slice's tail overlaps the next slice's start.  Each slice's work list
+//    takes rotation tiles from the requests on the device in priority order
+//    (estimated remaining GPU time minus `aging` x time since submission), so
+//    requests that arrive while others run join the next slice and their
+//    rotations overlap on the device with the older requests';
 //  * a request whose last tile is in a slice is selected at the end of that
 //    slice; its result is copied back and its memory returned to the pool.
 // Each rotation runs the same sweep_one() as a lone registration, so a request's
@@ -105,8 +107,12 @@ struct SliceSet {
     SelectDesc *h_sel = nullptr;             // pinned
     int32_t *h_header = nullptr;             // pinned
     void *d_items = nullptr, *d_sel = nullptr, *d_header = nullptr, *d_cursor = nullptr;
+    float4 *d_scratch = nullptr;             // source-sort scratch of this slice's launch
     hipEvent_t done = nullptr;
+    hipStream_t stream = nullptr;            // stream the slice ran on
     bool busy = false;
+    double pairs = 0.0;
+    Clock::time_point t_launch;
     std::vector<Request *> finishing;
 };
 
@@ -115,14 +121,18 @@ struct SliceSet {
 struct ServerImpl {
     Context *c = nullptr;
     dses_server_opts opt{};
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;            // admission work and even slices
+    hipStream_t stream2 = nullptr;           // odd slices
+    hipEvent_t last_slice = nullptr;         // the most recently launched slice
+    bool have_last = false;
+    uint64_t n_slices = 0;
+    double rate = 5.0e11;                    // estimated sweep rate, pairs per second
     void *pool_mem = nullptr;
     Pool pool;
     int max_slots = 0;
     SweepArgs *d_args = nullptr;             // one per slot
     DevResult *d_res = nullptr, *h_res = nullptr;
     uint32_t *d_status = nullptr;
-    float4 *d_scratch = nullptr;
     float *h_stage = nullptr;                // pinned per-slot source staging
     SliceSet sets[kSliceSets];
     int grid = 0;
@@ -161,10 +171,13 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     opt = o;
     if (opt.memory_budget <= 0) opt.memory_budget = (int64_t)1 << 30;
     if (opt.max_inflight <= 0) opt.max_inflight = 64;
+    if (opt.aging == 0.0f) opt.aging = 1.0f;
+    if (opt.aging < 0.0f) opt.aging = 0.0f;
     max_slots = opt.max_inflight;
     grid = std::max(1, c->n_cu);
     slice_pairs = 6.0e9;            // about 2-6 ms of sweep work per slice
     DSES_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    DSES_HIP(hipStreamCreateWithFlags(&stream2, hipStreamNonBlocking));
     if (hipMalloc(&pool_mem, (size_t)opt.memory_budget) != hipSuccess) {
         (void)hipGetLastError();
         set_error("cannot reserve the serving memory budget on the device");
@@ -175,7 +188,6 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     DSES_HIP(hipMalloc(&d_res, max_slots * sizeof(DevResult)));
     DSES_HIP(hipMalloc(&d_status, max_slots * sizeof(uint32_t)));
     DSES_HIP(hipMemset(d_status, 0, max_slots * sizeof(uint32_t)));
-    DSES_HIP(hipMalloc(&d_scratch, (size_t)grid * kServeMaxSrc * sizeof(float4)));
     void *p = nullptr;
     DSES_HIP(hipHostMalloc(&p, max_slots * sizeof(DevResult), hipHostMallocDefault));
     h_res = static_cast<DevResult *>(p);
@@ -192,6 +204,7 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
         DSES_HIP(hipMalloc(&s.d_sel, max_slots * sizeof(SelectDesc)));
         DSES_HIP(hipMalloc(&s.d_header, 64));
         DSES_HIP(hipMalloc(&s.d_cursor, 64));
+        DSES_HIP(hipMalloc(&s.d_scratch, (size_t)grid * kServeMaxSrc * sizeof(float4)));
         DSES_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
     }
     for (int i = max_slots - 1; i >= 0; --i) free_slots.push_back(i);
@@ -208,7 +221,9 @@ ServerImpl::~ServerImpl()
     cv_work.notify_all();
     if (worker.joinable()) worker.join();
     if (stream) (void)hipStreamSynchronize(stream);
+    if (stream2) (void)hipStreamSynchronize(stream2);
     for (auto &s : sets) {
+        if (s.d_scratch) (void)hipFree(s.d_scratch);
         if (s.h_items) (void)hipHostFree(s.h_items);
         if (s.h_sel) (void)hipHostFree(s.h_sel);
         if (s.h_header) (void)hipHostFree(s.h_header);
@@ -223,9 +238,9 @@ ServerImpl::~ServerImpl()
     if (d_args) (void)hipFree(d_args);
     if (d_res) (void)hipFree(d_res);
     if (d_status) (void)hipFree(d_status);
-    if (d_scratch) (void)hipFree(d_scratch);
     if (pool_mem) (void)hipFree(pool_mem);
     if (stream) (void)hipStreamDestroy(stream);
+    if (stream2) (void)hipStreamDestroy(stream2);
     for (auto &kv : all) delete kv.second;
 }
 
@@ -262,7 +277,7 @@ dses_status ServerImpl::prepare(Request *r)
     a.tab = sorted ? stg->tab : nullptr;
     a.tab_lo = stg->tab_lo;
     a.tab_n = sorted ? stg->tab_n : 0;
-    a.scratch = sorted ? d_scratch : nullptr;
+    a.scratch = sorted ? reinterpret_cast<float4 *>(1) : nullptr;   // per-slice scratch at launch
     a.scratch_stride = kServeMaxSrc;
     a.g = g;
     a.grid = cg;
@@ -323,9 +338,15 @@ bool ServerImpl::launch_slice()
     for (Request *r : active)
         if (r->next_k < r->k) order.push_back(r);
     if (order.empty()) return false;
-    std::stable_sort(order.begin(), order.end(), [](const Request *a, const Request *b) {
-        return (a->k - a->next_k) * a->pair_cost < (b->k - b->next_k) * b->pair_cost;
-    });
+    const auto now = Clock::now();
+    const double aging = opt.aging;
+    auto prio = [&](const Request *r) {
+        const double remaining = (r->k - r->next_k) * r->pair_cost / rate;
+        const double age = std::chrono::duration<double>(now - r->t_submit).count();
+        return remaining - aging * age;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](const Request *a, const Request *b) { return prio(a) < prio(b); });
     const int scorer = order.front()->scorer;      // one kernel instantiation per slice
     int n_items = 0, n_sel = 0;
     double budget = slice_pairs;
@@ -351,25 +372,45 @@ bool ServerImpl::launch_slice()
     }
     s->h_header[0] = n_items;
     s->h_header[1] = n_sel;
+    s->pairs = slice_pairs - budget;
+    s->t_launch = Clock::now();
     mu.unlock();
     bool ok = true;
     auto chk = [&](hipError_t e) { if (e != hipSuccess) { ok = false; fatal = hipGetErrorString(e); } };
-    chk(hipMemcpyAsync(s->d_items, s->h_items, n_items * sizeof(BatchItem), hipMemcpyHostToDevice, stream));
-    chk(hipMemcpyAsync(s->d_sel, s->h_sel, std::max(1, n_sel) * sizeof(SelectDesc), hipMemcpyHostToDevice, stream));
-    chk(hipMemcpyAsync(s->d_header, s->h_header, 8, hipMemcpyHostToDevice, stream));
-    chk(launch_clear(static_cast<uint32_t *>(s->d_cursor), 1, stream));
+    // slices alternate between the two streams; admission uploads were issued on
+    // `stream`, so the odd stream first waits for them
+    hipStream_t st = (n_slices & 1) ? stream2 : stream;
+    hipEvent_t uploads = nullptr;
+    if (st == stream2) {
+        chk(hipEventCreateWithFlags(&uploads, hipEventDisableTiming));
+        chk(hipEventRecord(uploads, stream));
+        chk(hipStreamWaitEvent(stream2, uploads, 0));
+    }
+    chk(hipMemcpyAsync(s->d_items, s->h_items, n_items * sizeof(BatchItem), hipMemcpyHostToDevice, st));
+    chk(hipMemcpyAsync(s->d_sel, s->h_sel, std::max(1, n_sel) * sizeof(SelectDesc), hipMemcpyHostToDevice, st));
+    chk(hipMemcpyAsync(s->d_header, s->h_header, 8, hipMemcpyHostToDevice, st));
+    chk(launch_clear(static_cast<uint32_t *>(s->d_cursor), 1, st));
     BatchArgs ba{d_args, static_cast<BatchItem *>(s->d_items),
-                 static_cast<int32_t *>(s->d_header), static_cast<uint32_t *>(s->d_cursor)};
-    chk(launch_sweep_batch(ba, scorer, grid, stream));
+                 static_cast<int32_t *>(s->d_header), static_cast<uint32_t *>(s->d_cursor),
+                 s->d_scratch};
+    chk(launch_sweep_batch(ba, scorer, grid, st));
     if (n_sel > 0) {
+        // a finishing request's earlier tiles may sit in the previous slice on the
+        // other stream: select only after that slice is complete too
+        if (have_last) chk(hipStreamWaitEvent(st, last_slice, 0));
         chk(launch_batch_aux(nullptr, static_cast<SelectDesc *>(s->d_sel),
-                             static_cast<int32_t *>(s->d_header), n_sel, 1, stream));
+                             static_cast<int32_t *>(s->d_header), n_sel, 1, st));
         for (Request *r : s->finishing)
             chk(hipMemcpyAsync(h_res + r->slot, d_res + r->slot, sizeof(DevResult),
-                               hipMemcpyDeviceToHost, stream));
+                               hipMemcpyDeviceToHost, st));
     }
-    chk(hipEventRecord(s->done, stream));
+    chk(hipEventRecord(s->done, st));
+    if (uploads) chk(hipEventDestroy(uploads));
+    last_slice = s->done;
+    have_last = true;
+    ++n_slices;
     mu.lock();
+    s->stream = st;
     s->busy = true;
     return ok;
 }
@@ -403,6 +444,9 @@ void ServerImpl::poll_slices()
             r->src.clear();
             r->src.shrink_to_fit();
         }
+        const double dt = std::chrono::duration<double>(Clock::now() - s.t_launch).count();
+        if (dt > 1e-4 && s.pairs > 0.0)
+            rate = 0.8 * rate + 0.2 * std::min(4.0e12, std::max(1.0e10, s.pairs / dt));
         s.finishing.clear();
         s.busy = false;
         cv_done.notify_all();

@@ -14,7 +14,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "host.h"
@@ -45,6 +47,7 @@ struct Prepared {
     size_t off_src = 0, off_tgt = 0, off_rot = 0, off_ys = 0, off_yt = 0, off_perm = 0,
            off_tab = 0, off_rec = 0, off_gpts = 0, off_gstart = 0;
     void *records = nullptr;
+    bool ready = false;
 };
 
 size_t bump(size_t &cursor, size_t bytes)
@@ -201,7 +204,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
     int batch_scorer = -1;
     int32_t max_n = 1;
     size_t arena_bytes = 0;
-    for (int i = 0; i < count; ++i) {
+    auto prepare_one = [&](int i) {
         const dses_problem &q = probs[i];
         Prepared &x = P[i];
         auto fail = [&](dses_status s, const char *msg) {
@@ -214,11 +217,11 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         if (!q.src || q.n <= 0 || m <= 0 || k <= 0 || (!T && !q.tgt) ||
             (!q.rotset && !q.rotations) || q.n * m >= ((int64_t)1 << 31) || k > INT32_MAX) {
             fail(DSES_E_INVAL, "invalid problem sizes or pointers");
-            continue;
+            return;
         }
         dses_status st = resolve_params(q.eps, q.metric, q.delta_t, q.tau, q.t_min, q.t_max,
                                         o.scorer, &x.p);
-        if (st != DSES_OK) { x.status = st; continue; }
+        if (st != DSES_OK) { x.status = st; return; }
         x.n = (int32_t)q.n;
         x.m = (int32_t)m;
         x.k = (int32_t)k;
@@ -227,11 +230,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         if (x.scorer == DSES_SCORER_DF &&
             (!T || !T->df || T->df_r != x.p.r || x.p.metric == DSES_TRUNC_L1)) {
             fail(DSES_E_INVAL, "DF scorer needs a resident target with a matching field");
-            continue;
-        }
-        if (batch_scorer >= 0 && x.scorer != batch_scorer) {
-            fail(DSES_E_INVAL, "all problems of a batch must use the same scorer");
-            continue;
+            return;
         }
         // host view of the reference
         const float *ht = nullptr;
@@ -245,7 +244,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
                           hipMemcpyDeviceToHost) != hipSuccess) {
                 (void)hipGetLastError();
                 fail(DSES_E_DEVICE, "reading the reference back failed");
-                continue;
+                return;
             }
             ht = x.tgt_copy.data();
         }
@@ -266,11 +265,11 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
             }
         if (!ok) {
             fail(DSES_E_INVAL, "non-finite or out-of-range coordinate, or non-orthonormal rotation");
-            continue;
+            return;
         }
         x.host_tgt = ht;
         const int bits = counter_bound(ht, x.m, x.n, x.p) <= 65535 ? 16 : 32;
-        if ((st = plan_geom(c, x.p, x.n, x.m, bits, &x.g)) != DSES_OK) { x.status = st; continue; }
+        if ((st = plan_geom(c, x.p, x.n, x.m, bits, &x.g)) != DSES_OK) { x.status = st; return; }
         if (T) {
             auto *tm = const_cast<TargetRes *>(T);
             std::lock_guard<std::mutex> gl(tm->grid_mu);
@@ -287,7 +286,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
                 CellGrid cg{};
                 if ((st = ensure_target_grid(const_cast<TargetRes *>(T), x.p.r, &cg)) != DSES_OK) {
                     x.status = st;
-                    continue;
+                    return;
                 }
                 x.grid_pts = cg.pts;
                 x.grid_start = cg.start;
@@ -295,9 +294,33 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
                 x.grid.inv = cg.inv;
             } else if ((st = build_grid(ht, x.m, x.p.r, &x.grid)) != DSES_OK) {
                 x.status = st;
-                continue;
+                return;
             }
         }
+        x.ready = true;
+    };
+    {
+        const int nt = std::max(1, std::min<int>(count, std::min<int>(16,
+                                 (int)std::thread::hardware_concurrency())));
+        std::vector<std::thread> pool;
+        std::atomic<int> next{0};
+        for (int w = 0; w < nt; ++w)
+            pool.emplace_back([&] {
+                (void)hipSetDevice(c->device);
+                for (int i = next++; i < count; i = next++) prepare_one(i);
+            });
+        for (auto &t : pool) t.join();
+    }
+    for (int i = 0; i < count; ++i) {
+        const dses_problem &q = probs[i];
+        Prepared &x = P[i];
+        if (x.status != DSES_OK) continue;
+        if (batch_scorer >= 0 && x.scorer != batch_scorer) {
+            x.status = DSES_E_INVAL;
+            set_error("all problems of a batch must use the same scorer");
+            continue;
+        }
+        const TargetRes *T = x.target;
         batch_scorer = x.scorer;
         max_n = std::max(max_n, x.n);
         // arena layout

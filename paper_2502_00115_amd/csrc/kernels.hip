@@ -206,26 +206,49 @@ __device__ __forceinline__ ChunkLayout chunk_layout(int c0, int n, int wave, int
     return L;
 }
 
-// One pair's vote.  c* are the box-relative bin coordinates; the x range check is
-// against the current slab [x0, x0 + np).  Byte address in LDS:
-//   16-bit: ((cx - x0) * Sy + cy) * row_words * 4 + (cz >> 1) * 4, half = cz & 1
-//   32-bit: ((cx - x0) * Sy + cy) * Sz * 4 + cz * 4
+// One pair's vote.  c* are box-relative bin coordinates; the x range check is
+// against the current slab [x0, x0 + np).  LDS byte address (16-bit counters):
+//   ((cx - x0) * Sy + cy) * row_words * 4 + (cz >> 1) * 4, half = cz & 1
+// (32-bit: ((cx - x0) * Sy + cy) * Sz * 4 + cz * 4).
+// The 16-bit path is one asm block: three v_cmpx narrow EXEC to the in-box lanes,
+// the address arithmetic and the ds_add_u32 run on those lanes only, and EXEC is
+// restored.  Compared with a compiler-generated branch this removes the per-pair
+// VALU -> SALU -> branch round trip (v_cmp, s_and, s_and_saveexec, s_cbranch,
+// s_or), which left the vector ALU idle about half of the time.
 template <int CW>
 __device__ __forceinline__ void vote_pair(uint32_t *hist, int cx, int cy, int cz, int x0,
                                           uint32_t np, uint32_t Sy, uint32_t Sz, uint32_t sx4,
                                           uint32_t sy4, uint32_t negc)
 {
+    if (CW == 16) {
+        const uint32_t base =
+            negc + (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t *)hist;
+        uint64_t save;
+        uint32_t t0, t1, t2;
+        asm volatile(
+            "s_mov_b64 %[save], exec\n\t"
+            "v_subrev_u32 %[t0], %[x0], %[cx]\n\t"
+            "v_cmpx_gt_u32 vcc, %[np], %[t0]\n\t"
+            "v_cmpx_gt_u32 vcc, %[sy], %[cy]\n\t"
+            "v_cmpx_gt_u32 vcc, %[sz], %[cz]\n\t"
+            "v_lshrrev_b32 %[t1], 1, %[cz]\n\t"
+            "v_lshl_add_u32 %[t1], %[t1], 2, %[base]\n\t"
+            "v_mad_u32_u24 %[t1], %[cy], %[sy4], %[t1]\n\t"
+            "v_mad_u32_u24 %[t1], %[cx], %[sx4], %[t1]\n\t"
+            "v_lshlrev_b32 %[t2], 4, %[cz]\n\t"
+            "v_lshlrev_b32_e64 %[t2], %[t2], 1\n\t"
+            "ds_add_u32 %[t1], %[t2]\n\t"
+            "s_mov_b64 exec, %[save]"
+            : [save] "=&s"(save), [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2)
+            : [cx] "v"(cx), [cy] "v"(cy), [cz] "v"(cz), [x0] "s"(x0), [np] "s"(np),
+              [sy] "s"(Sy), [sz] "s"(Sz), [sx4] "s"(sx4), [sy4] "s"(sy4), [base] "s"(base)
+            : "vcc", "memory");
+        return;
+    }
     if ((uint32_t)(cx - x0) < np && (uint32_t)cy < Sy && (uint32_t)cz < Sz) {
-        if (CW == 16) {
-            const uint32_t zb = lshl2_add((uint32_t)cz >> 1, negc);
-            const uint32_t addr = mad24((uint32_t)cx, sx4, mad24((uint32_t)cy, sy4, zb));
-            atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(hist) + addr),
-                      1u << (((uint32_t)cz << 4) & 31u));
-        } else {
-            const uint32_t zb = lshl2_add((uint32_t)cz, negc);
-            const uint32_t addr = mad24((uint32_t)cx, sx4, mad24((uint32_t)cy, sy4, zb));
-            atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(hist) + addr), 1u);
-        }
+        const uint32_t zb = lshl2_add((uint32_t)cz, negc);
+        const uint32_t addr = mad24((uint32_t)cx, sx4, mad24((uint32_t)cy, sy4, zb));
+        atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(hist) + addr), 1u);
     }
 }
 
@@ -313,6 +336,7 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             vote_pair<CW>(hist, cvt_flr(ysx[j] - Px), cvt_flr(ysy[j] - Py), cvt_flr(ysz[j] - Pz),
                           x0, (uint32_t)np, Sy, Sz, sx4, sy4, negc);
     }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // asm-issued LDS atomics
 }
 
 // Bucket-sort the rotated, scaled source points of one rotation by x into this

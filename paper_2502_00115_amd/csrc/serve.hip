@@ -23,6 +23,8 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <list>
@@ -121,7 +123,9 @@ struct SliceSet {
 struct ServerImpl {
     Context *c = nullptr;
     dses_server_opts opt{};
-    hipStream_t stream = nullptr;            // admission work and even slices
+    hipStream_t up = nullptr;                // admission uploads and staging
+    hipEvent_t up_done = nullptr;            // recorded after every admission's uploads
+    hipStream_t stream = nullptr;            // even slices
     hipStream_t stream2 = nullptr;           // odd slices
     hipEvent_t last_slice = nullptr;         // the most recently launched slice
     bool have_last = false;
@@ -148,6 +152,11 @@ struct ServerImpl {
     bool stop = false;
     std::thread worker;
     std::string fatal;
+    // optional trace (environment DSES_SERVE_TRACE=<file>): one line per finished
+    // slice and per finished request, times in seconds since the server started
+    FILE *trace = nullptr;
+    Clock::time_point t0 = Clock::now();
+    double since(Clock::time_point t) const { return std::chrono::duration<double>(t - t0).count(); }
 
     dses_status init(Context *ctx, const dses_server_opts &o);
     void run();
@@ -176,8 +185,11 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     max_slots = opt.max_inflight;
     grid = std::max(1, c->n_cu);
     slice_pairs = 6.0e9;            // about 2-6 ms of sweep work per slice
+    DSES_HIP(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
     DSES_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     DSES_HIP(hipStreamCreateWithFlags(&stream2, hipStreamNonBlocking));
+    DSES_HIP(hipEventCreateWithFlags(&up_done, hipEventDisableTiming));
+    DSES_HIP(hipEventRecord(up_done, up));
     if (hipMalloc(&pool_mem, (size_t)opt.memory_budget) != hipSuccess) {
         (void)hipGetLastError();
         set_error("cannot reserve the serving memory budget on the device");
@@ -208,6 +220,8 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
         DSES_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
     }
     for (int i = max_slots - 1; i >= 0; --i) free_slots.push_back(i);
+    if (const char *tp = std::getenv("DSES_SERVE_TRACE")) trace = std::fopen(tp, "w");
+    t0 = Clock::now();
     worker = std::thread([this] { run(); });
     return DSES_OK;
 }
@@ -220,8 +234,10 @@ ServerImpl::~ServerImpl()
     }
     cv_work.notify_all();
     if (worker.joinable()) worker.join();
+    if (up) (void)hipStreamSynchronize(up);
     if (stream) (void)hipStreamSynchronize(stream);
     if (stream2) (void)hipStreamSynchronize(stream2);
+    if (up_done) (void)hipEventDestroy(up_done);
     for (auto &s : sets) {
         if (s.d_scratch) (void)hipFree(s.d_scratch);
         if (s.h_items) (void)hipHostFree(s.h_items);
@@ -239,9 +255,11 @@ ServerImpl::~ServerImpl()
     if (d_res) (void)hipFree(d_res);
     if (d_status) (void)hipFree(d_status);
     if (pool_mem) (void)hipFree(pool_mem);
+    if (up) (void)hipStreamDestroy(up);
     if (stream) (void)hipStreamDestroy(stream);
     if (stream2) (void)hipStreamDestroy(stream2);
     for (auto &kv : all) delete kv.second;
+    if (trace) std::fclose(trace);
 }
 
 // Device preparation of an admitted request (scheduler thread; the request owns
@@ -257,7 +275,7 @@ dses_status ServerImpl::prepare(Request *r)
     dses_status st = plan_geom(c, r->p, r->n, r->m, bits, &g);
     if (st != DSES_OK) return st;
     const TargetRes::Stage *stg = nullptr;
-    if ((st = ensure_target_stage(tm, r->p, stream, &stg)) != DSES_OK) return st;
+    if ((st = ensure_target_stage(tm, r->p, up, &stg)) != DSES_OK) return st;
     CellGrid cg{};
     if (r->scorer == DSES_SCORER_GRID && (st = ensure_target_grid(tm, r->p.r, &cg)) != DSES_OK)
         return st;
@@ -289,9 +307,9 @@ dses_status ServerImpl::prepare(Request *r)
     }
     a.rec = r->d_rec;
     a.k = r->k;
-    DSES_HIP(hipMemcpyAsync(d_src, stage, 12 * (size_t)r->n, hipMemcpyHostToDevice, stream));
-    DSES_HIP(hipMemcpyAsync(d_args + r->slot, &a, sizeof(SweepArgs), hipMemcpyHostToDevice,
-                            stream));
+    DSES_HIP(hipMemcpyAsync(d_src, stage, 12 * (size_t)r->n, hipMemcpyHostToDevice, up));
+    DSES_HIP(hipMemcpyAsync(d_args + r->slot, &a, sizeof(SweepArgs), hipMemcpyHostToDevice, up));
+    DSES_HIP(hipEventRecord(up_done, up));
     return DSES_OK;
 }
 
@@ -377,15 +395,10 @@ bool ServerImpl::launch_slice()
     mu.unlock();
     bool ok = true;
     auto chk = [&](hipError_t e) { if (e != hipSuccess) { ok = false; fatal = hipGetErrorString(e); } };
-    // slices alternate between the two streams; admission uploads were issued on
-    // `stream`, so the odd stream first waits for them
+    // slices alternate between two streams so one slice's tail overlaps the next;
+    // each first waits for the admission uploads issued so far (on `up`)
     hipStream_t st = (n_slices & 1) ? stream2 : stream;
-    hipEvent_t uploads = nullptr;
-    if (st == stream2) {
-        chk(hipEventCreateWithFlags(&uploads, hipEventDisableTiming));
-        chk(hipEventRecord(uploads, stream));
-        chk(hipStreamWaitEvent(stream2, uploads, 0));
-    }
+    chk(hipStreamWaitEvent(st, up_done, 0));
     chk(hipMemcpyAsync(s->d_items, s->h_items, n_items * sizeof(BatchItem), hipMemcpyHostToDevice, st));
     chk(hipMemcpyAsync(s->d_sel, s->h_sel, std::max(1, n_sel) * sizeof(SelectDesc), hipMemcpyHostToDevice, st));
     chk(hipMemcpyAsync(s->d_header, s->h_header, 8, hipMemcpyHostToDevice, st));
@@ -405,7 +418,6 @@ bool ServerImpl::launch_slice()
                                hipMemcpyDeviceToHost, st));
     }
     chk(hipEventRecord(s->done, st));
-    if (uploads) chk(hipEventDestroy(uploads));
     last_slice = s->done;
     have_last = true;
     ++n_slices;
@@ -438,13 +450,21 @@ void ServerImpl::poll_slices()
             }
             r->state = Request::DONE;
             r->t_done = Clock::now();
+            if (trace)
+                std::fprintf(trace, "R %llu %d %d %d %.6f %.6f %.6f\n",
+                             (unsigned long long)r->id, r->n, r->m, r->k, since(r->t_submit),
+                             since(r->t_admit), since(r->t_done));
             pool.release(r->off, r->bytes);
             free_slots.push_back(r->slot);
             active.erase(std::remove(active.begin(), active.end(), r), active.end());
             r->src.clear();
             r->src.shrink_to_fit();
         }
-        const double dt = std::chrono::duration<double>(Clock::now() - s.t_launch).count();
+        const auto now = Clock::now();
+        if (trace)
+            std::fprintf(trace, "S %d %.6f %.6f %.0f %zu\n", s.stream == stream2 ? 1 : 0,
+                         since(s.t_launch), since(now), s.pairs, s.finishing.size());
+        const double dt = std::chrono::duration<double>(now - s.t_launch).count();
         if (dt > 1e-4 && s.pairs > 0.0)
             rate = 0.8 * rate + 0.2 * std::min(4.0e12, std::max(1.0e10, s.pairs / dt));
         s.finishing.clear();

@@ -25,9 +25,13 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3          # MI355X published FP32 vector peak
 WORKLOADS = ("c2", "c1", "c5", "c3", "c4")
 
 
+# sources that decide what the plain-path sweep launch reads and writes
+SWEEP_SOURCES = ("api.hip", "internal.h", "kernels.hip")
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
-    for name in sorted(os.listdir(os.path.join(ROOT, "paper_2502_00115_amd", "csrc"))):
+    for name in SWEEP_SOURCES:
         with open(os.path.join(ROOT, "paper_2502_00115_amd", "csrc", name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -150,7 +154,7 @@ def bench_serve(args):
     plain_wall = time.perf_counter() - start
 
     # served
-    srv = dses.Server(aging=args.aging)
+    srv = dses.Server(aging=args.aging, slice_mpairs=args.slice_mpairs)
     ids = [None] * n_req
     start = time.perf_counter()
 
@@ -172,6 +176,12 @@ def bench_serve(args):
     queue_served = [t[0] for t in tim]
     srv.close()
     cands = 36864 * n_req
+    if args.latency_dump:
+        with open(args.latency_dump, "w") as f:
+            json.dump({"arrival_s": [float(a) for a in arrivals], "plain_s": lat_plain,
+                       "served_s": lat_served, "plain_service_s": svc_plain,
+                       "n": [len(s) for _, s in reqs[:n_req]],
+                       "m": [T[t].m for t, _ in reqs[:n_req]]}, f)
     pct = lambda a, q: float(np.percentile(np.array(a) * 1e3, q))  # noqa: E731
     return {"metric": "registration latency p50/p99, served vs plain (1 GPU)",
             "value": cands / served_wall, "unit": "candidates/s", "n_gpus": 1,
@@ -181,7 +191,7 @@ def bench_serve(args):
             "config": {"workload": f"{n_req} Poisson requests (rate 0.8x plain capacity = "
                                    f"{rate:.2f}/s) vs 8 resident references with 128^3 "
                                    "distance fields, 36,864 rotations each, DF scoring",
-                       "aging": args.aging},
+                       "aging": args.aging, "slice_mpairs": args.slice_mpairs},
             "served": {"p50_ms": pct(lat_served, 50), "p99_ms": pct(lat_served, 99),
                        "mean_ms": float(np.mean(lat_served)) * 1e3,
                        "mean_admission_wait_ms": float(np.mean(queue_served)) * 1e3,
@@ -204,6 +214,10 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="c4: measured requests")
     ap.add_argument("--aging", type=float, default=0.0,
                     help="c4: server priority aging (0: library default)")
+    ap.add_argument("--latency-dump", default=None,
+                    help="c4: write per-request arrival, plain and served latency (JSON)")
+    ap.add_argument("--slice-mpairs", type=int, default=0,
+                    help="c4: server work per slice, millions of pairs (0: library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain elementwise copy of 256 MiB (counter calibration)")
     args = ap.parse_args()

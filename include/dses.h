@@ -264,7 +264,8 @@ typedef struct {
                                  remaining GPU time minus aging x its age (smallest
                                  first); 0 -> 1.0, < 0 -> 0 (shortest remaining work
                                  first), very large -> first come first served        */
-    int32_t reserved;
+    int32_t slice_mpairs;     /* work per slice (one batched launch), in millions of
+                                 rotated point pairs; 0 -> 6000                        */
 } dses_server_opts;
 
 dses_status dses_server_create(const dses_server_opts *opt, dses_server **out);

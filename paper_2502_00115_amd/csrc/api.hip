@@ -350,11 +350,11 @@ bool build_x_table(const float *tgt, const std::vector<int32_t> &perm, float s, 
     const double hi = std::floor((double)ysx.back());
     if (!(hi - lo < (double)(1 << 20))) return false;
     *tab_lo = (int32_t)lo;
-    const size_t n = (size_t)(hi - lo) + 2;
+    const size_t n = (size_t)kTabPerBin * ((size_t)(hi - lo) + 1) + 1;
     tab->resize(n);
     size_t j = 0;
     for (size_t q = 0; q < n; ++q) {
-        const float v = (float)(lo + (double)q);
+        const float v = (float)(lo + (double)q / kTabPerBin);
         while (j < m && ysx[j] < v) ++j;
         (*tab)[q] = (int32_t)j;
     }

@@ -76,7 +76,8 @@ dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, i
 int64_t counter_bound(const float *tgt_aos, int32_t m, int32_t n, const Params &p);
 
 // Reference order sorted by x, and the table tab[q] = first sorted index whose scaled
-// x coordinate is >= tab_lo + q (false if the coordinate range is too wide).
+// x coordinate is >= tab_lo + q / kTabPerBin (false if the coordinate range is too
+// wide).
 void sort_by_x(const float *tgt_aos, int32_t m, std::vector<int32_t> *perm);
 bool build_x_table(const float *tgt_aos, const std::vector<int32_t> &perm, float s, int32_t klo_x,
                    std::vector<int32_t> *tab, int32_t *tab_lo);

@@ -51,13 +51,14 @@ struct Field {
 
 constexpr int kSortBuckets = 1024;      // per-rotation source buckets (1 bin unit wide)
 constexpr int kSortMax = 16384;         // largest source cloud that is bucket-sorted
+constexpr int kTabPerBin = 4;           // x-table entries per bin (reference windows)
 
 struct SweepArgs {
     const float *src;      // n x 3 AoS
     const float *rot;      // K x 9
     const float *ys;       // scaled + offset reference, SoA (3 * m), sorted by x
     const float *yt;       // reference, SoA (3 * m), same order
-    const int32_t *tab;    // tab[q] = first j with ys_x[j] >= tab_lo + q, q < tab_n
+    const int32_t *tab;    // tab[q] = first j with ys_x[j] >= tab_lo + q / kTabPerBin, q < tab_n
     int32_t tab_lo, tab_n;
     float4 *scratch;       // per workgroup slot: n rotated scaled sources, bucket-sorted by x
     int64_t scratch_stride;   // float4 entries per slot (>= n)

@@ -252,6 +252,50 @@ __device__ __forceinline__ void vote_pair(uint32_t *hist, int cx, int cy, int cz
     }
 }
 
+typedef uint32_t f4u __attribute__((ext_vector_type(4)));
+
+// Buffer resource over the staged reference (x, y, z arrays of m floats); loads
+// past its end return zero instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t ref_rsrc(const float *ys, int m)
+{
+    // word 3: 32-bit data format, no swizzle (raw buffer)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(ys), 0, 12 * m, 0x00020000);
+}
+
+// Reference points j .. j+3 (x, y, z): three 16-byte loads, the same address on
+// every lane.
+__device__ __forceinline__ void ref_load4(__amdgpu_buffer_rsrc_t rs, int m, int j, f4u &x, f4u &y,
+                                          f4u &z)
+{
+    x = __builtin_amdgcn_raw_buffer_load_b128(rs, 0, 4 * j, 0);
+    y = __builtin_amdgcn_raw_buffer_load_b128(rs, 0, 4 * (m + j), 0);
+    z = __builtin_amdgcn_raw_buffer_load_b128(rs, 0, 4 * (2 * m + j), 0);
+}
+
+// One float of the staged reference (index into the x, y, z arrays).
+__device__ __forceinline__ float ref_load1(__amdgpu_buffer_rsrc_t rs, int i)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 0, 4 * i, 0));
+}
+
+// Votes of one source point (per lane) against four reference points.
+template <int CW>
+__device__ __forceinline__ void vote4(uint32_t *hist, f4u x, f4u y, f4u z, float Px, float Py,
+                                      float Pz, int x0, uint32_t np, uint32_t Sy, uint32_t Sz,
+                                      uint32_t sx4, uint32_t sy4, uint32_t negc)
+{
+    int cx[4], cy[4], cz[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        cx[q] = cvt_flr(__uint_as_float(x[q]) - Px);
+        cy[q] = cvt_flr(__uint_as_float(y[q]) - Py);
+        cz[q] = cvt_flr(__uint_as_float(z[q]) - Pz);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        vote_pair<CW>(hist, cx[q], cy[q], cz[q], x0, np, Sy, Sz, sx4, sy4, negc);
+}
+
 __device__ __forceinline__ float wave_min(float v)
 {
     for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
@@ -264,16 +308,35 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
+// Parts per 64-source group so that sw groups x G parts spread evenly over the
+// kWaves waves (fewest parts among the best spreads; at most 8).
+__device__ __forceinline__ int vote_parts(int sw)
+{
+    int best = 1, best_num = sw, best_den = kWaves * ((sw + kWaves - 1) / kWaves);
+    for (int G = 2; G <= 8; ++G) {
+        const int num = sw * G, den = kWaves * ((num + kWaves - 1) / kWaves);
+        if (num * best_den > best_num * den) { best = G; best_num = num; best_den = den; }
+    }
+    return best;
+}
+
 // Reference index range [lo, hi) of the x-sorted reference whose pairs with any
 // source of x coordinate in [pmin, pmax] can fall in box x-planes [x0, x1):
-// floor(Y - P) in [x0, x1) implies Y in [P + x0, P + x1), widened by one bin on
-// each side for float rounding.  The per-pair x test stays exact.
+// floor(Y - P) in [x0, x1) implies Y in [P + x0, P + x1), widened by a margin that
+// exceeds the float rounding of Y - P and of the bounds; the table has kTabPerBin
+// entries per bin.  The per-pair x test stays exact, so the window only has to
+// contain every voting pair.
 __device__ __forceinline__ void ref_window(const SweepArgs &a, float pmin, float pmax, int x0,
                                            int x1, int &lo, int &hi)
 {
     const kint tab = kc(a.tab);
-    const int qlo = cvt_flr(pmin + (float)(x0 - 1)) - a.tab_lo;
-    const int qhi = cvt_flr(pmax + (float)(x1 + 1)) + 1 - a.tab_lo;
+    const float tl = (float)a.tab_lo;
+    // margin: 1/64 bin plus a bound on the float rounding of the sums below and of
+    // the per-pair subtraction (relative 2^-24 each, at most a few terms)
+    const float e = 0.015625f + 3.8e-6f * (fabsf(pmin) + fabsf(pmax) + fabsf((float)x0) +
+                                           fabsf((float)x1) + fabsf(tl));
+    const int qlo = cvt_flr((pmin + (float)x0 - tl - e) * (float)kTabPerBin);
+    const int qhi = cvt_flr((pmax + (float)x1 - tl + e) * (float)kTabPerBin) + 1;
     lo = qlo <= 0 ? 0 : (qlo >= a.tab_n ? a.g.m : tab[qlo]);
     hi = qhi <= 0 ? 0 : (qhi >= a.tab_n ? a.g.m : tab[qhi]);
 }
@@ -288,53 +351,69 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
     const uint32_t sy4 = 4u * (uint32_t)g.row_words, sx4 = sy4 * Sy;
     const uint32_t negc = 0u - (uint32_t)x0 * sx4;
     const int m = g.m;
-    const kfloat ysx = kc(a.ys), ysy = kc(a.ys + m), ysz = kc(a.ys + 2 * m);
+    const __amdgpu_buffer_rsrc_t rs = ref_rsrc(a.ys, m);
     const float4 *mine = a.scratch + (size_t)slot * a.scratch_stride;
     for (int c0 = 0; c0 < g.n; c0 += kBlock) {
-        const ChunkLayout L = chunk_layout(c0, g.n, wave, lane);
-        if (!L.active) continue;
-        float Px = 1.0e7f, Py = 1.0e7f, Pz = 1.0e7f;      // padding lanes never vote
-        if (L.i < g.n) {
+        // work units of this chunk: (64-source group, part of its reference window);
+        // the waves take units round-robin, so all kWaves vote even when the chunk
+        // has fewer than kWaves source groups
+        const int sw = (min(kBlock, g.n - c0) + 63) >> 6;
+        const int G = vote_parts(sw);
+        for (int u = wave; u < sw * G; u += kWaves) {
+            const int part = u / sw;
+            const int i = c0 + (u - part * sw) * 64 + lane;
+            float Px = 1.0e7f, Py = 1.0e7f, Pz = 1.0e7f;      // padding lanes never vote
+            if (i < g.n) {
+                if (sorted) {
+                    const float4 P = mine[i];
+                    Px = P.x;
+                    Py = P.y;
+                    Pz = P.z;
+                } else {
+                    float px, py, pz;
+                    rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
+                    Px = __fmul_rn(px, g.s);
+                    Py = __fmul_rn(py, g.s);
+                    Pz = __fmul_rn(pz, g.s);
+                }
+            }
+            int lo = 0, hi = m;
             if (sorted) {
-                const float4 P = mine[L.i];
-                Px = P.x;
-                Py = P.y;
-                Pz = P.z;
-            } else {
-                float px, py, pz;
-                rotate(R, a.src[3 * L.i], a.src[3 * L.i + 1], a.src[3 * L.i + 2], px, py, pz);
-                Px = __fmul_rn(px, g.s);
-                Py = __fmul_rn(py, g.s);
-                Pz = __fmul_rn(pz, g.s);
+                const bool real = i < g.n;
+                const float pmin = wave_min(real ? Px : INFINITY);
+                const float pmax = wave_max(real ? Px : -INFINITY);
+                ref_window(a, pmin, pmax, x0, x0 + np, lo, hi);
+                lo = uni(lo);
+                hi = uni(max(hi, lo));
+            }
+            const int j0 = uni(lo + (int)((int64_t)(hi - lo) * part / G));
+            const int j1 = uni(lo + (int)((int64_t)(hi - lo) * (part + 1) / G));
+            // reference coordinates come through the vector memory path (buffer
+            // loads, two 4-point groups in flight): scalar loads would share the
+            // LDS counter, and waiting for them would also wait for every
+            // outstanding ds_add of the wave
+            int j = j0;
+            if (j + 4 <= j1) {
+                f4u ax, ay, az, bx, by, bz;
+                ref_load4(rs, m, j, ax, ay, az);
+                for (; j + 8 <= j1; j += 8) {
+                    ref_load4(rs, m, j + 4, bx, by, bz);
+                    vote4<CW>(hist, ax, ay, az, Px, Py, Pz, x0, np, Sy, Sz, sx4, sy4, negc);
+                    ref_load4(rs, m, min(j + 8, j1 - 4), ax, ay, az);
+                    vote4<CW>(hist, bx, by, bz, Px, Py, Pz, x0, np, Sy, Sz, sx4, sy4, negc);
+                }
+                if (j + 4 <= j1) {
+                    vote4<CW>(hist, ax, ay, az, Px, Py, Pz, x0, np, Sy, Sz, sx4, sy4, negc);
+                    j += 4;
+                }
+            }
+            for (; j < j1; ++j) {
+                const float yx = ref_load1(rs, j), yy = ref_load1(rs, m + j);
+                const float yz = ref_load1(rs, 2 * m + j);
+                vote_pair<CW>(hist, cvt_flr(yx - Px), cvt_flr(yy - Py), cvt_flr(yz - Pz), x0,
+                              (uint32_t)np, Sy, Sz, sx4, sy4, negc);
             }
         }
-        int j0 = uni((int)((int64_t)m * L.part / L.G));
-        int j1 = uni((int)((int64_t)m * (L.part + 1) / L.G));
-        if (sorted) {
-            const bool real = L.i < g.n;
-            const float pmin = wave_min(real ? Px : INFINITY);
-            const float pmax = wave_max(real ? Px : -INFINITY);
-            int lo, hi;
-            ref_window(a, pmin, pmax, x0, x0 + np, lo, hi);
-            j0 = max(j0, uni(lo));
-            j1 = min(j1, uni(hi));
-        }
-        int j = j0;
-        for (; j + 4 <= j1; j += 4) {
-            int cx[4], cy[4], cz[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                cx[u] = cvt_flr(ysx[j + u] - Px);
-                cy[u] = cvt_flr(ysy[j + u] - Py);
-                cz[u] = cvt_flr(ysz[j + u] - Pz);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                vote_pair<CW>(hist, cx[u], cy[u], cz[u], x0, (uint32_t)np, Sy, Sz, sx4, sy4, negc);
-        }
-        for (; j < j1; ++j)
-            vote_pair<CW>(hist, cvt_flr(ysx[j] - Px), cvt_flr(ysy[j] - Py), cvt_flr(ysz[j] - Pz),
-                          x0, (uint32_t)np, Sy, Sz, sx4, sy4, negc);
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // asm-issued LDS atomics
 }

@@ -116,6 +116,7 @@ struct SliceSet {
     double pairs = 0.0;
     Clock::time_point t_launch;
     std::vector<Request *> finishing;
+    std::vector<uint64_t> carried;           // ids of the requests with tiles in the slice (trace)
 };
 
 }  // namespace
@@ -184,10 +185,16 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     if (opt.aging < 0.0f) opt.aging = 0.0f;
     max_slots = opt.max_inflight;
     grid = std::max(1, c->n_cu);
-    slice_pairs = 6.0e9;            // about 2-6 ms of sweep work per slice
+    slice_pairs = 1.0e6 * (opt.slice_mpairs > 0 ? opt.slice_mpairs : 6000);
     DSES_HIP(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
-    DSES_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
-    DSES_HIP(hipStreamCreateWithFlags(&stream2, hipStreamNonBlocking));
+    // The slice streams must sit on two different hardware queues: kernels of one
+    // queue never overlap, and streams created the ordinary way share a small
+    // pool of queues (two of them can land on the same one).  A stream created
+    // with a CU mask gets a queue of its own; the mask here covers every CU.
+    std::vector<uint32_t> cu_mask((size_t)(grid + 31) / 32, 0xffffffffu);
+    if (grid % 32) cu_mask.back() = (1u << (grid % 32)) - 1u;
+    DSES_HIP(hipExtStreamCreateWithCUMask(&stream, (uint32_t)cu_mask.size(), cu_mask.data()));
+    DSES_HIP(hipExtStreamCreateWithCUMask(&stream2, (uint32_t)cu_mask.size(), cu_mask.data()));
     DSES_HIP(hipEventCreateWithFlags(&up_done, hipEventDisableTiming));
     DSES_HIP(hipEventRecord(up_done, up));
     if (hipMalloc(&pool_mem, (size_t)opt.memory_budget) != hipSuccess) {
@@ -369,12 +376,15 @@ bool ServerImpl::launch_slice()
     int n_items = 0, n_sel = 0;
     double budget = slice_pairs;
     s->finishing.clear();
+    s->carried.clear();
     for (Request *r : order) {
         if (budget <= 0.0 || n_items >= kMaxSliceItems) break;
         if (r->scorer != scorer) continue;
         const double per_tile_target = std::max(1.0, slice_pairs / (4.0 * grid));
         const int32_t tile =
             (int32_t)std::max(1.0, std::min((double)r->k, per_tile_target / r->pair_cost));
+        if (trace && r->next_k < r->k && budget > 0.0 && n_items < kMaxSliceItems)
+            s->carried.push_back(r->id);
         while (r->next_k < r->k && budget > 0.0 && n_items < kMaxSliceItems) {
             const int32_t k0 = r->next_k, k1 = std::min(r->k, k0 + tile);
             s->h_items[n_items++] = BatchItem{r->slot, k0, k1, 0};
@@ -461,9 +471,12 @@ void ServerImpl::poll_slices()
             r->src.shrink_to_fit();
         }
         const auto now = Clock::now();
-        if (trace)
-            std::fprintf(trace, "S %d %.6f %.6f %.0f %zu\n", s.stream == stream2 ? 1 : 0,
+        if (trace) {
+            std::fprintf(trace, "S %d %.6f %.6f %.0f %zu", s.stream == stream2 ? 1 : 0,
                          since(s.t_launch), since(now), s.pairs, s.finishing.size());
+            for (uint64_t id : s.carried) std::fprintf(trace, " %llu", (unsigned long long)id);
+            std::fprintf(trace, "\n");
+        }
         const double dt = std::chrono::duration<double>(now - s.t_launch).count();
         if (dt > 1e-4 && s.pairs > 0.0)
             rate = 0.8 * rate + 0.2 * std::min(4.0e12, std::max(1.0e10, s.pairs / dt));
@@ -530,7 +543,7 @@ dses_status dses_server_create(const dses_server_opts *opt, dses_server **out)
     dses_server_opts o{};
     if (opt) o = *opt;
     if (o.memory_budget < 0 || o.max_inflight < 0 || o.max_inflight > 4096 ||
-        o.scorer < DSES_SCORER_AUTO || o.scorer > DSES_SCORER_DF) {
+        o.scorer < DSES_SCORER_AUTO || o.scorer > DSES_SCORER_DF || o.slice_mpairs < 0) {
         set_error("invalid server options");
         return DSES_E_INVAL;
     }

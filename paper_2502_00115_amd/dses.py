@@ -85,7 +85,7 @@ class BatchOpts(C.Structure):
 class ServerOpts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("flags", C.c_uint32),
                 ("memory_budget", C.c_int64), ("max_inflight", C.c_int32),
-                ("scorer", C.c_int32), ("aging", C.c_float), ("reserved", C.c_int32)]
+                ("scorer", C.c_int32), ("aging", C.c_float), ("slice_mpairs", C.c_int32)]
 
 
 RECORD_DTYPE = np.dtype([("bin", "<i4", (3,)), ("votes", "<u4"), ("inliers", "<i4"),
@@ -382,9 +382,10 @@ def register_batch(problems, *, scorer="auto", use_graph=True, tile_rot=0, recor
 class Server:
     """Continuous-batching registration server (dses_server_*)."""
 
-    def __init__(self, memory_budget=0, max_inflight=0, scorer="auto", aging=0.0):
+    def __init__(self, memory_budget=0, max_inflight=0, scorer="auto", aging=0.0,
+                 slice_mpairs=0):
         o = ServerOpts(C.sizeof(ServerOpts), 0, int(memory_budget), int(max_inflight),
-                       SCORERS[scorer], float(aging), 0)
+                       SCORERS[scorer], float(aging), int(slice_mpairs))
         h = C.c_void_p()
         _check(lib().dses_server_create(C.byref(o), C.byref(h)))
         self.handle = h

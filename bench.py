@@ -88,7 +88,19 @@ def bench_batch(args):
     items = [{"src": dev(p.src), "tgt": dev(p.tgt), "rotations": dev(p.rotations), "eps": p.eps}
              for p in probs]
     cands = sum(len(p.rotations) for p in probs)
-    for _ in range(max(1, args.warmup)):
+    # default layout, then one tuning call (its layout is kept for this batch class)
+    dses.register_batch(items, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dses.register_batch(items, use_graph=True)
+    torch.cuda.synchronize()
+    default_s = time.perf_counter() - t0
+    default_cfg = dses.batch_last_config()
+    t0 = time.perf_counter()
+    dses.register_batch(items, use_graph=True, autotune=True)
+    tune_s = time.perf_counter() - t0
+    tuned_cfg = dses.batch_last_config()
+    for _ in range(max(0, args.warmup - 1)):
         dses.register_batch(items, use_graph=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -96,6 +108,7 @@ def bench_batch(args):
         res, st = dses.register_batch(items, use_graph=True)
     torch.cuda.synchronize()
     batched = (time.perf_counter() - t0) / args.steps
+    layout = dses.batch_last_config()
     assert all(v == 0 for v in st)
     t0 = time.perf_counter()
     plain = [dses.register(it["src"], it["tgt"], it["rotations"], it["eps"]) for it in items]
@@ -111,6 +124,9 @@ def bench_batch(args):
                                    "from a HIP graph", "candidates": cands},
             "plain": {"value": cands / plain_s, "ms_total": plain_s * 1e3,
                       "path": "64 sequential dses_register calls"},
+            "layout": layout, "untuned": {"ms": default_s * 1e3, "layout": default_cfg},
+            "tuning": {"s": tune_s, "candidates": tuned_cfg["candidates"],
+                       "sweep_ms_best": tuned_cfg["sweep_ms"]},
             "identical_to_plain": bool(same)}
 
 
@@ -209,8 +225,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=WORKLOADS, default="c2")
     ap.add_argument("--scorer", default="auto")
-    ap.add_argument("--cpu-sample", type=int, default=6144,
-                    help="rotations the CPU oracle sweeps for the baseline (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=-1,
+                    help="rotations of the oracle CPU baseline (-1: as many as about "
+                         "2.2e10 point pairs, some 10 s on 16 cores; 0: skip)")
     ap.add_argument("--requests", type=int, default=200, help="c4: measured requests")
     ap.add_argument("--aging", type=float, default=0.0,
                     help="c4: server priority aging (0: library default)")
@@ -253,23 +270,40 @@ def main():
     rot = torch.from_numpy(p.rotations).to(dev)
     n, m, k = len(p.src), len(p.tgt), len(p.rotations)
 
+    if args.scorer == "df":
+        # distance-field scoring needs the reference resident with its 128^3 field
+        target = dses.Target(tgt, df_trunc=p.eps, df_res=128)
+        rotset = dses.RotationSet(rot)
+
+        def run(**kw):
+            return dses.register_resident(target, rotset, src, p.eps, scorer="df", **kw)
+    else:
+        def run(**kw):
+            return dses.register(src, tgt, rot, p.eps, scorer=args.scorer, **kw)
     for _ in range(args.warmup):
-        dses.register(src, tgt, rot, p.eps, scorer=args.scorer)
+        run()
     torch.cuda.synchronize()
     dses.kernel_stats(reset=True)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for step in range(args.steps):
         ts = time.perf_counter()
-        r = dses.register(src, tgt, rot, p.eps, scorer=args.scorer, timing=True)
+        r = run(timing=True)
         lat.append(time.perf_counter() - ts)
+        if lat[-1] > 5.0:
+            print(f"bench.py: step {step + 1}/{args.steps} {lat[-1]:.1f} s", file=sys.stderr,
+                  flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = dses.kernel_stats()
 
     sweep_ms = st["vote_score_ms"] / max(1, st["vote_score_launches"])
-    flop_per_launch = (11.0 * n * m + 18.0 * n) * k
+    # algorithmic work per candidate: 3 FLOP per vote pair, 8 per brute-force score pair,
+    # 18 per transformed point; distance-field scoring replaces the score pairs by
+    # one lookup per point
+    score_pairs = 0.0 if args.scorer == "df" else 8.0 * n * m
+    flop_per_launch = (3.0 * n * m + score_pairs + 18.0 * n) * k
     achieved = flop_per_launch / (sweep_ms * 1e-3) / 1e12
     traffic = load_traffic(args.workload)
     lat_ms = np.array(lat) * 1e3
@@ -293,13 +327,18 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_sweep (vote + mode + score)",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
-                     "work": "algorithmic (11*N*M + 18*N) FLOP per candidate",
+                     "work": ("algorithmic (3*N*M + 18*N) FLOP per candidate (DF scoring)"
+                              if args.scorer == "df" else
+                              "algorithmic (11*N*M + 18*N) FLOP per candidate"),
                      "kernel_ms": sweep_ms},
         "result": {"rot_index": r.rot_index, "inliers": r.inliers, "error": r.error},
     }
-    if args.cpu_sample > 0:
+    if args.cpu_sample != 0:
         threads = min(16, len(os.sched_getaffinity(0)))
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample, threads)
+        sample = args.cpu_sample if args.cpu_sample > 0 else max(16, int(2.2e10 / (n * m)))
+        print(f"bench.py: oracle CPU baseline on {min(sample, k)} rotations", file=sys.stderr,
+              flush=True)
+        out["cpu_baseline"] = cpu_baseline(p, sample, threads)
     print(json.dumps(out), flush=True)
 
 

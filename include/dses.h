@@ -100,6 +100,7 @@ typedef enum {
 
 #define DSES_DEVICE_PTRS 0x1u   /* inputs (and records) are device pointers            */
 #define DSES_TIMING 0x2u        /* time each kernel with HIP events (dses_kernel_stats) */
+#define DSES_BATCH_TUNE 0x4u    /* dses_register_batch: autotune the launch layout (below) */
 
 typedef struct {
     uint32_t struct_size;     /* sizeof(dses_options); 0-filled fields mean defaults  */
@@ -109,11 +110,27 @@ typedef struct {
     float t_min[3];           /* translation box; t_min == t_max == 0 -> [-1, 1]^3      */
     float t_max[3];
     int32_t scorer;           /* dses_scorer; 0 -> AUTO                                 */
-    int32_t reserved;
+    int32_t top_k;            /* 0..DSES_TOPK_MAX best candidates to return in topk      */
     void *stream;             /* hipStream_t to run on; NULL -> the library's stream    */
     void *records;            /* optional: K dses_record, one per rotation, filled on
                                  DSES_OK (host memory, or device with DSES_DEVICE_PTRS) */
+    void *topk;               /* optional: top_k dses_candidate, best first in the
+                                 selection order (error, then more inliers, then lower
+                                 rotation index; the first equals the result); entries
+                                 past the number of valid rotations have rot_index -1.
+                                 Host memory, or device with DSES_DEVICE_PTRS          */
 } dses_options;
+
+#define DSES_TOPK_MAX 64
+
+/* One scored candidate {R_k, t_k} (28 bytes), for the top-k output. */
+typedef struct {
+    int32_t rot_index;        /* index into the rotation list, -1: none               */
+    int32_t inliers;
+    float error;
+    uint32_t votes;           /* M of t_k                                             */
+    float t[3];               /* t_k = b* delta                                       */
+} dses_candidate;
 
 /* Result of one registration. */
 typedef struct {
@@ -235,19 +252,46 @@ typedef struct {
 
 typedef struct {
     uint32_t struct_size;
-    uint32_t flags;           /* DSES_DEVICE_PTRS | DSES_TIMING */
+    uint32_t flags;           /* DSES_DEVICE_PTRS | DSES_TIMING | DSES_BATCH_TUNE */
     int32_t scorer;           /* dses_scorer for every problem */
     int32_t use_graph;        /* 1: capture the launch in a HIP graph and replay it */
-    int32_t tile_rot;         /* rotations per work item; 0 -> autotuned            */
-    int32_t reserved;
+    int32_t tile_rot;         /* rotations per work item; 0 -> tuned or default layout */
+    int32_t parts_max;        /* most reference-window parts per 64-source group in the
+                                 vote (1..8); 0 -> tuned or default (8)               */
     void *stream;
 } dses_batch_opts;
 
 /* Register every problem; results (and records) are identical to running each
- * problem alone with dses_register.  Synchronous. */
+ * problem alone with dses_register, whatever the launch layout.  Synchronous.
+ *
+ * Launch layout.  The persistent launch takes (instance, rotation tile) items from
+ * one work list, most expensive first.  Two knobs shape it: the work-list
+ * granularity (tiles sized so that the list holds about `items_per_cu` items per
+ * compute unit, unless tile_rot fixes the tile) and parts_max (how finely the vote
+ * splits each 64-source group's reference window over the workgroup's waves).
+ * With DSES_BATCH_TUNE the call first times the sweep kernel alone on this batch
+ * for candidate layouts (items_per_cu in {6, 12, 24, 48, 96}, then parts_max in
+ * {1, 2, 4, 8}, one coordinate at a time), keeps the fastest for every later batch
+ * of the same class (same count and scorer, same power-of-two bucket of total
+ * pairs, of mean source size and of mean rotation count), and then runs the batch
+ * with it.  Without the flag a batch uses its class's tuned layout if one exists,
+ * else the default (items_per_cu 24, parts_max 8). */
 dses_status dses_register_batch(const dses_problem *probs, int32_t count,
                                 const dses_batch_opts *opt, dses_result *out,
                                 dses_status *status);
+
+typedef struct {
+    int32_t items_per_cu;     /* work-list granularity used (0 when tile_rot fixed it) */
+    int32_t parts_max;        /* vote window parts used                                */
+    int32_t n_items;          /* work items in the launch                             */
+    int32_t source;           /* 0 default, 1 tuned by this call, 2 tuned earlier for
+                                 this class, 3 given by the caller                    */
+    int32_t candidates;       /* layouts timed by this call (source 1)                */
+    float sweep_ms;           /* sweep kernel time of the chosen layout when tuned    */
+} dses_batch_config;
+
+/* Launch layout of this thread's last successful dses_register_batch call. */
+dses_status dses_batch_last_config(dses_batch_config *out);
 
 /* ---------------------------------------------------------------------------- */
 /* Serving: a request loop with memory-based admission and continuous batching. */

@@ -165,6 +165,19 @@ def select(recs) -> int:
     return int(lib().orc_select(recs.ctypes.data, len(recs)))
 
 
+def topk(recs, k) -> np.ndarray:
+    """The k best candidates in the selection order of the return step of Alg. 2
+    (smaller error, then more inliers, then lower index) over the rotations with at
+    least one in-box vote: the definition written out as a sort.  Returns rotation
+    indices, -1 past the number of valid rotations."""
+    recs = np.ascontiguousarray(recs, RECORD_DTYPE)
+    valid = [q for q in range(len(recs)) if recs["valid"][q]]
+    order = sorted(valid, key=lambda q: (float(recs["error"][q]), -int(recs["inliers"][q]), q))
+    out = np.full(k, -1, np.int64)
+    out[:min(k, len(order))] = order[:k]
+    return out
+
+
 def register(src, tgt, rotations, eps, **kw):
     """Full Alg. 2: returns a dict {R, t, rot_index, inliers, error, votes, records}."""
     recs = records(src, tgt, rotations, eps, **kw)

@@ -376,9 +376,15 @@ static int effective_scorer(const Job &job)
 // the plain driver
 // ---------------------------------------------------------------------------
 dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check_inputs,
-                      dses_result *out, void *records, bool records_on_device)
+                      dses_result *out, const dses_options &o)
 {
     const Params &p = job.p;
+    void *records = o.records;
+    const bool on_device = (o.flags & DSES_DEVICE_PTRS) != 0;
+    if (o.top_k < 0 || o.top_k > DSES_TOPK_MAX || (o.top_k > 0 && !o.topk)) {
+        set_error("top_k must be in 0..DSES_TOPK_MAX with a topk buffer");
+        return DSES_E_INVAL;
+    }
     const int scorer = effective_scorer(job);
     if (scorer == DSES_SCORER_DF) {
         if (!job.target || !job.target->df) {
@@ -539,11 +545,23 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     }
     if (records) {
         DSES_HIP(hipMemcpyAsync(records, a.rec, (size_t)job.k * sizeof(dses_record),
-                                records_on_device ? hipMemcpyDeviceToDevice
-                                                  : hipMemcpyDeviceToHost,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                 stream));
-        DSES_HIP(hipStreamSynchronize(stream));
     }
+    if (o.top_k > 0) {
+        const size_t sb = topk_scratch_bytes(job.k, o.top_k);
+        if ((st = c->topk_a.ensure(sb)) != DSES_OK) return st;
+        if ((st = c->topk_b.ensure(sb)) != DSES_OK) return st;
+        if ((st = c->topk_out.ensure(DSES_TOPK_MAX * sizeof(dses_candidate))) != DSES_OK) return st;
+        auto *dst = on_device ? static_cast<dses_candidate *>(o.topk)
+                              : static_cast<dses_candidate *>(c->topk_out.ptr);
+        DSES_HIP(launch_topk(a.rec, job.k, o.top_k, p.delta, c->topk_a.ptr, c->topk_b.ptr, dst,
+                             stream));
+        if (!on_device)
+            DSES_HIP(hipMemcpyAsync(o.topk, dst, (size_t)o.top_k * sizeof(dses_candidate),
+                                    hipMemcpyDeviceToHost, stream));
+    }
+    if (records || o.top_k > 0) DSES_HIP(hipStreamSynchronize(stream));
     if (out) {
         std::memcpy(out->R, r.R, sizeof(out->R));
         std::memcpy(out->t, r.t, sizeof(out->t));
@@ -599,6 +617,10 @@ dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t
         }
         o = *opt;
     }
+    if (o.top_k < 0 || o.top_k > DSES_TOPK_MAX || (o.top_k > 0 && !o.topk)) {
+        set_error("top_k must be in 0..DSES_TOPK_MAX with a topk buffer");
+        return DSES_E_INVAL;
+    }
     Params p;
     dses_status st = resolve_params(eps, metric, o.delta_t, o.tau, o.t_min, o.t_max, o.scorer, &p);
     if (st != DSES_OK) return st;
@@ -640,7 +662,7 @@ dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t
         job.rot = static_cast<float *>(c->in_rot.ptr);
         job.host_tgt = tgt;
     }
-    return run_plain(c, job, stream, dev, out, o.records, dev);
+    return run_plain(c, job, stream, dev, out, o);
 }
 
 }  // extern "C"

@@ -15,7 +15,9 @@
 #include <cmath>
 #include <cstring>
 #include <atomic>
+#include <map>
 #include <numeric>
+#include <tuple>
 #include <thread>
 #include <vector>
 
@@ -73,6 +75,27 @@ struct BatchState {
 };
 
 BatchState *g_batch = nullptr;
+
+// Launch layout of a batch: work-list granularity and vote window parts.
+struct Layout {
+    int items_per_cu = 24;
+    int parts_max = 8;
+};
+
+// Tuned layouts by batch class (count, scorer, log2 buckets of total pairs, mean
+// source size and mean rotation count), guarded by the context mutex.
+struct ClassKey {
+    int count, scorer, pairs_b, n_b, k_b;
+    bool operator<(const ClassKey &o) const
+    {
+        return std::tie(count, scorer, pairs_b, n_b, k_b) <
+               std::tie(o.count, o.scorer, o.pairs_b, o.n_b, o.k_b);
+    }
+};
+std::map<ClassKey, std::pair<Layout, float>> g_tuned;
+
+thread_local dses_batch_config t_last_config{};
+thread_local bool t_have_config = false;
 
 }  // namespace
 
@@ -187,7 +210,8 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
     }
     dses_batch_opts o{};
     if (opt) o = *opt;
-    if (o.scorer < DSES_SCORER_AUTO || o.scorer > DSES_SCORER_DF || o.tile_rot < 0) {
+    if (o.scorer < DSES_SCORER_AUTO || o.scorer > DSES_SCORER_DF || o.tile_rot < 0 ||
+        o.parts_max < 0 || o.parts_max > 8) {
         set_error("invalid batch options");
         return DSES_E_INVAL;
     }
@@ -354,35 +378,73 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
     if (st != DSES_OK) return st;
     char *arena = static_cast<char *>(b->arena.ptr);
 
-    // work list: rotation tiles, most expensive first
-    double total = 0.0;
+    // work list: rotation tiles, most expensive first; the tile is sized so the list
+    // holds about items_per_cu items per compute unit (or fixed by tile_rot)
+    double total = 0.0, sum_n = 0.0, sum_k = 0.0;
+    int n_ok = 0;
     for (auto &x : P)
-        if (x.status == DSES_OK) total += (double)x.n * x.m * x.k;
-    const double target_cost = std::max(1.0, total / ((double)grid * 24.0));
-    struct Tile { double cost; BatchItem it; };
-    std::vector<Tile> tiles;
-    for (int i = 0; i < count; ++i) {
-        const Prepared &x = P[i];
-        if (x.status != DSES_OK) continue;
-        const double per_rot = (double)x.n * x.m + 1.0;
-        int tile = o.tile_rot > 0 ? o.tile_rot
-                                  : (int)std::max(1.0, std::min((double)x.k, target_cost / per_rot));
-        for (int32_t k0 = 0; k0 < x.k; k0 += tile) {
-            const int32_t k1 = std::min<int32_t>(x.k, k0 + tile);
-            tiles.push_back({per_rot * (k1 - k0), BatchItem{i, k0, k1, 0}});
+        if (x.status == DSES_OK) {
+            total += (double)x.n * x.m * x.k;
+            sum_n += x.n;
+            sum_k += x.k;
+            ++n_ok;
+        }
+    auto build_items = [&](int items_per_cu, std::vector<BatchItem> *list) {
+        const double target_cost = std::max(1.0, total / ((double)grid * items_per_cu));
+        struct Tile { double cost; BatchItem it; };
+        std::vector<Tile> tiles;
+        for (int i = 0; i < count; ++i) {
+            const Prepared &x = P[i];
+            if (x.status != DSES_OK) continue;
+            const double per_rot = (double)x.n * x.m + 1.0;
+            const int tile = o.tile_rot > 0
+                                 ? o.tile_rot
+                                 : (int)std::max(1.0, std::min((double)x.k, target_cost / per_rot));
+            for (int32_t k0 = 0; k0 < x.k; k0 += tile) {
+                const int32_t k1 = std::min<int32_t>(x.k, k0 + tile);
+                tiles.push_back({per_rot * (k1 - k0), BatchItem{i, k0, k1, 0}});
+            }
+        }
+        std::stable_sort(tiles.begin(), tiles.end(),
+                         [](const Tile &a, const Tile &bb) { return a.cost > bb.cost; });
+        list->resize(tiles.size());
+        for (size_t t = 0; t < tiles.size(); ++t) (*list)[t] = tiles[t].it;
+    };
+    static const int kItemsPerCu[] = {6, 12, 24, 48, 96};
+    static const int kPartsMax[] = {1, 2, 4, 8};
+    const bool tune = (o.flags & DSES_BATCH_TUNE) != 0;
+    const bool caller_layout = o.tile_rot > 0 || o.parts_max > 0;
+    auto lg = [](double v) { return v >= 1.0 ? (int)std::floor(std::log2(v)) : 0; };
+    const ClassKey key{count, batch_scorer, lg(total), lg(sum_n / std::max(1, n_ok)),
+                       lg(sum_k / std::max(1, n_ok))};
+    Layout lay;
+    dses_batch_config cfg{};
+    cfg.source = 0;
+    if (!tune) {
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            lay = it->second.first;
+            cfg.source = 2;
+            cfg.sweep_ms = it->second.second;
         }
     }
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const Tile &a, const Tile &bb) { return a.cost > bb.cost; });
-    const int n_items = (int)tiles.size();
-    if ((st = ensure_capacity(b, count, n_items, (size_t)grid * max_n * sizeof(float4))) != DSES_OK)
+    if (o.parts_max > 0) lay.parts_max = o.parts_max;
+    if (caller_layout && !tune) cfg.source = 3;
+    std::vector<BatchItem> items;
+    int max_items = 0;
+    for (int f : kItemsPerCu) {
+        if (!tune && f != lay.items_per_cu) continue;
+        build_items(f, &items);
+        max_items = std::max(max_items, (int)items.size());
+    }
+    build_items(lay.items_per_cu, &items);
+    int n_items = (int)items.size();
+    if ((st = ensure_capacity(b, count, max_items, (size_t)grid * max_n * sizeof(float4))) != DSES_OK)
         return st;
 
     std::vector<SweepArgs> inst(b->cap_count);
     std::vector<StageDesc> stage(b->cap_count);
     std::vector<SelectDesc> sel(b->cap_count);
-    std::vector<BatchItem> items(n_items);
-    for (int t = 0; t < n_items; ++t) items[t] = tiles[t].it;
     uint32_t *status_dev = static_cast<uint32_t *>(b->status.ptr);
     DevResult *res_dev = static_cast<DevResult *>(b->results.ptr);
     for (int i = 0; i < count; ++i) {
@@ -430,6 +492,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         a.g = x.g;
         a.rec = reinterpret_cast<dses_record *>(arena + x.off_rec);
         a.k = x.k;
+        a.parts_max = lay.parts_max;
         if (x.scorer == DSES_SCORER_GRID) {
             if (x.target) {
                 a.grid.pts = x.grid_pts;
@@ -460,7 +523,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
                        const_cast<float *>(a.ys), const_cast<float *>(a.yt)};
         sl = SelectDesc{a.rec, x.k, x.p.delta, x.rot, res_dev + i, status_dev + i};
     }
-    const int32_t header[2] = {n_items, count};
+    int32_t header[2] = {n_items, count};
     DSES_HIP(hipMemcpyAsync(b->inst.ptr, inst.data(), inst.size() * sizeof(SweepArgs),
                             hipMemcpyHostToDevice, stream));
     DSES_HIP(hipMemcpyAsync(b->stage.ptr, stage.data(), stage.size() * sizeof(StageDesc),
@@ -480,6 +543,80 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         }
     // everything above must land before a captured graph is replayed
     DSES_HIP(hipStreamSynchronize(stream));
+
+    if (tune) {
+        // time the sweep alone for each candidate layout (stage once, then clear the
+        // work cursor and sweep); one coordinate at a time: granularity with the
+        // default vote split, then the vote split with the best granularity
+        uint32_t *cursor = status_dev + b->cap_count;
+        const int32_t *hdr_dev = static_cast<int32_t *>(b->header.ptr);
+        DSES_HIP(launch_batch_aux(static_cast<StageDesc *>(b->stage.ptr), nullptr, hdr_dev,
+                                  b->cap_count, 0, stream));
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        DSES_HIP(hipEventCreate(&t0));
+        DSES_HIP(hipEventCreate(&t1));
+        auto time_layout = [&](const Layout &L, float *ms) -> dses_status {
+            build_items(L.items_per_cu, &items);
+            header[0] = (int32_t)items.size();
+            for (int i = 0; i < count; ++i) inst[i].parts_max = L.parts_max;
+            DSES_HIP(hipMemcpyAsync(b->items.ptr, items.data(), items.size() * sizeof(BatchItem),
+                                    hipMemcpyHostToDevice, stream));
+            DSES_HIP(hipMemcpyAsync(b->header.ptr, header, sizeof(header), hipMemcpyHostToDevice,
+                                    stream));
+            DSES_HIP(hipMemcpyAsync(b->inst.ptr, inst.data(), count * sizeof(SweepArgs),
+                                    hipMemcpyHostToDevice, stream));
+            DSES_HIP(launch_clear(cursor, 1, stream));
+            DSES_HIP(hipEventRecord(t0, stream));
+            BatchArgs ba{static_cast<SweepArgs *>(b->inst.ptr),
+                         static_cast<BatchItem *>(b->items.ptr), hdr_dev, cursor, nullptr};
+            DSES_HIP(launch_sweep_batch(ba, batch_scorer, grid, stream));
+            DSES_HIP(hipEventRecord(t1, stream));
+            DSES_HIP(hipStreamSynchronize(stream));
+            DSES_HIP(hipEventElapsedTime(ms, t0, t1));
+            ++cfg.candidates;
+            return DSES_OK;
+        };
+        Layout best = lay;
+        float best_ms = INFINITY;
+        dses_status tst = DSES_OK;
+        if (o.tile_rot <= 0)
+            for (int f : kItemsPerCu) {
+                Layout L{f, best.parts_max};
+                float ms = 0.0f;
+                if ((tst = time_layout(L, &ms)) != DSES_OK) break;
+                if (ms < best_ms) { best_ms = ms; best = L; }
+            }
+        if (tst == DSES_OK && o.parts_max <= 0)
+            for (int gm : kPartsMax) {
+                if (gm == best.parts_max && best_ms < INFINITY) continue;
+                Layout L{best.items_per_cu, gm};
+                float ms = 0.0f;
+                if ((tst = time_layout(L, &ms)) != DSES_OK) break;
+                if (ms < best_ms) { best_ms = ms; best = L; }
+            }
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+        if (tst != DSES_OK) return tst;
+        lay = best;
+        if (!caller_layout) g_tuned[key] = {best, best_ms};
+        cfg.source = cfg.candidates > 0 ? 1 : 3;
+        cfg.sweep_ms = cfg.candidates > 0 ? best_ms : 0.0f;
+        // restore the chosen layout for the run below
+        build_items(lay.items_per_cu, &items);
+        n_items = (int)items.size();
+        header[0] = n_items;
+        for (int i = 0; i < count; ++i) inst[i].parts_max = lay.parts_max;
+        DSES_HIP(hipMemcpyAsync(b->items.ptr, items.data(), items.size() * sizeof(BatchItem),
+                                hipMemcpyHostToDevice, stream));
+        DSES_HIP(hipMemcpyAsync(b->header.ptr, header, sizeof(header), hipMemcpyHostToDevice,
+                                stream));
+        DSES_HIP(hipMemcpyAsync(b->inst.ptr, inst.data(), count * sizeof(SweepArgs),
+                                hipMemcpyHostToDevice, stream));
+        DSES_HIP(hipStreamSynchronize(stream));
+    }
+    cfg.items_per_cu = o.tile_rot > 0 ? 0 : lay.items_per_cu;
+    cfg.parts_max = lay.parts_max;
+    cfg.n_items = n_items;
 
     const bool timing = (o.flags & DSES_TIMING) != 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -539,7 +676,24 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         }
     }
     if (any_records) DSES_HIP(hipStreamSynchronize(stream));
+    t_last_config = cfg;
+    t_have_config = true;
     for (int i = 0; i < count; ++i)
         if (status_out[i] != DSES_OK) return DSES_OK;     // per-problem statuses carry the detail
+    return DSES_OK;
+}
+
+extern "C" dses_status dses_batch_last_config(dses_batch_config *out)
+{
+    set_error("");
+    if (!out) {
+        set_error("NULL output");
+        return DSES_E_INVAL;
+    }
+    if (!t_have_config) {
+        set_error("no batch has completed on this thread");
+        return DSES_E_STATE;
+    }
+    *out = t_last_config;
     return DSES_OK;
 }

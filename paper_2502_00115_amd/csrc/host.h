@@ -47,6 +47,7 @@ struct Context {
     std::mutex mu;                       // serialises the plain entry points
     // workspace of the plain path
     DevBuf in_src, in_tgt, in_rot, ys, yt, rec, res, status, grid_pts, grid_start, perm, tab, scratch;
+    DevBuf topk_a, topk_b, topk_out;     // top-k passes and output staging
     DevResult *host_res = nullptr;       // pinned
     // timing
     bool timing_enabled = false;
@@ -145,7 +146,7 @@ struct Job {
 
 // Run one registration on `stream` using the context workspace (caller holds c->mu).
 dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check_inputs,
-                      dses_result *out, void *records, bool records_on_device);
+                      dses_result *out, const dses_options &o);
 
 void add_stats(Context *c, double vote_ms, double score_ms, double select_ms, double stage_ms,
                int64_t launches, int64_t pairs_voted, int64_t pairs_scored, int64_t cands);

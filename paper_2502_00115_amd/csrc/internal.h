@@ -67,6 +67,7 @@ struct SweepArgs {
     Field field;
     dses_record *rec;      // one record per rotation index
     int32_t k;             // rotations
+    int32_t parts_max;     // most reference-window parts per 64-source group (0: 8)
 };
 
 // Batched registration.
@@ -131,6 +132,12 @@ hipError_t launch_stage(const float *tgt, const int32_t *perm, int32_t m, float 
 hipError_t launch_sweep(const SweepArgs &a, int scorer, int grid, hipStream_t stream);
 hipError_t launch_select(const dses_record *rec, int32_t k, const float *rot, float delta,
                          DevResult *res, const uint32_t *status, hipStream_t stream);
+// Top-k candidates of K records in selection order (k <= DSES_TOPK_MAX): passes of
+// workgroup sorts reduce 2048 entries to k each until one workgroup remains; the
+// scratch buffers hold ceil(K / 2048) * k entries of 12 bytes each.
+size_t topk_scratch_bytes(int32_t K, int32_t k);
+hipError_t launch_topk(const dses_record *rec, int32_t K, int32_t k, float delta, void *scr_a,
+                       void *scr_b, dses_candidate *out, hipStream_t stream);
 hipError_t launch_clear(uint32_t *p, int32_t words, hipStream_t stream);
 hipError_t launch_sweep_batch(const BatchArgs &b, int scorer, int grid, hipStream_t stream);
 // which = 0: batched staging, 1: batched selection

@@ -18,6 +18,8 @@
 //  * Scoring reuses the lanes' source points; the error sum is a fixed-order tree,
 //    so a rotation's record does not depend on what else runs on the GPU.
 #include <hip/hip_runtime.h>
+
+#include <utility>
 #include <math.h>
 #include <stdint.h>
 
@@ -309,11 +311,12 @@ __device__ __forceinline__ float wave_max(float v)
 }
 
 // Parts per 64-source group so that sw groups x G parts spread evenly over the
-// kWaves waves (fewest parts among the best spreads; at most 8).
-__device__ __forceinline__ int vote_parts(int sw)
+// kWaves waves (fewest parts among the best spreads; at most gmax, itself <= 8).
+__device__ __forceinline__ int vote_parts(int sw, int gmax)
 {
+    gmax = gmax > 0 ? min(gmax, 8) : 8;
     int best = 1, best_num = sw, best_den = kWaves * ((sw + kWaves - 1) / kWaves);
-    for (int G = 2; G <= 8; ++G) {
+    for (int G = 2; G <= gmax; ++G) {
         const int num = sw * G, den = kWaves * ((num + kWaves - 1) / kWaves);
         if (num * best_den > best_num * den) { best = G; best_num = num; best_den = den; }
     }
@@ -358,7 +361,7 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
         // the waves take units round-robin, so all kWaves vote even when the chunk
         // has fewer than kWaves source groups
         const int sw = (min(kBlock, g.n - c0) + 63) >> 6;
-        const int G = vote_parts(sw);
+        const int G = vote_parts(sw, a.parts_max);
         for (int u = wave; u < sw * G; u += kWaves) {
             const int part = u / sw;
             const int i = c0 + (u - part * sw) * 64 + lane;
@@ -837,6 +840,112 @@ hipError_t launch_select(const dses_record *rec, int32_t k, const float *rot, fl
 {
     hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, stream, rec, k, rot, delta, res,
                        status);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// top-k: the k best candidates in selection order.  An entry is the triple
+// (error bits, ~inliers, index), compared as unsigned integers: for the
+// non-negative errors of valid candidates the float order equals the bit order,
+// ~inliers puts more inliers first, and the index breaks the remaining ties, so
+// the order is exactly the one of sel_better.  Rotations without an in-box vote
+// become (all ones), after every valid entry.
+// --------------------------------------------------------------------------
+constexpr int kTopChunk = 2048;     // entries sorted per workgroup and pass
+
+struct TopEntry {
+    uint32_t e, ninl, idx;
+};
+
+__device__ __forceinline__ bool top_less(const TopEntry &a, const TopEntry &b)
+{
+    if (a.e != b.e) return a.e < b.e;
+    if (a.ninl != b.ninl) return a.ninl < b.ninl;
+    return a.idx < b.idx;
+}
+
+// One pass: workgroup b sorts entries [b * kTopChunk, ...) in LDS (bitonic) and
+// writes its first k to out[b * k, ...).  FROM_REC: the entries are built from
+// records (index = position), else read from a previous pass.
+template <bool FROM_REC>
+__global__ void __launch_bounds__(1024) k_topk_pass(const void *in, int32_t count, int32_t k,
+                                                    TopEntry *out)
+{
+    __shared__ uint32_t se[kTopChunk], sn[kTopChunk], si[kTopChunk];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kTopChunk;
+    for (int q = tid; q < kTopChunk; q += blockDim.x) {
+        TopEntry t{0xffffffffu, 0xffffffffu, 0xffffffffu};
+        const int64_t g = base + q;
+        if (g < count) {
+            if (FROM_REC) {
+                const dses_record r = static_cast<const dses_record *>(in)[g];
+                if (r.votes != 0) t = TopEntry{__float_as_uint(r.error), ~(uint32_t)r.inliers,
+                                               (uint32_t)g};
+            } else {
+                t = static_cast<const TopEntry *>(in)[g];
+            }
+        }
+        se[q] = t.e;
+        sn[q] = t.ninl;
+        si[q] = t.idx;
+    }
+    __syncthreads();
+    for (int size = 2; size <= kTopChunk; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < kTopChunk / 2; t += blockDim.x) {
+                const int i = 2 * stride * (t / stride) + (t % stride), j = i + stride;
+                const bool up = (i & size) == 0;
+                const TopEntry a{se[i], sn[i], si[i]}, b{se[j], sn[j], si[j]};
+                if (top_less(b, a) == up) {
+                    se[i] = b.e; sn[i] = b.ninl; si[i] = b.idx;
+                    se[j] = a.e; sn[j] = a.ninl; si[j] = a.idx;
+                }
+            }
+            __syncthreads();
+        }
+    if (tid < k) out[(int64_t)blockIdx.x * k + tid] = TopEntry{se[tid], sn[tid], si[tid]};
+}
+
+__global__ void k_topk_emit(const TopEntry *top, int32_t k, const dses_record *rec, float delta,
+                            dses_candidate *out)
+{
+    const int t = threadIdx.x;
+    if (t >= k) return;
+    dses_candidate c{-1, 0, INFINITY, 0u, {0.0f, 0.0f, 0.0f}};
+    const TopEntry e = top[t];
+    if (e.idx != 0xffffffffu) {
+        const dses_record r = rec[e.idx];
+        c.rot_index = (int32_t)e.idx;
+        c.inliers = r.inliers;
+        c.error = r.error;
+        c.votes = r.votes;
+        for (int a = 0; a < 3; ++a) c.t[a] = __fmul_rn((float)r.bin[a], delta);
+    }
+    out[t] = c;
+}
+
+size_t topk_scratch_bytes(int32_t K, int32_t k)
+{
+    return (size_t)((K + kTopChunk - 1) / kTopChunk) * (size_t)k * sizeof(TopEntry);
+}
+
+hipError_t launch_topk(const dses_record *rec, int32_t K, int32_t k, float delta, void *scr_a,
+                       void *scr_b, dses_candidate *out, hipStream_t stream)
+{
+    int32_t count = K;
+    int blocks = (count + kTopChunk - 1) / kTopChunk;
+    auto *a = static_cast<TopEntry *>(scr_a), *b = static_cast<TopEntry *>(scr_b);
+    hipLaunchKernelGGL(k_topk_pass<true>, dim3(blocks), dim3(1024), 0, stream,
+                       static_cast<const void *>(rec), count, k, a);
+    while (blocks > 1) {
+        count = blocks * k;
+        blocks = (count + kTopChunk - 1) / kTopChunk;
+        hipLaunchKernelGGL(k_topk_pass<false>, dim3(blocks), dim3(1024), 0, stream,
+                           static_cast<const void *>(a), count, k, b);
+        std::swap(a, b);
+    }
+    hipLaunchKernelGGL(k_topk_emit, dim3(1), dim3(64), 0, stream, a, k, rec, delta, out);
     return hipGetLastError();
 }
 

@@ -328,7 +328,7 @@ dses_status dses_register_resident(const dses_target *tgt, const dses_rotset *ro
                                 stream));
         job.src = static_cast<float *>(c->in_src.ptr);
     }
-    return run_plain(c, job, stream, dev, out, o.records, dev);
+    return run_plain(c, job, stream, dev, out, o);
 }
 
 }  // extern "C"

@@ -22,12 +22,13 @@ STATUS_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOCANDIDATE", -3: "E_NOMEM", -4: 
                 -5: "E_DEVICE", -6: "E_STATE"}
 METRICS = {"trunc_l2": 0, "inliers": 1, "tls": 2, "trunc_l1": 3}
 SCORERS = {"auto": 0, "brute": 1, "grid": 2, "df": 3}
-DEVICE_PTRS, TIMING = 0x1, 0x2
+DEVICE_PTRS, TIMING, BATCH_TUNE = 0x1, 0x2, 0x4
 
 EXPORTED = [
     "dses_last_error", "dses_init", "dses_version", "dses_kernel_stats", "dses_register",
     "dses_target_create", "dses_target_destroy", "dses_target_field", "dses_rotations_create",
     "dses_rotations_destroy", "dses_register_resident", "dses_register_batch",
+    "dses_batch_last_config",
     "dses_server_create", "dses_server_submit", "dses_server_wait", "dses_server_poll",
     "dses_server_timing", "dses_server_destroy",
 ]
@@ -45,8 +46,8 @@ class DsesError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("flags", C.c_uint32), ("delta_t", C.c_float),
                 ("tau", C.c_float), ("t_min", C.c_float * 3), ("t_max", C.c_float * 3),
-                ("scorer", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p),
-                ("records", C.c_void_p)]
+                ("scorer", C.c_int32), ("top_k", C.c_int32), ("stream", C.c_void_p),
+                ("records", C.c_void_p), ("topk", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -78,8 +79,13 @@ class Problem(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("flags", C.c_uint32), ("scorer", C.c_int32),
-                ("use_graph", C.c_int32), ("tile_rot", C.c_int32), ("reserved", C.c_int32),
+                ("use_graph", C.c_int32), ("tile_rot", C.c_int32), ("parts_max", C.c_int32),
                 ("stream", C.c_void_p)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("items_per_cu", C.c_int32), ("parts_max", C.c_int32), ("n_items", C.c_int32),
+                ("source", C.c_int32), ("candidates", C.c_int32), ("sweep_ms", C.c_float)]
 
 
 class ServerOpts(C.Structure):
@@ -91,6 +97,10 @@ class ServerOpts(C.Structure):
 RECORD_DTYPE = np.dtype([("bin", "<i4", (3,)), ("votes", "<u4"), ("inliers", "<i4"),
                          ("error", "<f4")])
 assert RECORD_DTYPE.itemsize == 24
+CANDIDATE_DTYPE = np.dtype([("rot_index", "<i4"), ("inliers", "<i4"), ("error", "<f4"),
+                            ("votes", "<u4"), ("t", "<f4", (3,))])
+assert CANDIDATE_DTYPE.itemsize == 28
+TOPK_MAX = 64
 
 _lib = None
 
@@ -116,6 +126,7 @@ def lib():
         L.dses_rotations_destroy.argtypes = [vp]
         L.dses_register_resident.argtypes = [vp, vp, vp, i64, f, i32, C.POINTER(Options),
                                              C.POINTER(Result)]
+        L.dses_batch_last_config.argtypes = [C.POINTER(BatchConfig)]
         L.dses_register_batch.argtypes = [C.POINTER(Problem), i32, C.POINTER(BatchOpts),
                                           C.POINTER(Result), C.POINTER(i32)]
         L.dses_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(vp)]
@@ -160,12 +171,13 @@ class Registration:
     votes: int
     n_valid: int
     records: np.ndarray | None = None
+    top: np.ndarray | None = None          # CANDIDATE_DTYPE, best first (top_k > 0)
 
 
-def _result(r: Result, records=None) -> Registration:
+def _result(r: Result, records=None, top=None) -> Registration:
     return Registration(np.array(r.R, np.float32).reshape(3, 3), np.array(r.t, np.float32),
                         int(r.rot_index), int(r.inliers), float(r.error), int(r.votes),
-                        int(r.n_valid), records)
+                        int(r.n_valid), records, top)
 
 
 def _is_torch(x):
@@ -241,26 +253,48 @@ def _records_buffer(args: _Args, k: int):
     return buf, C.c_void_p(buf.ctypes.data)
 
 
-def _records_out(buf):
+def _records_out(buf, dtype=RECORD_DTYPE):
     if isinstance(buf, np.ndarray):
         return buf
-    return np.frombuffer(buf.cpu().numpy().tobytes(), RECORD_DTYPE)
+    return np.frombuffer(buf.cpu().numpy().tobytes(), dtype)
+
+
+def _topk_buffer(args: _Args, k: int, o: Options):
+    """Caller-owned top-k array for k candidates (device memory for device inputs)."""
+    if not 0 <= k <= TOPK_MAX:
+        raise ValueError(f"top_k must be in 0..{TOPK_MAX}")
+    if k == 0:
+        return None
+    if args.device:
+        import torch
+        buf = torch.empty(k * CANDIDATE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        ptr = buf.data_ptr()
+    else:
+        buf = np.zeros(k, CANDIDATE_DTYPE)
+        ptr = buf.ctypes.data
+    args.keep.append(buf)
+    o.top_k = k
+    o.topk = C.c_void_p(ptr)
+    return buf
 
 
 def register(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=None,
-             t_min=None, t_max=None, scorer="auto", records=False, timing=False,
+             t_min=None, t_max=None, scorer="auto", records=False, top_k=0, timing=False,
              stream=None) -> Registration:
-    """dses_register: the full sweep over the rotation list."""
+    """dses_register: the full sweep over the rotation list (top_k > 0: also the best
+    top_k candidates in selection order, Registration.top)."""
     args = _Args()
     ps, n = args.ptr(src, 3)
     pt, m = args.ptr(tgt, 3)
     pr, k = args.ptr(rotations, 9)
     rbuf, rptr = _records_buffer(args, k) if records else (None, None)
     o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr)
+    tbuf = _topk_buffer(args, int(top_k), o)
     res = Result()
     _check(lib().dses_register(ps, n, pt, m, pr, k, C.c_float(eps), METRICS[metric],
                                C.byref(o), C.byref(res)))
-    return _result(res, _records_out(rbuf) if records else None)
+    return _result(res, _records_out(rbuf) if records else None,
+                   _records_out(tbuf, CANDIDATE_DTYPE) if tbuf is not None else None)
 
 
 def kernel_stats(reset=False) -> dict:
@@ -326,21 +360,25 @@ class RotationSet:
 
 def register_resident(target: Target, rotset: RotationSet, src, eps, metric="trunc_l2", *,
                       delta_t=None, tau=None, t_min=None, t_max=None, scorer="auto",
-                      records=False, timing=False, stream=None) -> Registration:
+                      records=False, top_k=0, timing=False, stream=None) -> Registration:
     args = _Args()
     ps, n = args.ptr(src, 3)
     rbuf, rptr = _records_buffer(args, rotset.k) if records else (None, None)
     o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr)
+    tbuf = _topk_buffer(args, int(top_k), o)
     res = Result()
     _check(lib().dses_register_resident(target.handle, rotset.handle, ps, n, C.c_float(eps),
                                         METRICS[metric], C.byref(o), C.byref(res)))
-    return _result(res, _records_out(rbuf) if records else None)
+    return _result(res, _records_out(rbuf) if records else None,
+                   _records_out(tbuf, CANDIDATE_DTYPE) if tbuf is not None else None)
 
 
-def register_batch(problems, *, scorer="auto", use_graph=True, tile_rot=0, records=False,
-                   timing=False, stream=None):
+def register_batch(problems, *, scorer="auto", use_graph=True, tile_rot=0, parts_max=0,
+                   autotune=False, records=False, timing=False, stream=None):
     """dses_register_batch over dicts with keys src, tgt/target, rotations/rotset, eps,
-    and optionally metric, delta_t, tau, t_min, t_max.  Returns (results, statuses)."""
+    and optionally metric, delta_t, tau, t_min, t_max.  Returns (results, statuses).
+    autotune=True sets DSES_BATCH_TUNE (time candidate launch layouts on this batch and
+    keep the fastest for its class); batch_last_config() reports the layout used."""
     args = _Args()
     arr = (Problem * len(problems))()
     bufs = []
@@ -369,14 +407,25 @@ def register_batch(problems, *, scorer="auto", use_graph=True, tile_rot=0, recor
         else:
             bufs.append(None)
     o = BatchOpts(C.sizeof(BatchOpts), (DEVICE_PTRS if args.device else 0) |
-                  (TIMING if timing else 0), SCORERS[scorer], int(bool(use_graph)),
-                  int(tile_rot), 0, _stream_of(stream) if args.device else None)
+                  (TIMING if timing else 0) | (BATCH_TUNE if autotune else 0), SCORERS[scorer],
+                  int(bool(use_graph)), int(tile_rot), int(parts_max),
+                  _stream_of(stream) if args.device else None)
     res = (Result * len(problems))()
     st = (C.c_int32 * len(problems))()
     _check(lib().dses_register_batch(arr, len(problems), C.byref(o), res, st))
     out = [_result(res[i], _records_out(bufs[i]) if records else None)
            if st[i] == DSES_OK else None for i in range(len(problems))]
     return out, [int(v) for v in st]
+
+
+def batch_last_config() -> dict:
+    """Launch layout of this thread's last dses_register_batch (dses_batch_last_config)."""
+    cfg = BatchConfig()
+    _check(lib().dses_batch_last_config(C.byref(cfg)))
+    source = {0: "default", 1: "tuned", 2: "tuned-cache", 3: "caller"}[cfg.source]
+    return {"items_per_cu": cfg.items_per_cu, "parts_max": cfg.parts_max,
+            "n_items": cfg.n_items, "source": source, "candidates": cfg.candidates,
+            "sweep_ms": cfg.sweep_ms}
 
 
 class Server:

@@ -67,6 +67,15 @@ def test_argument_errors_need_no_gpu(libpath):
         assert e.value.status == dses.DSES_E_INVAL, (kw, e.value)
     with pytest.raises(ValueError):
         dses.register(np.zeros((4, 2)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05)
+    item = {"src": np.zeros((3, 3)), "tgt": np.zeros((4, 3)),
+            "rotations": np.eye(3).reshape(1, 9), "eps": 0.05}
+    for kw in ({"parts_max": 9}, {"parts_max": -1}, {"tile_rot": -2}):
+        with pytest.raises(dses.DsesError) as e:
+            dses.register_batch([item], **kw)
+        assert e.value.status == dses.DSES_E_INVAL, (kw, e.value)
+    with pytest.raises(dses.DsesError) as e:
+        dses.Server(slice_mpairs=-1)
+    assert e.value.status == dses.DSES_E_INVAL
 
 
 def test_no_device_is_a_loud_error(libpath):

@@ -209,3 +209,41 @@ def test_server_many_concurrent_clients():
     for a, b in zip(alone, out):
         _same(a, b)
     srv.close()
+
+
+def test_autotune_keeps_results_and_caches_the_layout():
+    probs = _small_c3(count=5, k=512, seed=7)
+    items = [_as_dict(p) for p in probs]
+    base, st = dses.register_batch(items, records=True)
+    assert st == [0] * len(probs)
+    tuned, st = dses.register_batch(items, autotune=True, records=True)
+    assert st == [0] * len(probs)
+    cfg = dses.batch_last_config()
+    assert cfg["source"] == "tuned" and cfg["candidates"] >= 8
+    assert cfg["items_per_cu"] in (6, 12, 24, 48, 96) and cfg["parts_max"] in (1, 2, 4, 8)
+    assert cfg["sweep_ms"] > 0.0
+    for a, b in zip(base, tuned):
+        _same(a, b)
+        assert a.records.tobytes() == b.records.tobytes()
+    # the same class of batch reuses the tuned layout, in a graph replay too
+    again, st = dses.register_batch(items, use_graph=True, records=True)
+    assert st == [0] * len(probs)
+    cfg2 = dses.batch_last_config()
+    assert cfg2["source"] == "tuned-cache"
+    assert (cfg2["items_per_cu"], cfg2["parts_max"]) == (cfg["items_per_cu"], cfg["parts_max"])
+    for a, b in zip(base, again):
+        assert a.records.tobytes() == b.records.tobytes()
+
+
+@pytest.mark.parametrize("parts_max", [1, 2, 3, 8])
+def test_vote_window_split_does_not_change_results(parts_max):
+    # sources of 150..900 points: 3..15 groups of 64, split into up to parts_max parts
+    probs = _small_c3(count=4, k=256, seed=8)
+    alone = [dses.register(p.src, p.tgt, p.rotations, p.eps, records=True) for p in probs]
+    got, st = dses.register_batch([_as_dict(p) for p in probs], parts_max=parts_max,
+                                  tile_rot=7, records=True)
+    assert st == [0] * len(probs)
+    cfg = dses.batch_last_config()
+    assert cfg["source"] == "caller" and cfg["parts_max"] == parts_max
+    for a, b in zip(alone, got):
+        assert a.records.tobytes() == b.records.tobytes()

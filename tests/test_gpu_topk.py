@@ -1,0 +1,92 @@
+"""Top-k candidates (the selection order of the return step of Alg. 2, k best):
+exact against the kernel's own records, within the error tolerance of the oracle's
+order statistics, and through the multi-pass reduction for large rotation lists."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_00115_amd import synth
+from parity import err_tol
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2502_00115_amd import dses  # noqa: E402
+
+
+def _own_order(rec, k):
+    valid = np.nonzero(rec["votes"] > 0)[0]
+    order = sorted(valid, key=lambda q: (float(rec["error"][q]), -int(rec["inliers"][q]), int(q)))
+    out = np.full(k, -1, np.int64)
+    out[:min(k, len(order))] = order[:k]
+    return out
+
+
+def _check_own(g, k, delta):
+    rec = g.records
+    expect = _own_order(rec, k)
+    np.testing.assert_array_equal(g.top["rot_index"], expect)
+    assert g.top["rot_index"][0] == g.rot_index
+    ok = expect >= 0
+    q = expect[ok]
+    np.testing.assert_array_equal(g.top["inliers"][ok], rec["inliers"][q])
+    np.testing.assert_array_equal(g.top["votes"][ok], rec["votes"][q])
+    assert g.top["error"][ok].tobytes() == rec["error"][q].tobytes()
+    t = rec["bin"][q].astype(np.float32) * np.float32(delta)
+    assert g.top["t"][ok].tobytes() == t.astype(np.float32).tobytes()
+    assert np.all(g.top["rot_index"][~ok] == -1)
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("k", [1, 16, 64])
+def test_topk_c1_exact_and_oracle_order_statistics(seed, k):
+    p = synth.make_c1(seed)
+    g = dses.register(p.src, p.tgt, p.rotations, p.eps, records=True, top_k=k)
+    _check_own(g, k, p.eps)
+    orc = oracle.records(p.src, p.tgt, p.rotations, p.eps)
+    ot = oracle.topk(orc, k)
+    assert np.all((ot >= 0) == (g.top["rot_index"] >= 0))
+    # the i-th best error agrees with the oracle's i-th best within the error tolerance
+    eo = orc["error"][ot[ot >= 0]]
+    eg = g.top["error"][g.top["rot_index"] >= 0].astype(np.float64)
+    assert np.all(np.abs(eg - eo) <= err_tol(eo, len(p.src))), (eg[:4], eo[:4])
+
+
+def test_topk_fewer_valid_rotations_than_k():
+    # a small box: most rotations have no in-box vote
+    p = synth.make_c1(4)
+    g = dses.register(p.src, p.tgt, p.rotations, p.eps, records=True, top_k=64,
+                      t_min=-0.08, t_max=0.08)
+    n_valid = int((g.records["votes"] > 0).sum())
+    assert n_valid == g.n_valid
+    _check_own(g, 64, p.eps)
+    assert int((g.top["rot_index"] >= 0).sum()) == min(64, n_valid)
+
+
+def test_topk_device_pointers_and_resident():
+    p = synth.make_c2(1)
+    dev = [torch.from_numpy(a).cuda() for a in (p.src, p.tgt, p.rotations)]
+    g = dses.register(*dev, p.eps, records=True, top_k=32)
+    _check_own(g, 32, p.eps)
+    T, S = dses.Target(p.tgt), dses.RotationSet(p.rotations)
+    h = dses.register_resident(T, S, p.src, p.eps, records=True, top_k=32)
+    assert h.top.tobytes() == g.top.tobytes()
+
+
+def test_topk_three_reduction_passes():
+    # 150,001 rotations: 74 sorted chunks of 2048 -> 74 * 64 entries -> 3 chunks -> 1
+    rng = np.random.default_rng(11)
+    p = synth.make_c1(7)
+    rots = synth.random_rotations(rng, 150000).reshape(-1, 9)
+    rots = np.concatenate([rots, p.rotations[-1:]]).astype(np.float32)
+    g = dses.register(p.src, p.tgt, rots, p.eps, records=True, top_k=64)
+    _check_own(g, 64, p.eps)
+
+
+def test_topk_rejects_bad_k():
+    p = synth.make_c1(0)
+    with pytest.raises(ValueError):
+        dses.register(p.src, p.tgt, p.rotations, p.eps, top_k=65)

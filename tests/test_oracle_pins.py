@@ -263,6 +263,32 @@ def test_select_tie_breaks():
     assert oracle.select(recs) == -1
 
 
+def test_topk_order_and_first_equals_select():
+    recs = np.zeros(7, oracle.RECORD_DTYPE)
+    recs["valid"] = [1, 1, 0, 1, 1, 1, 1]
+    recs["error"] = [2.0, 1.0, 0.5, 1.0, 1.0, 3.0, 1.0]
+    recs["inliers"] = [9, 5, 9, 7, 7, 1, 8]
+    # by hand: (1.0, 8) idx 6; (1.0, 7) idx 3, 4; (1.0, 5) idx 1; 2.0 idx 0; 3.0 idx 5
+    np.testing.assert_array_equal(oracle.topk(recs, 8), [6, 3, 4, 1, 0, 5, -1, -1])
+    assert oracle.topk(recs, 1)[0] == oracle.select(recs)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        recs = np.zeros(50, oracle.RECORD_DTYPE)
+        recs["valid"] = rng.random(50) < 0.8
+        recs["error"] = rng.integers(0, 4, 50).astype(float)   # many ties
+        recs["inliers"] = rng.integers(0, 4, 50)
+        top = oracle.topk(recs, 10)
+        assert top[0] == oracle.select(recs)
+        # every later entry is the select() of the records left after removing the earlier
+        left = recs.copy()
+        for q in top:
+            if q < 0:
+                assert not left["valid"].any()
+                break
+            assert q == oracle.select(left)
+            left["valid"][q] = 0
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_exact_recovery(seed):
     """Noise-free exact subset, true rotation on the list and t* on the lattice:

@@ -181,7 +181,7 @@ dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, i
 // float rounding of the bin decision), and such a cube meets at most 2 cells per
 // axis of a grid of pitch slightly above delta.  So every count is at most
 // n * (largest reference population of a 2x2x2 block of cells).
-int64_t counter_bound(const float *tgt, int32_t m, int32_t n, const Params &p)
+int64_t ref_block_population(const float *tgt, int32_t m, const Params &p)
 {
     double maxabs = 0.0;
     for (int64_t e = 0; e < 3 * (int64_t)m; ++e) maxabs = std::max(maxabs, (double)std::fabs(tgt[e]));
@@ -190,36 +190,35 @@ int64_t counter_bound(const float *tgt, int32_t m, int32_t n, const Params &p)
     const double s = 1.0 / (double)p.delta;
     const double slack = 16.0 * 5.97e-8 * (4.0 * maxabs * s + kmax + 2.0);   // bin units
     const double h = (double)p.delta * (1.0 + std::max(1e-3, 4.0 * slack));
-    std::unordered_map<int64_t, int32_t> cell;
-    cell.reserve((size_t)m * 2);
     auto key = [](int64_t x, int64_t y, int64_t z) {
         return ((x + (1 << 20)) << 42) | ((y + (1 << 20)) << 21) | (z + (1 << 20));
     };
-    std::vector<int64_t> ids((size_t)m * 3);
+    // points per cell of pitch h, then each cell's count added to the 8 blocks of
+    // 2 x 2 x 2 cells that contain it; the bound is the largest block total
+    std::unordered_map<int64_t, int32_t> cell;
+    cell.reserve((size_t)m * 2);
     for (int32_t j = 0; j < m; ++j)
-        for (int a = 0; a < 3; ++a)
-            ids[3 * (size_t)j + a] = (int64_t)std::floor((double)tgt[3 * j + a] / h);
-    for (int32_t j = 0; j < m; ++j)
-        cell[key(ids[3 * j], ids[3 * j + 1], ids[3 * j + 2])] += 1;
-    int64_t best = 0;
+        cell[key((int64_t)std::floor((double)tgt[3 * j] / h),
+                 (int64_t)std::floor((double)tgt[3 * j + 1] / h),
+                 (int64_t)std::floor((double)tgt[3 * j + 2] / h))] += 1;
+    std::unordered_map<int64_t, int64_t> block;
+    block.reserve(cell.size() * 16);
     for (const auto &kv : cell) {
         const int64_t z = (kv.first & ((1 << 21) - 1)) - (1 << 20);
         const int64_t y = ((kv.first >> 21) & ((1 << 21) - 1)) - (1 << 20);
         const int64_t x = (kv.first >> 42) - (1 << 20);
         for (int ox = -1; ox <= 0; ++ox)
             for (int oy = -1; oy <= 0; ++oy)
-                for (int oz = -1; oz <= 0; ++oz) {
-                    int64_t tot = 0;
-                    for (int dx = 0; dx < 2; ++dx)
-                        for (int dy = 0; dy < 2; ++dy)
-                            for (int dz = 0; dz < 2; ++dz) {
-                                auto it = cell.find(key(x + ox + dx, y + oy + dy, z + oz + dz));
-                                if (it != cell.end()) tot += it->second;
-                            }
-                    best = std::max(best, tot);
-                }
+                for (int oz = -1; oz <= 0; ++oz) block[key(x + ox, y + oy, z + oz)] += kv.second;
     }
-    return best * (int64_t)n;
+    int64_t best = 0;
+    for (const auto &kv : block) best = std::max(best, kv.second);
+    return best;
+}
+
+int64_t counter_bound(const float *tgt, int32_t m, int32_t n, const Params &p)
+{
+    return ref_block_population(tgt, m, p) * (int64_t)n;
 }
 
 // ---------------------------------------------------------------------------
@@ -417,7 +416,10 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
             }
         ht = host_copy.data();
     }
-    const int counter_bits = counter_bound(ht, job.m, job.n, p) <= 65535 ? 16 : 32;
+    const int64_t bound =
+        job.target ? target_block_population(const_cast<TargetRes *>(job.target), p) * job.n
+                   : counter_bound(ht, job.m, job.n, p);
+    const int counter_bits = bound <= 65535 ? 16 : 32;
     Geom g;
     if ((st = plan_geom(c, p, job.n, job.m, counter_bits, &g)) != DSES_OK) return st;
 

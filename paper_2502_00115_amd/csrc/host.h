@@ -73,7 +73,11 @@ float coord_limit(const Params &p);
 
 dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, int counter_bits,
                       Geom *g);
-// Upper bound on any bin's vote count (decides 16- vs 32-bit LDS counters).
+// Upper bound on any bin's vote count (decides 16- vs 32-bit LDS counters):
+// n x the largest reference population of a 2 x 2 x 2 block of cells of pitch
+// slightly above delta (for a fixed source point, the pairs sharing a bin have
+// their references in one delta-cube).
+int64_t ref_block_population(const float *tgt_aos, int32_t m, const Params &p);
 int64_t counter_bound(const float *tgt_aos, int32_t m, int32_t n, const Params &p);
 
 // Reference order sorted by x, and the table tab[q] = first sorted index whose scaled
@@ -117,6 +121,12 @@ struct TargetRes {
         int32_t tab_lo, tab_n;
     };
     std::deque<Stage> stages;                // deque: references survive push_back
+    struct Population {                      // ref_block_population for (delta, box)
+        float delta;
+        int32_t klo[3], size[3];
+        int64_t pop;
+    };
+    std::vector<Population> pops;
     struct Grid {                            // cell grid for one radius
         float r;
         float *pts;
@@ -153,6 +163,8 @@ void add_stats(Context *c, double vote_ms, double score_ms, double select_ms, do
 
 // Stage a resident target for lattice pitch p.delta / box p.klo (cached; holds
 // tm->grid_mu while building; synchronous on `stream`).
+// ref_block_population of a resident target, cached per (delta, box).
+int64_t target_block_population(TargetRes *tm, const Params &p);
 dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stream,
                                 const TargetRes::Stage **out);
 // Build (or reuse) the resident target's cell grid for radius r; fills cg.

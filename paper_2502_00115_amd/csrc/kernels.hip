@@ -63,12 +63,6 @@ __device__ __forceinline__ void rotate(const float *R, float x, float y, float z
     pz = fmaf(R[8], z, fmaf(R[7], y, __fmul_rn(R[6], x)));
 }
 
-// (count desc, lin asc) reduction step.
-__device__ __forceinline__ void better(uint32_t &c, uint32_t &l, uint32_t oc, uint32_t ol)
-{
-    if (oc > c || (oc == c && ol < l)) { c = oc; l = ol; }
-}
-
 __device__ __forceinline__ float wave_sum(float v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -264,14 +258,45 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t ref_rsrc(const float *ys, int 
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(ys), 0, 12 * m, 0x00020000);
 }
 
-// Reference points j .. j+3 (x, y, z): three 16-byte loads, the same address on
-// every lane.
-__device__ __forceinline__ void ref_load4(__amdgpu_buffer_rsrc_t rs, int m, int j, f4u &x, f4u &y,
-                                          f4u &z)
+// The same descriptor as four scalar words, for the asm loads below.
+__device__ __forceinline__ f4u ref_desc(const float *ys, int m)
 {
-    x = __builtin_amdgcn_raw_buffer_load_b128(rs, 0, 4 * j, 0);
-    y = __builtin_amdgcn_raw_buffer_load_b128(rs, 0, 4 * (m + j), 0);
-    z = __builtin_amdgcn_raw_buffer_load_b128(rs, 0, 4 * (2 * m + j), 0);
+    const uint64_t p = (uint64_t)(uintptr_t)ys;
+    f4u d;
+    d.x = __builtin_amdgcn_readfirstlane((uint32_t)p);
+    d.y = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    d.z = (uint32_t)(12 * m);
+    d.w = 0x00020000u;
+    return d;
+}
+
+// Reference points j .. j+3 (x, y, z): three 16-byte loads, the same address on
+// every lane.  Issued from asm together with ref_wait so that each wait covers
+// exactly the group it needs: the compiler's own wait placement at this loop
+// depth sometimes drains every load in flight (vmcnt(0)), stalling each group
+// for a full memory round trip.  Every group issued here must be waited for
+// (ref_wait) before its registers die, or a late load could overwrite registers
+// the compiler has reused.
+__device__ __forceinline__ void ref_issue4(const f4u &desc, int m, int j, f4u &x, f4u &y, f4u &z)
+{
+    const int o0 = 4 * j, o1 = 4 * (m + j), o2 = 4 * (2 * m + j);
+    asm volatile("buffer_load_dwordx4 %0, off, %3, %4\n\t"
+                 "buffer_load_dwordx4 %1, off, %3, %5\n\t"
+                 "buffer_load_dwordx4 %2, off, %3, %6"
+                 : "=&v"(x), "=&v"(y), "=&v"(z)
+                 : "s"(desc), "s"(o0), "s"(o1), "s"(o2));
+}
+
+// Wait until all but the newest N vector-memory operations are complete; the
+// group's registers pass through the asm so no use can be scheduled before it.
+template <int N>
+__device__ __forceinline__ void ref_wait(f4u &x, f4u &y, f4u &z)
+{
+    static_assert(N == 0 || N == 3, "ref_wait<0> or ref_wait<3>");
+    if (N == 3)
+        asm volatile("s_waitcnt vmcnt(3)" : "+v"(x), "+v"(y), "+v"(z));
+    else
+        asm volatile("s_waitcnt vmcnt(0)" : "+v"(x), "+v"(y), "+v"(z));
 }
 
 // One float of the staged reference (index into the x, y, z arrays).
@@ -355,6 +380,7 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
     const uint32_t negc = 0u - (uint32_t)x0 * sx4;
     const int m = g.m;
     const __amdgpu_buffer_rsrc_t rs = ref_rsrc(a.ys, m);
+    const f4u desc = ref_desc(a.ys, m);
     const float4 *mine = a.scratch + (size_t)slot * a.scratch_stride;
     for (int c0 = 0; c0 < g.n; c0 += kBlock) {
         // work units of this chunk: (64-source group, part of its reference window);
@@ -398,13 +424,16 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             int j = j0;
             if (j + 4 <= j1) {
                 f4u ax, ay, az, bx, by, bz;
-                ref_load4(rs, m, j, ax, ay, az);
+                ref_issue4(desc, m, j, ax, ay, az);
                 for (; j + 8 <= j1; j += 8) {
-                    ref_load4(rs, m, j + 4, bx, by, bz);
+                    ref_issue4(desc, m, j + 4, bx, by, bz);
+                    ref_wait<3>(ax, ay, az);
                     vote4<CW>(hist, ax, ay, az, Px, Py, Pz, x0, np, Sy, Sz, sx4, sy4, negc);
-                    ref_load4(rs, m, min(j + 8, j1 - 4), ax, ay, az);
+                    ref_issue4(desc, m, min(j + 8, j1 - 4), ax, ay, az);
+                    ref_wait<3>(bx, by, bz);
                     vote4<CW>(hist, bx, by, bz, Px, Py, Pz, x0, np, Sy, Sz, sx4, sy4, negc);
                 }
+                ref_wait<0>(ax, ay, az);          // the last group issued, used or not
                 if (j + 4 <= j1) {
                     vote4<CW>(hist, ax, ay, az, Px, Py, Pz, x0, np, Sy, Sz, sx4, sy4, negc);
                     j += 4;
@@ -467,22 +496,70 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
     __syncthreads();
 }
 
-// Scan one slab: per-thread best (count, lowest position).  Positions are word
-// index * 2 + half, which orders bins exactly as their linear index does.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Largest counter of a slab (words4 uint4 of counters), workgroup-uniform.
 template <int CW>
-__device__ void scan_slab(const uint32_t *hist, int words, uint32_t pos0, uint32_t &bc,
-                          uint32_t &bp)
+__device__ uint32_t slab_max(const uint32_t *hist, int words4, uint32_t *scr)
 {
-    for (int w = threadIdx.x; w < words; w += kBlock) {
-        const uint32_t v = hist[w];
-        if (CW == 16) {
-            const uint32_t lo = v & 0xFFFFu, hi = v >> 16;
-            if (lo > bc) { bc = lo; bp = pos0 + 2u * w; }
-            if (hi > bc) { bc = hi; bp = pos0 + 2u * w + 1u; }
-        } else {
-            if (v > bc) { bc = v; bp = pos0 + (uint32_t)w; }
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint4 *h4 = reinterpret_cast<const uint4 *>(hist);
+    uint32_t mx = 0;
+    if (CW == 16) {
+        u16x2 m = {0, 0};
+        for (int w = tid; w < words4; w += kBlock) {
+            const uint4 v = h4[w];
+            m = __builtin_elementwise_max(m, __builtin_bit_cast(u16x2, v.x));
+            m = __builtin_elementwise_max(m, __builtin_bit_cast(u16x2, v.y));
+            m = __builtin_elementwise_max(m, __builtin_bit_cast(u16x2, v.z));
+            m = __builtin_elementwise_max(m, __builtin_bit_cast(u16x2, v.w));
+        }
+        mx = max((uint32_t)m.x, (uint32_t)m.y);
+    } else {
+        for (int w = tid; w < words4; w += kBlock) {
+            const uint4 v = h4[w];
+            mx = max(mx, max(max(v.x, v.y), max(v.z, v.w)));
         }
     }
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+    if (lane == 0) scr[8 + wave] = mx;
+    __syncthreads();
+    uint32_t r = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) r = max(r, scr[8 + w]);
+    __syncthreads();
+    return r;
+}
+
+// Lowest position (word index * 2 + half for 16-bit counters) whose count is c.
+template <int CW>
+__device__ uint32_t slab_first(const uint32_t *hist, int words4, uint32_t c, uint32_t pos0,
+                               uint32_t *scr)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint4 *h4 = reinterpret_cast<const uint4 *>(hist);
+    uint32_t best = 0xFFFFFFFFu;
+    for (int w = tid; w < words4 && best == 0xFFFFFFFFu; w += kBlock) {
+        const uint4 v = h4[w];
+        const uint32_t e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 3; q >= 0; --q) {
+            if (CW == 16) {
+                if ((e[q] >> 16) == c) best = 2u * (4u * w + q) + 1u;
+                if ((e[q] & 0xFFFFu) == c) best = 2u * (4u * w + q);
+            } else if (e[q] == c) {
+                best = 4u * w + q;
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, off, 64));
+    if (lane == 0) scr[8 + wave] = best;
+    __syncthreads();
+    uint32_t r = 0xFFFFFFFFu;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) r = min(r, scr[8 + w]);
+    __syncthreads();
+    return pos0 + r;
 }
 
 __device__ __forceinline__ float rho(int metric, float d, float dmetric, float d2, float eps,
@@ -606,23 +683,15 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
         __syncthreads();
         vote_slab<CW>(a, R, x0, np, hist, sorted, slot);
         __syncthreads();
-        uint32_t bc = 0, bp = 0xFFFFFFFFu;
+        // the slab's largest count first (cheap), and only when it beats the best of
+        // the earlier slabs its lowest position (a later slab never wins a tie: its
+        // positions are higher)
         const uint32_t pos0 = (uint32_t)x0 * Sy * RW * (CW == 16 ? 2u : 1u);
-        scan_slab<CW>(hist, words, pos0, bc, bp);
-        for (int off = 32; off > 0; off >>= 1)
-            better(bc, bp, __shfl_xor(bc, off, 64), __shfl_xor(bp, off, 64));
-        if (lane == 0) { scr[8 + 2 * wave] = bc; scr[9 + 2 * wave] = bp; }
-        __syncthreads();
-        if (wave == 0) {
-            uint32_t c = lane < kWaves ? scr[8 + 2 * lane] : 0u;
-            uint32_t l = lane < kWaves ? scr[9 + 2 * lane] : 0xFFFFFFFFu;
-            for (int off = 32; off > 0; off >>= 1)
-                better(c, l, __shfl_xor(c, off, 64), __shfl_xor(l, off, 64));
-            if (lane == 0) { scr[2] = c; scr[3] = l; }
+        const uint32_t smax = slab_max<CW>(hist, words4, scr);
+        if (smax > best_c) {
+            best_p = slab_first<CW>(hist, words4, smax, pos0, scr);
+            best_c = smax;
         }
-        __syncthreads();
-        const uint32_t sc = scr[2], sp = scr[3];
-        if (sc > best_c) { best_c = sc; best_p = sp; }
         __syncthreads();                      // scr / hist reused by the next slab
     }
 

@@ -62,6 +62,20 @@ dses_status ensure_target_grid(TargetRes *tm, float r, CellGrid *cg)
     return DSES_OK;
 }
 
+int64_t target_block_population(TargetRes *tm, const Params &p)
+{
+    std::lock_guard<std::mutex> gl(tm->grid_mu);
+    for (const auto &e : tm->pops)
+        if (e.delta == p.delta && std::equal(e.klo, e.klo + 3, p.klo) &&
+            std::equal(e.size, e.size + 3, p.size))
+            return e.pop;
+    TargetRes::Population e{p.delta, {p.klo[0], p.klo[1], p.klo[2]},
+                            {p.size[0], p.size[1], p.size[2]},
+                            ref_block_population(tm->host_aos.data(), tm->m, p)};
+    tm->pops.push_back(e);
+    return e.pop;
+}
+
 dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stream,
                                 const TargetRes::Stage **out)
 {

@@ -277,7 +277,7 @@ ServerImpl::~ServerImpl()
 dses_status ServerImpl::prepare(Request *r)
 {
     auto *tm = const_cast<TargetRes *>(r->target);
-    const int bits = counter_bound(tm->host_aos.data(), r->m, r->n, r->p) <= 65535 ? 16 : 32;
+    const int bits = target_block_population(tm, r->p) * r->n <= 65535 ? 16 : 32;
     Geom g;
     dses_status st = plan_geom(c, r->p, r->n, r->m, bits, &g);
     if (st != DSES_OK) return st;

@@ -1,21 +1,22 @@
 // DSES device kernels for CDNA4 (gfx950): input staging, the fused per-rotation
-// sweep (vote -> mode -> score) and candidate selection.
+// sweep (vote -> mode -> score), candidate selection and top-k.
 //
-// Sweep design (one workgroup of 16 wave64s per rotation):
-//  * Source points live in registers, one per lane; the rotation is applied once
-//    per point (FMA chain of the header's ROUND definition).
+// Sweep design (one workgroup of 16 wave64s per rotation, one workgroup per CU):
+//  * Source points are rotated and scaled once per rotation and bucket-sorted by
+//    x into a per-workgroup scratch slot; in the vote each lane holds one source.
 //  * Reference points are wave-uniform: every lane of a wave walks the same
-//    reference index, so the compiler loads them through the scalar unit into
-//    SGPRs and the vector ALU only does pair arithmetic.
+//    reference index of the x-sorted reference, restricted to the window whose
+//    pairs can land in the current slab.  They arrive through 16-byte buffer
+//    loads (same address on every lane), two groups of 4 in flight.
 //  * The vote array of Alg. 2 lives in LDS as 16-bit counters packed two per
 //    32-bit word (incremented with ds_add_u32 of 1 or 1<<16), so the 41^3 box of
-//    delta = 0.05 fits one 160 KB LDS allocation.  Larger boxes are swept in
-//    x-slabs that each fit LDS.  16-bit counters are used only when the host has
-//    proven that no bin can reach 2^16 votes (see counter_bound in api.hip);
-//    otherwise every counter is 32-bit.
-//  * The mode is an LDS scan (count, then lowest linear index) reduced with
-//    wave64 shuffles.
-//  * Scoring reuses the lanes' source points; the error sum is a fixed-order tree,
+//    delta = 0.05 fits one allocation.  Larger boxes are swept in x-slabs that
+//    each fit LDS.  16-bit counters are used only when the host has proven that
+//    no bin can reach 2^16 votes (see counter_bound in api.hip); otherwise every
+//    counter is 32-bit.
+//  * The mode per slab: the largest count by a packed 16-bit max over the slab,
+//    then, only when it beats the earlier slabs, its lowest linear index.
+//  * Scoring reuses the rotated sources; the error sum is a fixed-order tree,
 //    so a rotation's record does not depend on what else runs on the GPU.
 #include <hip/hip_runtime.h>
 
@@ -1080,15 +1081,48 @@ __global__ void k_stage_batch(const StageDesc *d, const int32_t *header)
     }
 }
 
-__global__ void __launch_bounds__(1024) k_select_batch(const SelectDesc *d, const int32_t *header)
+// The same selection by one wave64 with shuffles only.  It uses no LDS, so it
+// can start on a CU next to a sweep workgroup of another launch (the served
+// path overlaps launches) instead of waiting for a CU to drain.
+__device__ void select_wave(const dses_record *rec, int32_t K, const float *rot, float delta,
+                            DevResult *res, const uint32_t *status)
 {
-    __shared__ float se[16];
-    __shared__ int si[16], sk[16], sv[16];
+    const int lane = threadIdx.x;
+    float be = INFINITY;
+    int bi = 0, bk = -1, nvalid = 0;
+    for (int k = lane; k < K; k += 64) {
+        const dses_record r = rec[k];
+        if (r.votes == 0) continue;
+        ++nvalid;
+        if (sel_better(be, bi, bk, r.error, r.inliers, k)) { be = r.error; bi = r.inliers; bk = k; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const float oe = __shfl_xor(be, off, 64);
+        const int oi = __shfl_xor(bi, off, 64), ok = __shfl_xor(bk, off, 64);
+        if (sel_better(be, bi, bk, oe, oi, ok)) { be = oe; bi = oi; bk = ok; }
+        nvalid += __shfl_xor(nvalid, off, 64);
+    }
+    if (lane == 0) {
+        res->rot_index = bk;
+        res->n_valid = nvalid;
+        res->bad_input = status ? status[0] : 0u;
+        if (bk >= 0) {
+            const dses_record r = rec[bk];
+            res->votes = r.votes;
+            res->inliers = r.inliers;
+            res->error = r.error;
+            for (int a2 = 0; a2 < 3; ++a2) res->t[a2] = __fmul_rn((float)r.bin[a2], delta);
+            for (int e2 = 0; e2 < 9; ++e2) res->R[e2] = rot[9 * (size_t)bk + e2];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64) k_select_batch(const SelectDesc *d, const int32_t *header)
+{
     const int count = header[1];
     for (int inst = blockIdx.x; inst < count; inst += gridDim.x) {
         const SelectDesc sd = d[inst];
-        select_body(sd.rec, sd.k, sd.rot, sd.delta, sd.res, sd.status, se, si, sk, sv);
-        __syncthreads();
+        select_wave(sd.rec, sd.k, sd.rot, sd.delta, sd.res, sd.status);
     }
 }
 
@@ -1099,7 +1133,7 @@ hipError_t launch_batch_aux(const StageDesc *stage, const SelectDesc *sel, const
     if (which == 0)
         hipLaunchKernelGGL(k_stage_batch, dim3(16, gy), dim3(256), 0, stream, stage, header);
     else
-        hipLaunchKernelGGL(k_select_batch, dim3(gy), dim3(1024), 0, stream, sel, header);
+        hipLaunchKernelGGL(k_select_batch, dim3(gy), dim3(64), 0, stream, sel, header);
     return hipGetLastError();
 }
 

@@ -181,7 +181,7 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     opt = o;
     if (opt.memory_budget <= 0) opt.memory_budget = (int64_t)1 << 30;
     if (opt.max_inflight <= 0) opt.max_inflight = 64;
-    if (opt.aging == 0.0f) opt.aging = 1.0f;
+    if (opt.aging == 0.0f) opt.aging = 4.0f;
     if (opt.aging < 0.0f) opt.aging = 0.0f;
     max_slots = opt.max_inflight;
     grid = std::max(1, c->n_cu);

@@ -225,6 +225,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=WORKLOADS, default="c2")
     ap.add_argument("--scorer", default="auto")
+    ap.add_argument("--q", type=float, default=0.0,
+                    help="pruning of Alg. 2: score only rotations with M_k >= q M* (0: all)")
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="rotations of the oracle CPU baseline (-1: as many as about "
                          "2.2e10 point pairs, some 10 s on 16 cores; 0: skip)")
@@ -276,10 +278,11 @@ def main():
         rotset = dses.RotationSet(rot)
 
         def run(**kw):
-            return dses.register_resident(target, rotset, src, p.eps, scorer="df", **kw)
+            return dses.register_resident(target, rotset, src, p.eps, scorer="df", q=args.q,
+                                          **kw)
     else:
         def run(**kw):
-            return dses.register(src, tgt, rot, p.eps, scorer=args.scorer, **kw)
+            return dses.register(src, tgt, rot, p.eps, scorer=args.scorer, q=args.q, **kw)
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -303,7 +306,10 @@ def main():
     # 18 per transformed point; distance-field scoring replaces the score pairs by
     # one lookup per point
     score_pairs = 0.0 if args.scorer == "df" else 8.0 * n * m
-    flop_per_launch = (3.0 * n * m + score_pairs + 18.0 * n) * k
+    scored = k
+    if args.q > 0.0:                     # pruning: every rotation voted, the kept ones scored
+        scored = int(np.isfinite(run(records=True).records["error"]).sum())
+    flop_per_launch = (3.0 * n * m + 18.0 * n) * k + score_pairs * scored
     achieved = flop_per_launch / (sweep_ms * 1e-3) / 1e12
     traffic = load_traffic(args.workload)
     lat_ms = np.array(lat) * 1e3
@@ -321,7 +327,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "n_src": n, "n_ref": m, "rotations": k, "eps": p.eps,
-                   "metric": "trunc_l2", "scorer": args.scorer, "parallelism": "single GPU"},
+                   "metric": "trunc_l2", "scorer": args.scorer, "q": args.q,
+                   "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                        "p99": float(np.percentile(lat_ms, 99)), "path": "plain, one call"},
         "roofline": {"bound": "alu", "kernel": "k_sweep (vote + mode + score)",
@@ -333,6 +340,9 @@ def main():
                      "kernel_ms": sweep_ms},
         "result": {"rot_index": r.rot_index, "inliers": r.inliers, "error": r.error},
     }
+    if args.q > 0.0:
+        out["result"]["scored"] = scored
+        out["roofline"]["work"] += " (q > 0: score pairs only for the scored rotations)"
     if args.cpu_sample != 0:
         threads = min(16, len(os.sched_getaffinity(0)))
         sample = args.cpu_sample if args.cpu_sample > 0 else max(16, int(2.2e10 / (n * m)))

@@ -119,6 +119,12 @@ typedef struct {
                                  rotation index; the first equals the result); entries
                                  past the number of valid rotations have rot_index -1.
                                  Host memory, or device with DSES_DEVICE_PTRS          */
+    float q;                  /* pruning of Alg. 2 (Sec. IV-B): 0 -> score every
+                                 candidate; q in (0, 1] -> vote all rotations, then
+                                 score only those whose mode count M_k >= q M* (M* =
+                                 the largest M_k; compared in double precision), the
+                                 others keep their bin and votes with error +inf and
+                                 0 inliers and are never selected                     */
 } dses_options;
 
 #define DSES_TOPK_MAX 64

@@ -178,10 +178,25 @@ def topk(recs, k) -> np.ndarray:
     return out
 
 
-def register(src, tgt, rotations, eps, **kw):
+def prune_mask(recs, q) -> np.ndarray:
+    """Rotations scored under the pruning of Alg. 2 (Sec. IV-B): valid, with mode
+    count M_k >= q M*, M* the largest count; the comparison in double precision of
+    the counts and the single-precision q (the reading of the paper's "M >= q M*")."""
+    recs = np.ascontiguousarray(recs, RECORD_DTYPE)
+    votes = recs["votes"].astype(np.float64)
+    mstar = float(votes.max()) if len(votes) else 0.0
+    return recs["valid"].astype(bool) & (votes >= np.float64(np.float32(q)) * mstar)
+
+
+def register(src, tgt, rotations, eps, q=0.0, **kw):
     """Full Alg. 2: returns a dict {R, t, rot_index, inliers, error, votes, records}."""
     recs = records(src, tgt, rotations, eps, **kw)
-    best = select(recs)
+    if q > 0.0:
+        pruned = recs.copy()
+        pruned["valid"] = prune_mask(recs, q)
+        best = select(pruned)
+    else:
+        best = select(recs)
     delta = kw.get("delta") or eps
     rots = _f32(rotations, 9)
     if best < 0:

@@ -380,8 +380,9 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     const Params &p = job.p;
     void *records = o.records;
     const bool on_device = (o.flags & DSES_DEVICE_PTRS) != 0;
-    if (o.top_k < 0 || o.top_k > DSES_TOPK_MAX || (o.top_k > 0 && !o.topk)) {
-        set_error("top_k must be in 0..DSES_TOPK_MAX with a topk buffer");
+    if (o.top_k < 0 || o.top_k > DSES_TOPK_MAX || (o.top_k > 0 && !o.topk) ||
+        !(o.q >= 0.0f && o.q <= 1.0f)) {
+        set_error("top_k must be in 0..DSES_TOPK_MAX with a topk buffer, q in [0, 1]");
         return DSES_E_INVAL;
     }
     const int scorer = effective_scorer(job);
@@ -519,7 +520,14 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
                           static_cast<float *>(c->ys.ptr), static_cast<float *>(c->yt.ptr),
                           stream));
     rec_ev(1);
-    DSES_HIP(launch_sweep(a, scorer, grid, stream));
+    if (o.q > 0.0f) {
+        if ((st = c->prune.ensure(64)) != DSES_OK) return st;
+        uint32_t *pw = static_cast<uint32_t *>(c->prune.ptr);
+        DSES_HIP(launch_sweep(a, kScoreNone, grid, stream));
+        DSES_HIP(launch_score_pruned(a, scorer, o.q, pw, pw + 1, grid, stream));
+    } else {
+        DSES_HIP(launch_sweep(a, scorer, grid, stream));
+    }
     rec_ev(2);
     DSES_HIP(launch_select(a.rec, job.k, job.rot, p.delta, static_cast<DevResult *>(c->res.ptr),
                            bad, stream));
@@ -619,8 +627,9 @@ dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t
         }
         o = *opt;
     }
-    if (o.top_k < 0 || o.top_k > DSES_TOPK_MAX || (o.top_k > 0 && !o.topk)) {
-        set_error("top_k must be in 0..DSES_TOPK_MAX with a topk buffer");
+    if (o.top_k < 0 || o.top_k > DSES_TOPK_MAX || (o.top_k > 0 && !o.topk) ||
+        !(o.q >= 0.0f && o.q <= 1.0f)) {
+        set_error("top_k must be in 0..DSES_TOPK_MAX with a topk buffer, q in [0, 1]");
         return DSES_E_INVAL;
     }
     Params p;

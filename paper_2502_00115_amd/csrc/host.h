@@ -48,6 +48,7 @@ struct Context {
     // workspace of the plain path
     DevBuf in_src, in_tgt, in_rot, ys, yt, rec, res, status, grid_pts, grid_start, perm, tab, scratch;
     DevBuf topk_a, topk_b, topk_out;     // top-k passes and output staging
+    DevBuf prune;                        // q-pruning: M* and the work cursor
     DevResult *host_res = nullptr;       // pinned
     // timing
     bool timing_enabled = false;

@@ -52,6 +52,9 @@ struct Field {
 constexpr int kSortBuckets = 1024;      // per-rotation source buckets (1 bin unit wide)
 constexpr int kSortMax = 16384;         // largest source cloud that is bucket-sorted
 constexpr int kTabPerBin = 4;           // x-table entries per bin (reference windows)
+// Kernel scorer value for a vote-only sweep (records unscored: error +inf,
+// 0 inliers); the public scorers are DSES_SCORER_BRUTE / GRID / DF.
+constexpr int kScoreNone = 0;
 
 struct SweepArgs {
     const float *src;      // n x 3 AoS
@@ -138,6 +141,10 @@ hipError_t launch_select(const dses_record *rec, int32_t k, const float *rot, fl
 size_t topk_scratch_bytes(int32_t K, int32_t k);
 hipError_t launch_topk(const dses_record *rec, int32_t K, int32_t k, float delta, void *scr_a,
                        void *scr_b, dses_candidate *out, hipStream_t stream);
+// q-pruned scoring after a kScoreNone sweep: M* into *mstar, then score the
+// rotations with M_k >= q M* (both device words, the cursor cleared here).
+hipError_t launch_score_pruned(const SweepArgs &a, int scorer, float q, uint32_t *mstar,
+                               uint32_t *cursor, int grid, hipStream_t stream);
 hipError_t launch_clear(uint32_t *p, int32_t words, hipStream_t stream);
 hipError_t launch_sweep_batch(const BatchArgs &b, int scorer, int grid, hipStream_t stream);
 // which = 0: batched staging, 1: batched selection

@@ -654,70 +654,34 @@ __device__ __forceinline__ float df_lookup(const Field &f, float qx, float qy, f
     return f.r;
 }
 
-// Vote, mode and score one rotation k with the whole workgroup; `slot` selects
-// the workgroup's source-sort scratch.  Writes a.rec[k].
-template <int CW, int SCORER>
-__device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
+// Score candidate {R_k, t_k = b delta} (Eq. (1)/(2): sum over the source of the
+// robust distance to the nearest reference point, and the inliers) with the
+// whole workgroup, and write its record.  kScoreNone writes the record unscored
+// (error +inf, 0 inliers).
+template <int SCORER>
+__device__ void score_candidate(const SweepArgs &a, int k, const float *R, int bx, int by, int bz,
+                                uint32_t votes, uint32_t *lds)
 {
     const Geom &g = a.g;
     uint32_t *hist = lds;
     uint32_t *scr = lds + kHistWordsMax;          // kScratchWords words
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t Sy = g.size[1];
-    const uint32_t RW = (uint32_t)g.row_words;
-    const bool sorted = a.scratch != nullptr;
-  {
-    float R[9];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) R[e] = kc(a.rot)[9 * k + e];
-    if (sorted) sort_sources(a, R, lds, scr, slot);
-
-    // ---------------- vote + mode over the slabs ----------------
-    uint32_t best_c = 0, best_p = 0xFFFFFFFFu;
-    for (int slab = 0; slab < g.nslabs; ++slab) {
-        const int x0 = slab * g.pps;
-        const int np = min(g.pps, g.size[0] - x0);
-        const int words = np * (int)Sy * (int)RW;
-        const int words4 = (words + 3) >> 2;
-        uint4 *h4 = reinterpret_cast<uint4 *>(hist);
-        for (int w = tid; w < words4; w += kBlock) h4[w] = make_uint4(0, 0, 0, 0);
-        __syncthreads();
-        vote_slab<CW>(a, R, x0, np, hist, sorted, slot);
-        __syncthreads();
-        // the slab's largest count first (cheap), and only when it beats the best of
-        // the earlier slabs its lowest position (a later slab never wins a tie: its
-        // positions are higher)
-        const uint32_t pos0 = (uint32_t)x0 * Sy * RW * (CW == 16 ? 2u : 1u);
-        const uint32_t smax = slab_max<CW>(hist, words4, scr);
-        if (smax > best_c) {
-            best_p = slab_first<CW>(hist, words4, smax, pos0, scr);
-            best_c = smax;
-        }
-        __syncthreads();                      // scr / hist reused by the next slab
-    }
-
-    dses_record rec;
-    if (best_c == 0) {
+    if (SCORER == kScoreNone) {
         if (tid == 0) {
-            rec.bin[0] = rec.bin[1] = rec.bin[2] = 0;
-            rec.votes = 0;
+            dses_record rec;
+            rec.bin[0] = bx;
+            rec.bin[1] = by;
+            rec.bin[2] = bz;
+            rec.votes = votes;
             rec.inliers = 0;
             rec.error = INFINITY;
             a.rec[k] = rec;
         }
         return;
     }
-    // position -> box-relative bin
-    const uint32_t w = CW == 16 ? best_p >> 1 : best_p;
-    const uint32_t row = w / RW;
-    const int cz = (int)((w - row * RW) * (CW == 16 ? 2u : 1u) + (CW == 16 ? (best_p & 1u) : 0u));
-    const int cy = (int)(row % Sy), cx = (int)(row / Sy);
-    const int bx = cx + g.klo[0], by = cy + g.klo[1], bz = cz + g.klo[2];
     const float tx = __fmul_rn((float)bx, g.delta);
     const float ty = __fmul_rn((float)by, g.delta);
     const float tz = __fmul_rn((float)bz, g.delta);
-
-    // ---------------- score the candidate {R, t*} ----------------
     const bool want_l1 = g.metric == DSES_TRUNC_L1;
     float err = 0.0f;
     int inl = 0;
@@ -793,15 +757,78 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
         float e = 0.0f;
         int c = 0;
         for (int q = 0; q < kWaves; ++q) { e += fscr[64 + q]; c += (int)scr[96 + q]; }
+        dses_record rec;
         rec.bin[0] = bx;
         rec.bin[1] = by;
         rec.bin[2] = bz;
-        rec.votes = best_c;
+        rec.votes = votes;
         rec.inliers = c;
         rec.error = e;
         a.rec[k] = rec;
     }
-    __syncthreads();                          // LDS scratch reused by the next rotation
+    __syncthreads();                          // LDS scratch reused by the caller
+}
+
+// Vote, mode and score one rotation k with the whole workgroup; `slot` selects
+// the workgroup's source-sort scratch.  Writes a.rec[k].
+template <int CW, int SCORER>
+__device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
+{
+    const Geom &g = a.g;
+    uint32_t *hist = lds;
+    uint32_t *scr = lds + kHistWordsMax;          // kScratchWords words
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t Sy = g.size[1];
+    const uint32_t RW = (uint32_t)g.row_words;
+    const bool sorted = a.scratch != nullptr;
+  {
+    float R[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) R[e] = kc(a.rot)[9 * k + e];
+    if (sorted) sort_sources(a, R, lds, scr, slot);
+
+    // ---------------- vote + mode over the slabs ----------------
+    uint32_t best_c = 0, best_p = 0xFFFFFFFFu;
+    for (int slab = 0; slab < g.nslabs; ++slab) {
+        const int x0 = slab * g.pps;
+        const int np = min(g.pps, g.size[0] - x0);
+        const int words = np * (int)Sy * (int)RW;
+        const int words4 = (words + 3) >> 2;
+        uint4 *h4 = reinterpret_cast<uint4 *>(hist);
+        for (int w = tid; w < words4; w += kBlock) h4[w] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        vote_slab<CW>(a, R, x0, np, hist, sorted, slot);
+        __syncthreads();
+        // the slab's largest count first (cheap), and only when it beats the best of
+        // the earlier slabs its lowest position (a later slab never wins a tie: its
+        // positions are higher)
+        const uint32_t pos0 = (uint32_t)x0 * Sy * RW * (CW == 16 ? 2u : 1u);
+        const uint32_t smax = slab_max<CW>(hist, words4, scr);
+        if (smax > best_c) {
+            best_p = slab_first<CW>(hist, words4, smax, pos0, scr);
+            best_c = smax;
+        }
+        __syncthreads();                      // scr / hist reused by the next slab
+    }
+
+    dses_record rec;
+    if (best_c == 0) {
+        if (tid == 0) {
+            rec.bin[0] = rec.bin[1] = rec.bin[2] = 0;
+            rec.votes = 0;
+            rec.inliers = 0;
+            rec.error = INFINITY;
+            a.rec[k] = rec;
+        }
+        return;
+    }
+    // position -> box-relative bin
+    const uint32_t w = CW == 16 ? best_p >> 1 : best_p;
+    const uint32_t row = w / RW;
+    const int cz = (int)((w - row * RW) * (CW == 16 ? 2u : 1u) + (CW == 16 ? (best_p & 1u) : 0u));
+    const int cy = (int)(row % Sy), cx = (int)(row / Sy);
+    const int bx = cx + g.klo[0], by = cy + g.klo[1], bz = cz + g.klo[2];
+    score_candidate<SCORER>(a, k, R, bx, by, bz, best_c, lds);
   }
 }
 
@@ -827,16 +854,96 @@ hipError_t launch_sweep(const SweepArgs &a, int scorer, int grid, hipStream_t st
     if (grid > a.k) grid = a.k;
     if (a.g.counter_bits == 16) {
         switch (scorer) {
+        case kScoreNone: return launch_one<16, kScoreNone>(a, grid, stream);
         case DSES_SCORER_BRUTE: return launch_one<16, DSES_SCORER_BRUTE>(a, grid, stream);
         case DSES_SCORER_GRID: return launch_one<16, DSES_SCORER_GRID>(a, grid, stream);
         default: return launch_one<16, DSES_SCORER_DF>(a, grid, stream);
         }
     }
     switch (scorer) {
+    case kScoreNone: return launch_one<32, kScoreNone>(a, grid, stream);
     case DSES_SCORER_BRUTE: return launch_one<32, DSES_SCORER_BRUTE>(a, grid, stream);
     case DSES_SCORER_GRID: return launch_one<32, DSES_SCORER_GRID>(a, grid, stream);
     default: return launch_one<32, DSES_SCORER_DF>(a, grid, stream);
     }
+}
+
+// --------------------------------------------------------------------------
+// q-pruned scoring (the pruning step of Alg. 2): after a vote-only sweep
+// (kScoreNone records), M* = the largest vote count, and only rotations with
+// M_k >= q M* are scored.  The comparison is made in double precision on the
+// integer counts and the float q, so it is exact and reproducible on the host.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_max_votes(const dses_record *rec, int32_t K,
+                                                    uint32_t *mstar, uint32_t *cursor)
+{
+    __shared__ uint32_t sm[16];
+    uint32_t m = 0;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) m = max(m, rec[k].votes);
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t r = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = max(r, sm[w]);
+        *mstar = r;
+        *cursor = 0u;                    // work cursor of the pruned scoring
+    }
+}
+
+__device__ __forceinline__ bool keep_candidate(uint32_t votes, uint32_t mstar, float q)
+{
+    return votes > 0u && (double)votes >= (double)q * (double)mstar;
+}
+
+constexpr int kPruneChunk = 32;          // rotations per cursor fetch
+
+template <int SCORER>
+__global__ void __launch_bounds__(kBlock) k_score_pruned(SweepArgs a, float q,
+                                                         const uint32_t *mstar, uint32_t *cursor)
+{
+    __shared__ __align__(16) uint32_t lds[kLdsWords];
+    const uint32_t ms = __builtin_amdgcn_readfirstlane(*(kint)(const int32_t *)mstar);
+    for (;;) {
+        if (threadIdx.x == 0) lds[kLdsWords - 1] = atomicAdd(cursor, (uint32_t)kPruneChunk);
+        __syncthreads();
+        const int k0 = __builtin_amdgcn_readfirstlane((int)lds[kLdsWords - 1]);
+        __syncthreads();
+        if (k0 >= a.k) break;
+        const int k1 = min(a.k, k0 + kPruneChunk);
+        for (int k = k0; k < k1; ++k) {
+            const dses_record r = a.rec[k];
+            if (!keep_candidate(r.votes, ms, q)) continue;
+            float R[9];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) R[e] = kc(a.rot)[9 * k + e];
+            score_candidate<SCORER>(a, k, R, r.bin[0], r.bin[1], r.bin[2], r.votes, lds);
+        }
+    }
+}
+
+hipError_t launch_score_pruned(const SweepArgs &a, int scorer, float q, uint32_t *mstar,
+                               uint32_t *cursor, int grid, hipStream_t stream)
+{
+    if (a.k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_max_votes, dim3(1), dim3(1024), 0, stream,
+                       static_cast<const dses_record *>(a.rec), a.k, mstar, cursor);
+    if (grid > a.k) grid = a.k;
+    switch (scorer) {
+    case DSES_SCORER_BRUTE:
+        hipLaunchKernelGGL(k_score_pruned<DSES_SCORER_BRUTE>, dim3(grid), dim3(kBlock), 0, stream,
+                           a, q, mstar, cursor);
+        break;
+    case DSES_SCORER_GRID:
+        hipLaunchKernelGGL(k_score_pruned<DSES_SCORER_GRID>, dim3(grid), dim3(kBlock), 0, stream,
+                           a, q, mstar, cursor);
+        break;
+    default:
+        hipLaunchKernelGGL(k_score_pruned<DSES_SCORER_DF>, dim3(grid), dim3(kBlock), 0, stream,
+                           a, q, mstar, cursor);
+        break;
+    }
+    return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------

@@ -67,6 +67,10 @@ def test_argument_errors_need_no_gpu(libpath):
         assert e.value.status == dses.DSES_E_INVAL, (kw, e.value)
     with pytest.raises(ValueError):
         dses.register(np.zeros((4, 2)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05)
+    for q in (-0.1, 1.5, float("nan")):
+        with pytest.raises(dses.DsesError) as e:
+            dses.register(np.zeros((3, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05, q=q)
+        assert e.value.status == dses.DSES_E_INVAL, (q, e.value)
     item = {"src": np.zeros((3, 3)), "tgt": np.zeros((4, 3)),
             "rotations": np.eye(3).reshape(1, 9), "eps": 0.05}
     for kw in ({"parts_max": 9}, {"parts_max": -1}, {"tile_rot": -2}):

@@ -289,6 +289,34 @@ def test_topk_order_and_first_equals_select():
             left["valid"][q] = 0
 
 
+def test_prune_mask_by_hand():
+    """Pruning of Alg. 2: keep valid rotations with M_k >= q M* (float32 q, exact
+    products in double)."""
+    recs = np.zeros(5, oracle.RECORD_DTYPE)
+    recs["valid"] = [1, 1, 0, 1, 1]
+    recs["votes"] = [5, 10, 0, 7, 10]
+    np.testing.assert_array_equal(oracle.prune_mask(recs, 0.0), [1, 1, 0, 1, 1])
+    # float32(0.7) * 10 = 6.99999988 <= 7: rotation 3 kept; float32(0.71) * 10 > 7: dropped
+    np.testing.assert_array_equal(oracle.prune_mask(recs, 0.7), [0, 1, 0, 1, 1])
+    np.testing.assert_array_equal(oracle.prune_mask(recs, 0.71), [0, 1, 0, 0, 1])
+    np.testing.assert_array_equal(oracle.prune_mask(recs, 1.0), [0, 1, 0, 0, 1])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_pruned_selection_matches_a_filtered_argmin(seed):
+    p = synth.make_c1(seed)
+    recs = oracle.records(p.src, p.tgt, p.rotations, p.eps)
+    valid = recs["valid"].astype(bool)
+    mx = recs["votes"][valid].max()
+    for q in (1.0, 0.6):
+        keep = [k for k in range(len(recs)) if valid[k] and recs["votes"][k] >= np.float32(q) * mx]
+        expect = min(keep, key=lambda k: (recs["error"][k], -recs["inliers"][k], k))
+        assert oracle.register(p.src, p.tgt, p.rotations, p.eps, q=q)["rot_index"] == expect
+    # q = 0 and a vanishing q keep everything
+    full = oracle.register(p.src, p.tgt, p.rotations, p.eps)["rot_index"]
+    assert oracle.register(p.src, p.tgt, p.rotations, p.eps, q=1e-9)["rot_index"] == full
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_exact_recovery(seed):
     """Noise-free exact subset, true rotation on the list and t* on the lattice:

@@ -237,6 +237,8 @@ def main():
                     help="c4: write per-request arrival, plain and served latency (JSON)")
     ap.add_argument("--slice-mpairs", type=int, default=0,
                     help="c4: server work per slice, millions of pairs (0: library default)")
+    ap.add_argument("--lds-probe", action="store_true",
+                    help="print the device's LDS atomic throughput (vote ceiling) and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain elementwise copy of 256 MiB (counter calibration)")
     args = ap.parse_args()
@@ -249,6 +251,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "torch.add(a, 1.0, out=b)", "bytes_read": 4 * a.numel(),
                           "bytes_written": 4 * b.numel()}), flush=True)
+        return
+    if args.lds_probe:
+        from paper_2502_00115_amd import dses
+        print(json.dumps({"lds_atomics": {pat: dses.measure_lds_atomics(pat)
+                                          for pat in ("conflict_free", "random")}}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "

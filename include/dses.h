@@ -300,6 +300,19 @@ typedef struct {
 dses_status dses_batch_last_config(dses_batch_config *out);
 
 /* ---------------------------------------------------------------------------- */
+/* Diagnostics                                                                  */
+/* ---------------------------------------------------------------------------- */
+/* LDS atomic throughput of this device, the ceiling of the vote's counter
+ * increments (vendors do not publish it): one 1,024-thread workgroup per CU with
+ * a 160 KB LDS allocation, every lane issuing ds_add_u32 of 1; pattern 0 sends
+ * each wave's 64 lanes to 64 distinct banks, pattern 1 to pseudo-random words
+ * of the allocation (the vote's pattern).  Returns increments per second for the
+ * whole device and, if per_cu_per_cycle is not NULL, per CU per clock cycle (at
+ * the device's reported peak clock).  Takes tens of milliseconds. */
+dses_status dses_measure_lds_atomics(int32_t pattern, double *adds_per_second,
+                                     double *per_cu_per_cycle);
+
+/* ---------------------------------------------------------------------------- */
 /* Serving: a request loop with memory-based admission and continuous batching. */
 /* ---------------------------------------------------------------------------- */
 typedef struct dses_server dses_server;

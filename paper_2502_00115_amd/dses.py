@@ -28,7 +28,7 @@ EXPORTED = [
     "dses_last_error", "dses_init", "dses_version", "dses_kernel_stats", "dses_register",
     "dses_target_create", "dses_target_destroy", "dses_target_field", "dses_rotations_create",
     "dses_rotations_destroy", "dses_register_resident", "dses_register_batch",
-    "dses_batch_last_config",
+    "dses_batch_last_config", "dses_measure_lds_atomics",
     "dses_server_create", "dses_server_submit", "dses_server_wait", "dses_server_poll",
     "dses_server_timing", "dses_server_destroy",
 ]
@@ -127,6 +127,8 @@ def lib():
         L.dses_register_resident.argtypes = [vp, vp, vp, i64, f, i32, C.POINTER(Options),
                                              C.POINTER(Result)]
         L.dses_batch_last_config.argtypes = [C.POINTER(BatchConfig)]
+        L.dses_measure_lds_atomics.argtypes = [i32, C.POINTER(C.c_double),
+                                               C.POINTER(C.c_double)]
         L.dses_register_batch.argtypes = [C.POINTER(Problem), i32, C.POINTER(BatchOpts),
                                           C.POINTER(Result), C.POINTER(i32)]
         L.dses_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(vp)]
@@ -420,6 +422,14 @@ def register_batch(problems, *, scorer="auto", use_graph=True, tile_rot=0, parts
     out = [_result(res[i], _records_out(bufs[i]) if records else None)
            if st[i] == DSES_OK else None for i in range(len(problems))]
     return out, [int(v) for v in st]
+
+
+def measure_lds_atomics(pattern: str = "random") -> dict:
+    """LDS atomic throughput of the device (dses_measure_lds_atomics)."""
+    a, b = C.c_double(), C.c_double()
+    _check(lib().dses_measure_lds_atomics({"conflict_free": 0, "random": 1}[pattern],
+                                          C.byref(a), C.byref(b)))
+    return {"adds_per_s": a.value, "per_cu_per_cycle": b.value}
 
 
 def batch_last_config() -> dict:

@@ -82,3 +82,11 @@ def test_df_error_within_lipschitz_bound_of_exact():
     np.testing.assert_array_equal(exact.records["bin"], approx.records["bin"])
     assert np.all(np.abs(exact.records["error"] - approx.records["error"]) <= bound)
     assert approx.rot_index == p.true_index
+
+
+def test_lds_atomic_probe_runs():
+    free = dses.measure_lds_atomics("conflict_free")
+    rnd = dses.measure_lds_atomics("random")
+    for r in (free, rnd):
+        assert r["adds_per_s"] > 1e11 and r["per_cu_per_cycle"] > 0.0
+    assert rnd["adds_per_s"] <= free["adds_per_s"] * 1.05

@@ -52,6 +52,13 @@
  *   DSES_INLIERS   error = N - inliers  (the L0^{m1} objective of Eq. (3), Thm. 3)
  *   DSES_TLS       error = sum_i min(d_i^2, tau^2)
  *   DSES_TRUNC_L1  error = sum_i min(min_j ||q_i - y_j||_1, tau)
+ *   DSES_TRUNC_LP  error = sum_i min(d_i, tau)^p, p in (0, 1] (dses_options.p; the
+ *                  Lp, p < 1, sparsity objectives the paper's "any norm" allows)
+ *   DSES_VOTES     no scoring: candidates are ranked by their mode count M_k alone
+ *                  (Thm. 3: under its separation condition M_k is the L0^{m1}
+ *                  inlier count of {R_k, t_k}); records and results carry
+ *                  error 0 and inliers = M_k, so the selection is the largest
+ *                  M_k, ties to the lower rotation index
  * inliers always counts d_i < eps with the Euclidean d_i.  All scoring runs in
  * float32; ties in the final selection go to more inliers, then the lower
  * rotation index (the paper is silent on ties).
@@ -83,7 +90,9 @@ typedef enum {
     DSES_TRUNC_L2 = 0,
     DSES_INLIERS = 1,
     DSES_TLS = 2,
-    DSES_TRUNC_L1 = 3
+    DSES_TRUNC_L1 = 3,
+    DSES_TRUNC_LP = 4,        /* dses_register / dses_register_resident only          */
+    DSES_VOTES = 5            /* dses_register / dses_register_resident only          */
 } dses_metric;
 
 /* How the per-candidate nearest-neighbour term of Eq. (2) is evaluated. */
@@ -124,7 +133,9 @@ typedef struct {
                                  score only those whose mode count M_k >= q M* (M* =
                                  the largest M_k; compared in double precision), the
                                  others keep their bin and votes with error +inf and
-                                 0 inliers and are never selected                     */
+                                 0 inliers and are never selected (not with
+                                 DSES_VOTES)                                          */
+    float p;                  /* exponent of DSES_TRUNC_LP, in (0, 1]; 0 -> 0.5        */
 } dses_options;
 
 #define DSES_TOPK_MAX 64

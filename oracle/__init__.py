@@ -26,7 +26,7 @@ import numpy as np
 
 from .build import LIB, build_oracle
 
-METRICS = {"trunc_l2": 0, "inliers": 1, "tls": 2, "trunc_l1": 3}
+METRICS = {"trunc_l2": 0, "inliers": 1, "tls": 2, "trunc_l1": 3, "trunc_lp": 4, "votes": 5}
 
 RECORD_DTYPE = np.dtype([("bin", "<i4", (3,)), ("votes", "<u4"), ("inliers", "<i4"),
                          ("boundary", "<i4"), ("error", "<f8"), ("valid", "<i4"),
@@ -52,8 +52,8 @@ def lib():
         L.orc_df_build.argtypes = [fp, C.c_int32, C.c_float, C.c_int32, C.c_int32, fp, fp, fp, dp]
         L.orc_df_build.restype = C.c_int
         L.orc_records.argtypes = [fp, C.c_int32, fp, C.c_int32, fp, C.c_int32, ip, C.c_int32,
-                                  C.c_float, C.c_float, C.c_float, fp, fp, C.c_int32, dp,
-                                  C.c_int32, fp, fp, C.c_int32, C.c_void_p]
+                                  C.c_float, C.c_float, C.c_float, fp, fp, C.c_int32, C.c_float,
+                                  dp, C.c_int32, fp, fp, C.c_int32, C.c_void_p]
         L.orc_records.restype = C.c_int
         L.orc_select.argtypes = [C.c_void_p, C.c_int32]
         L.orc_select.restype = C.c_int32
@@ -129,7 +129,7 @@ def df_build(tgt, r, res, threads=0) -> DistanceField:
 
 
 def records(src, tgt, rotations, eps, *, delta=None, tau=None, t_min=None, t_max=None,
-            metric="trunc_l2", which=None, df: DistanceField | None = None, threads=0):
+            metric="trunc_l2", p=0.5, which=None, df: DistanceField | None = None, threads=0):
     """One Alg. 2 candidate record per rotation (or per listed rotation index)."""
     src, tgt = _f32(src, 3), _f32(tgt, 3)
     rots = _f32(rotations, 9)
@@ -154,7 +154,7 @@ def records(src, tgt, rotations, eps, *, delta=None, tau=None, t_min=None, t_max
                            None if which is None else _p(which, C.c_int32), count,
                            C.c_float(eps), C.c_float(delta), C.c_float(tau),
                            _p(t_min, C.c_float), _p(t_max, C.c_float), METRICS[metric],
-                           fld_p, res, lo_p, inv_p, threads, out.ctypes.data)
+                           C.c_float(p), fld_p, res, lo_p, inv_p, threads, out.ctypes.data)
     if rc:
         raise ValueError("oracle rejected the input")
     return out

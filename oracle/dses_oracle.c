@@ -27,7 +27,8 @@
 #include <string.h>
 #include <unistd.h>
 
-enum { ORC_TRUNC_L2 = 0, ORC_INLIERS = 1, ORC_TLS = 2, ORC_TRUNC_L1 = 3 };
+enum { ORC_TRUNC_L2 = 0, ORC_INLIERS = 1, ORC_TLS = 2, ORC_TRUNC_L1 = 3, ORC_TRUNC_LP = 4,
+       ORC_VOTES = 5 };
 
 /* Per-rotation outcome of Alg. 2, one row of the candidate list. */
 typedef struct {
@@ -149,14 +150,17 @@ void orc_nn(const double *q, int32_t nq, const float *tgt, int32_t m, int32_t l1
     for (int32_t i = 0; i < nq; ++i) out[i] = nn_dist(q + 3 * i, tgt, m, l1);
 }
 
-/* Robust per-point error rho(d) for the metrics of Sec. III / IV-B.         */
-static double rho(int metric, double d, double tau, double eps)
+/* Robust per-point error rho(d) for the metrics of Sec. III / IV-B; lp is the */
+/* exponent of the truncated Lp objective (p < 1: the sparsity norms the paper */
+/* admits as "any desired norm").                                             */
+static double rho(int metric, double d, double tau, double eps, double lp)
 {
     switch (metric) {
     case ORC_TRUNC_L2: return d < tau ? d : tau;                    /* sum min(d, tau)     */
     case ORC_TLS:      return d < tau ? d * d : tau * tau;          /* sum min(d^2, tau^2) */
     case ORC_INLIERS:  return d < eps ? 0.0 : 1.0;                  /* L0^{m1}: N - inliers */
     case ORC_TRUNC_L1: return d < tau ? d : tau;                    /* with the L1 NN dist  */
+    case ORC_TRUNC_LP: return pow(d < tau ? d : tau, lp);           /* sum min(d, tau)^p   */
     default:           return NAN;
     }
 }
@@ -168,7 +172,7 @@ static double rho(int metric, double d, double tau, double eps)
 /* ------------------------------------------------------------------------ */
 static void score_candidate(const float *src, int32_t n, const float *tgt, int32_t m,
                             const float *R, const double *t, int metric, double eps, double tau,
-                            orc_record *rec)
+                            double lp, orc_record *rec)
 {
     double err = 0.0;
     int32_t inl = 0, bnd = 0;
@@ -182,7 +186,7 @@ static void score_candidate(const float *src, int32_t n, const float *tgt, int32
         double d = metric == ORC_TRUNC_L1 ? nn_dist(q, tgt, m, 1) : d2;
         if (d2 < eps) ++inl;
         if (fabs(d2 - eps) <= 1e-6) ++bnd;
-        err += rho(metric, d, tau, eps);
+        err += rho(metric, d, tau, eps, lp);
     }
     rec->inliers = inl;
     rec->boundary = bnd;
@@ -282,9 +286,9 @@ int orc_df_build(const float *tgt, int32_t m, float r, int32_t res, int32_t nthr
 /* single precision (the same rotate_f32 chain, then + t), its voxel decided  */
 /* by df_voxel_of(); outside the grid the distance exceeds r, so D = r.       */
 static void score_candidate_df(const float *src, int32_t n, const float *R, const float *tf,
-                               int metric, double eps, double tau, float r, int32_t res,
-                               const float *lo, const float *inv, const double *field,
-                               orc_record *rec)
+                               int metric, double eps, double tau, double lp, float r,
+                               int32_t res, const float *lo, const float *inv,
+                               const double *field, orc_record *rec)
 {
     double err = 0.0;
     int32_t inl = 0, bnd = 0;
@@ -298,7 +302,7 @@ static void score_candidate_df(const float *src, int32_t n, const float *R, cons
                        : (double)r;
         if (D < eps) ++inl;
         if (fabs(D - eps) <= 1e-6) ++bnd;
-        err += rho(metric, D, tau, eps);
+        err += rho(metric, D, tau, eps, lp);
     }
     rec->inliers = inl;
     rec->boundary = bnd;
@@ -312,7 +316,7 @@ typedef struct {
     const float *src; int32_t n; const float *tgt; int32_t m;
     const float *rots; const int32_t *which; int32_t count;
     float delta; const int32_t *k_lo; const int32_t *size;
-    int metric; double eps, tau;
+    int metric; double eps, tau, lp;
     /* distance-field mode (field == NULL: brute force) */
     const double *field; float r; int32_t res; const float *lo; const float *inv;
     orc_record *out;
@@ -334,16 +338,23 @@ static void *reg_worker(void *arg)
                               hist, rec->bin);
         rec->valid = rec->votes > 0;
         if (!rec->valid) { rec->error = INFINITY; continue; }
+        if (jb->metric == ORC_VOTES) {
+            /* Thm. 3 ranking: no scoring, the mode count stands for the L0^{m1}
+             * inlier count and the error is 0 for every valid candidate */
+            rec->inliers = (int32_t)rec->votes;
+            rec->error = 0.0;
+            continue;
+        }
         if (jb->field) {
             float tf[3];
             for (int a = 0; a < 3; ++a) tf[a] = (float)rec->bin[a] * jb->delta;
-            score_candidate_df(jb->src, jb->n, R, tf, jb->metric, jb->eps, jb->tau, jb->r, jb->res,
-                               jb->lo, jb->inv, jb->field, rec);
+            score_candidate_df(jb->src, jb->n, R, tf, jb->metric, jb->eps, jb->tau, jb->lp, jb->r,
+                               jb->res, jb->lo, jb->inv, jb->field, rec);
         } else {
             double t[3];
             for (int a = 0; a < 3; ++a) t[a] = (double)rec->bin[a] * (double)jb->delta;
             score_candidate(jb->src, jb->n, jb->tgt, jb->m, R, t, jb->metric, jb->eps, jb->tau,
-                            rec);
+                            jb->lp, rec);
         }
     }
     free(hist);
@@ -357,12 +368,13 @@ static void *reg_worker(void *arg)
  */
 int orc_records(const float *src, int32_t n, const float *tgt, int32_t m, const float *rots,
                 int32_t k, const int32_t *which, int32_t count, float eps, float delta, float tau,
-                const float *t_min, const float *t_max, int32_t metric, const double *field,
-                int32_t res, const float *lo, const float *inv, int32_t nthreads,
-                orc_record *out)
+                const float *t_min, const float *t_max, int32_t metric, float lp,
+                const double *field, int32_t res, const float *lo, const float *inv,
+                int32_t nthreads, orc_record *out)
 {
     int32_t k_lo[3], size[3];
     if (n <= 0 || m <= 0 || k <= 0 || count < 0 || !(eps > 0.0f)) return -1;
+    if (metric < ORC_TRUNC_L2 || metric > ORC_VOTES || !(lp > 0.0f && lp <= 1.0f)) return -1;
     if (orc_box(delta, t_min, t_max, k_lo, size)) return -1;
     if (which)
         for (int32_t u = 0; u < count; ++u)
@@ -376,7 +388,7 @@ int orc_records(const float *src, int32_t n, const float *tgt, int32_t m, const 
     float r = eps > tau ? eps : tau;
     for (int w = 0; w < nt; ++w) {
         jobs[w] = (reg_job){src, n, tgt, m, rots, which, count, delta, k_lo, size, metric,
-                            (double)eps, (double)tau, field, r, res, lo, inv, out,
+                            (double)eps, (double)tau, (double)lp, field, r, res, lo, inv, out,
                             (int32_t)((int64_t)count * w / nt),
                             (int32_t)((int64_t)count * (w + 1) / nt)};
         pthread_create(&th[w], NULL, reg_worker, &jobs[w]);

@@ -103,7 +103,7 @@ dses_status resolve_params(float eps, int metric, float delta_t, float tau, cons
         set_error("eps must be positive and finite");
         return DSES_E_INVAL;
     }
-    if (metric < DSES_TRUNC_L2 || metric > DSES_TRUNC_L1) {
+    if (metric < DSES_TRUNC_L2 || metric > DSES_VOTES) {
         set_error("unknown metric");
         return DSES_E_INVAL;
     }
@@ -157,6 +157,7 @@ dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, i
     g->tau = p.tau;
     g->r = p.r;
     g->metric = p.metric;
+    g->lp = p.lp;
     for (int a = 0; a < 3; ++a) { g->klo[a] = p.klo[a]; g->size[a] = p.size[a]; }
     g->counter_bits = counter_bits;
     g->row_words = counter_bits == 16 ? (p.size[2] + 1) / 2 : p.size[2];
@@ -360,8 +361,23 @@ bool build_x_table(const float *tgt, const std::vector<int32_t> &perm, float s, 
     return true;
 }
 
+dses_status apply_metric_options(const dses_options &o, Params *p)
+{
+    if (!(o.p >= 0.0f && o.p <= 1.0f)) {
+        set_error("the Lp exponent p must be in (0, 1] (0: default 0.5)");
+        return DSES_E_INVAL;
+    }
+    p->lp = o.p > 0.0f ? o.p : 0.5f;
+    if (p->metric == DSES_VOTES && o.q > 0.0f) {
+        set_error("q-pruning has no effect with DSES_VOTES");
+        return DSES_E_INVAL;
+    }
+    return DSES_OK;
+}
+
 static int effective_scorer(const Job &job)
 {
+    if (job.p.metric == DSES_VOTES) return kScoreVotes;
     int s = job.p.scorer;
     if (s == DSES_SCORER_AUTO)
         s = (job.target && job.target->df && job.target->df_r == job.p.r &&
@@ -635,7 +651,8 @@ dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t
     Params p;
     dses_status st = resolve_params(eps, metric, o.delta_t, o.tau, o.t_min, o.t_max, o.scorer, &p);
     if (st != DSES_OK) return st;
-    if (p.scorer == DSES_SCORER_DF) {
+    if ((st = apply_metric_options(o, &p)) != DSES_OK) return st;
+    if (p.scorer == DSES_SCORER_DF && p.metric != DSES_VOTES) {
         set_error("the DF scorer needs a resident target (dses_register_resident)");
         return DSES_E_INVAL;
     }

@@ -246,6 +246,10 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         dses_status st = resolve_params(q.eps, q.metric, q.delta_t, q.tau, q.t_min, q.t_max,
                                         o.scorer, &x.p);
         if (st != DSES_OK) { x.status = st; return; }
+        if (q.metric == DSES_TRUNC_LP || q.metric == DSES_VOTES) {
+            fail(DSES_E_INVAL, "DSES_TRUNC_LP and DSES_VOTES are plain-path metrics");
+            return;
+        }
         x.n = (int32_t)q.n;
         x.m = (int32_t)m;
         x.k = (int32_t)k;

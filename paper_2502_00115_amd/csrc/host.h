@@ -65,7 +65,12 @@ struct Params {
     int32_t klo[3], size[3];
     int metric;
     int scorer;
+    float lp = 0.5f;         // exponent of DSES_TRUNC_LP
 };
+
+// Applies the plain-path options that resolve_params does not see (the Lp
+// exponent; q has no meaning with DSES_VOTES).  Host-side check, no device use.
+dses_status apply_metric_options(const dses_options &o, Params *p);
 
 dses_status resolve_params(float eps, int metric, float delta_t, float tau, const float *t_min,
                            const float *t_max, int scorer, Params *p);

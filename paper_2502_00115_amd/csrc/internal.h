@@ -24,6 +24,7 @@ struct Geom {
     int32_t klo[3];        // lattice index of bin 0 per axis
     int32_t size[3];       // bins per axis
     int32_t metric;        // dses_metric
+    float lp;              // exponent of DSES_TRUNC_LP
     int32_t counter_bits;  // 16: two counters per LDS word (z rows padded to even), 32: one
     int32_t row_words;     // LDS words per z row: (size_z + 1) / 2 or size_z
     int32_t pps;           // x-planes per LDS slab
@@ -55,6 +56,9 @@ constexpr int kTabPerBin = 4;           // x-table entries per bin (reference wi
 // Kernel scorer value for a vote-only sweep (records unscored: error +inf,
 // 0 inliers); the public scorers are DSES_SCORER_BRUTE / GRID / DF.
 constexpr int kScoreNone = 0;
+// Kernel scorer value of DSES_VOTES: no scoring, records carry error 0 and
+// inliers = the mode count, so the selection ranks candidates by it.
+constexpr int kScoreVotes = 4;
 
 struct SweepArgs {
     const float *src;      // n x 3 AoS

@@ -564,12 +564,13 @@ __device__ uint32_t slab_first(const uint32_t *hist, int words4, uint32_t c, uin
 }
 
 __device__ __forceinline__ float rho(int metric, float d, float dmetric, float d2, float eps,
-                                     float tau)
+                                     float tau, float lp)
 {
     switch (metric) {
     case DSES_TRUNC_L2: return fminf(d, tau);
     case DSES_TLS: return fminf(d2, tau * tau);
     case DSES_INLIERS: return d < eps ? 0.0f : 1.0f;
+    case DSES_TRUNC_LP: return powf(fminf(d, tau), lp);
     default: return fminf(dmetric, tau);          // DSES_TRUNC_L1
     }
 }
@@ -666,15 +667,15 @@ __device__ void score_candidate(const SweepArgs &a, int k, const float *R, int b
     uint32_t *hist = lds;
     uint32_t *scr = lds + kHistWordsMax;          // kScratchWords words
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (SCORER == kScoreNone) {
+    if (SCORER == kScoreNone || SCORER == kScoreVotes) {
         if (tid == 0) {
             dses_record rec;
             rec.bin[0] = bx;
             rec.bin[1] = by;
             rec.bin[2] = bz;
             rec.votes = votes;
-            rec.inliers = 0;
-            rec.error = INFINITY;
+            rec.inliers = SCORER == kScoreVotes ? (int32_t)votes : 0;
+            rec.error = SCORER == kScoreVotes ? 0.0f : INFINITY;
             a.rec[k] = rec;
         }
         return;
@@ -737,12 +738,12 @@ __device__ void score_candidate(const SweepArgs &a, int k, const float *R, int b
         }
         if (valid && L.part == 0) {
             if (SCORER == DSES_SCORER_DF) {
-                err += rho(g.metric, D, D, D * D, g.eps, g.tau);
+                err += rho(g.metric, D, D, D * D, g.eps, g.tau, g.lp);
                 inl += D < g.eps ? 1 : 0;
             } else {
                 const float d = sqrtf(nn.d2);
                 const float dm = want_l1 ? nn.l1 : d;
-                err += rho(g.metric, d, dm, nn.d2, g.eps, g.tau);
+                err += rho(g.metric, d, dm, nn.d2, g.eps, g.tau, g.lp);
                 inl += d < g.eps ? 1 : 0;
             }
         }
@@ -855,6 +856,7 @@ hipError_t launch_sweep(const SweepArgs &a, int scorer, int grid, hipStream_t st
     if (a.g.counter_bits == 16) {
         switch (scorer) {
         case kScoreNone: return launch_one<16, kScoreNone>(a, grid, stream);
+        case kScoreVotes: return launch_one<16, kScoreVotes>(a, grid, stream);
         case DSES_SCORER_BRUTE: return launch_one<16, DSES_SCORER_BRUTE>(a, grid, stream);
         case DSES_SCORER_GRID: return launch_one<16, DSES_SCORER_GRID>(a, grid, stream);
         default: return launch_one<16, DSES_SCORER_DF>(a, grid, stream);
@@ -862,6 +864,7 @@ hipError_t launch_sweep(const SweepArgs &a, int scorer, int grid, hipStream_t st
     }
     switch (scorer) {
     case kScoreNone: return launch_one<32, kScoreNone>(a, grid, stream);
+    case kScoreVotes: return launch_one<32, kScoreVotes>(a, grid, stream);
     case DSES_SCORER_BRUTE: return launch_one<32, DSES_SCORER_BRUTE>(a, grid, stream);
     case DSES_SCORER_GRID: return launch_one<32, DSES_SCORER_GRID>(a, grid, stream);
     default: return launch_one<32, DSES_SCORER_DF>(a, grid, stream);

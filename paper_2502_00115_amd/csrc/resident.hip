@@ -313,6 +313,7 @@ dses_status dses_register_resident(const dses_target *tgt, const dses_rotset *ro
     Params p;
     dses_status st = resolve_params(eps, metric, o.delta_t, o.tau, o.t_min, o.t_max, o.scorer, &p);
     if (st != DSES_OK) return st;
+    if ((st = apply_metric_options(o, &p)) != DSES_OK) return st;
     const bool dev = (o.flags & DSES_DEVICE_PTRS) != 0;
     Context *c = ctx();
     if (!c) return DSES_E_DEVICE;

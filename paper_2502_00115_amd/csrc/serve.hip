@@ -572,6 +572,10 @@ dses_status dses_server_submit(dses_server *srv, const dses_target *tgt, const d
     ServerImpl &S = srv->impl;
     auto *r = new Request();
     dses_status st = resolve_params(eps, metric, 0.0f, 0.0f, nullptr, nullptr, S.opt.scorer, &r->p);
+    if (st == DSES_OK && (metric == DSES_TRUNC_LP || metric == DSES_VOTES)) {
+        set_error("DSES_TRUNC_LP and DSES_VOTES are plain-path metrics");
+        st = DSES_E_INVAL;
+    }
     if (st != DSES_OK) {
         delete r;
         return st;

@@ -20,7 +20,7 @@ DSES_OK, DSES_E_INVAL, DSES_E_NOCANDIDATE, DSES_E_NOMEM = 0, -1, -2, -3
 DSES_E_TIMEOUT, DSES_E_DEVICE, DSES_E_STATE = -4, -5, -6
 STATUS_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOCANDIDATE", -3: "E_NOMEM", -4: "E_TIMEOUT",
                 -5: "E_DEVICE", -6: "E_STATE"}
-METRICS = {"trunc_l2": 0, "inliers": 1, "tls": 2, "trunc_l1": 3}
+METRICS = {"trunc_l2": 0, "inliers": 1, "tls": 2, "trunc_l1": 3, "trunc_lp": 4, "votes": 5}
 SCORERS = {"auto": 0, "brute": 1, "grid": 2, "df": 3}
 DEVICE_PTRS, TIMING, BATCH_TUNE = 0x1, 0x2, 0x4
 
@@ -47,7 +47,8 @@ class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("flags", C.c_uint32), ("delta_t", C.c_float),
                 ("tau", C.c_float), ("t_min", C.c_float * 3), ("t_max", C.c_float * 3),
                 ("scorer", C.c_int32), ("top_k", C.c_int32), ("stream", C.c_void_p),
-                ("records", C.c_void_p), ("topk", C.c_void_p), ("q", C.c_float)]
+                ("records", C.c_void_p), ("topk", C.c_void_p), ("q", C.c_float),
+                ("p", C.c_float)]
 
 
 class Result(C.Structure):
@@ -228,9 +229,10 @@ def _stream_of(stream):
 
 
 def _options(args: _Args, delta_t, tau, t_min, t_max, scorer, timing, stream, records_ptr,
-             q=0.0):
+             q=0.0, lp=0.0):
     o = Options()
     o.q = float(q)
+    o.p = float(lp)
     o.struct_size = C.sizeof(Options)
     o.flags = (DEVICE_PTRS if args.device else 0) | (TIMING if timing else 0)
     o.delta_t = 0.0 if delta_t is None else float(delta_t)
@@ -284,16 +286,16 @@ def _topk_buffer(args: _Args, k: int, o: Options):
 
 def register(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=None,
              t_min=None, t_max=None, scorer="auto", records=False, top_k=0, q=0.0,
-             timing=False, stream=None) -> Registration:
+             lp=0.0, timing=False, stream=None) -> Registration:
     """dses_register: the full sweep over the rotation list (top_k > 0: also the best
     top_k candidates in selection order, Registration.top; q > 0: score only the
-    rotations with M_k >= q M*)."""
+    rotations with M_k >= q M*; lp: exponent of metric "trunc_lp")."""
     args = _Args()
     ps, n = args.ptr(src, 3)
     pt, m = args.ptr(tgt, 3)
     pr, k = args.ptr(rotations, 9)
     rbuf, rptr = _records_buffer(args, k) if records else (None, None)
-    o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr, q)
+    o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr, q, lp)
     tbuf = _topk_buffer(args, int(top_k), o)
     res = Result()
     _check(lib().dses_register(ps, n, pt, m, pr, k, C.c_float(eps), METRICS[metric],
@@ -365,12 +367,12 @@ class RotationSet:
 
 def register_resident(target: Target, rotset: RotationSet, src, eps, metric="trunc_l2", *,
                       delta_t=None, tau=None, t_min=None, t_max=None, scorer="auto",
-                      records=False, top_k=0, q=0.0, timing=False,
+                      records=False, top_k=0, q=0.0, lp=0.0, timing=False,
                       stream=None) -> Registration:
     args = _Args()
     ps, n = args.ptr(src, 3)
     rbuf, rptr = _records_buffer(args, rotset.k) if records else (None, None)
-    o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr, q)
+    o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr, q, lp)
     tbuf = _topk_buffer(args, int(top_k), o)
     res = Result()
     _check(lib().dses_register_resident(target.handle, rotset.handle, ps, n, C.c_float(eps),

@@ -239,6 +239,48 @@ def test_candidate_error_against_kdtree(metric):
         assert abs(r["error"] - rho.sum()) <= 1e-9 * max(1.0, rho.sum())
 
 
+@pytest.mark.parametrize("lp", [0.5, 0.25])
+def test_truncated_lp_against_kdtree(lp):
+    """Truncated Lp (p < 1): sum over X of min(d, tau)^p, d the Euclidean NN distance."""
+    p = synth.make_c1(6)
+    which = np.arange(3, 577, 29)
+    tau = 0.04
+    recs = oracle.records(p.src, p.tgt, p.rotations, p.eps, tau=tau, metric="trunc_lp", p=lp,
+                          which=which)
+    tree = cKDTree(_f64(p.tgt))
+    tau = float(np.float32(tau))
+    lp = float(np.float32(lp))
+    for r, k in zip(recs, which):
+        R = _f64(p.rotations[k]).reshape(3, 3)
+        q = _f64(p.src) @ R.T + r["bin"] * float(np.float32(p.eps))
+        d, _ = tree.query(q)
+        ref = np.sum(np.minimum(d, tau) ** lp)
+        assert abs(r["error"] - ref) <= 1e-9 * max(1.0, ref)
+
+
+def test_truncated_lp_with_p_one_is_truncated_l2():
+    p = synth.make_c1(7)
+    a = oracle.records(p.src, p.tgt, p.rotations, p.eps, metric="trunc_l2")
+    b = oracle.records(p.src, p.tgt, p.rotations, p.eps, metric="trunc_lp", p=1.0)
+    assert a.tobytes() == b.tobytes()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_votes_ranking_is_the_largest_mode_count(seed):
+    """Thm. 3 ranking: no scoring, the candidate with the largest M_k (lowest index on
+    ties); votes and bins are those of the scored run."""
+    p = synth.make_c1(seed)
+    scored = oracle.records(p.src, p.tgt, p.rotations, p.eps)
+    recs = oracle.records(p.src, p.tgt, p.rotations, p.eps, metric="votes")
+    np.testing.assert_array_equal(recs["votes"], scored["votes"])
+    np.testing.assert_array_equal(recs["bin"], scored["bin"])
+    v = recs["valid"].astype(bool)
+    assert np.all(recs["error"][v] == 0.0) and np.all(recs["inliers"][v] == recs["votes"][v])
+    votes = np.where(v, scored["votes"].astype(np.int64), -1)
+    expect = int(np.argmax(votes))                 # first maximum: the lowest index
+    assert oracle.register(p.src, p.tgt, p.rotations, p.eps, metric="votes")["rot_index"] == expect
+
+
 def test_source_vs_reference_direction():
     """Partial-to-full: extra reference points far from the source leave the error unchanged
     (the sum runs over X, the minimum over Y); extra source points do change it."""

@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3          # MI355X published FP32 vector peak
-WORKLOADS = ("c2", "c1", "c5", "c3", "c4")
+WORKLOADS = ("c2", "c1", "c5", "c3", "c4", "local", "fig2")
 
 
 # sources that decide what the plain-path sweep launch reads and writes
@@ -59,6 +59,11 @@ def make_workload(name):
     if name == "c5":
         return synth.make_c5(0), ("scene-scale, 16,384-pt reference, 4,096-pt source, "
                                   "294,912-rotation Hopf grid")
+    if name == "local":
+        return synth.make_local(0), ("local registration with an initial guess: 0.1 m object, "
+                                     "2,048-pt reference, 1,434-pt partial source, Euler grid "
+                                     "+-5 deg in 0.5 deg steps (9,261 rotations), translation "
+                                     "box +-1.6 cm, eps = delta = 2 mm")
     return synth.make_c2(0), ("single registration at object scale: 1,024-pt reference, "
                               "717-pt source, 36,864-rotation Hopf grid")
 
@@ -68,8 +73,10 @@ def cpu_baseline(p, sample, threads):
     import oracle
     rng = np.random.default_rng(0)
     which = np.sort(rng.choice(len(p.rotations), min(sample, len(p.rotations)), replace=False))
+    box = p.meta.get("t_box")
+    kw = {"t_min": -box, "t_max": box} if box is not None else {}
     t0 = time.perf_counter()
-    oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which, threads=threads)
+    oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which, threads=threads, **kw)
     dt = time.perf_counter() - t0
     return {"value": len(which) / dt, "unit": "candidates/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(which)} of {len(p.rotations)} rotations of the same registration "
@@ -128,6 +135,46 @@ def bench_batch(args):
             "tuning": {"s": tune_s, "candidates": tuned_cfg["candidates"],
                        "sweep_ms_best": tuned_cfg["sweep_ms"]},
             "identical_to_plain": bool(same)}
+
+
+def bench_fig2(args):
+    """Time per registration against the search range (the shape of the paper's Fig. 2):
+    Euler grids in 2.5-degree steps around the identity on the object-scale workload,
+    rotation range swept at a +-0.2 translation box, translation range swept at +-45 deg."""
+    import numpy as np
+    import torch
+    from paper_2502_00115_amd import dses, synth
+
+    p = synth.make_c2(0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    src, tgt = dev(p.src), dev(p.tgt)
+    step = np.deg2rad(2.5)
+
+    def time_one(K, box):
+        rot = dev(synth.euler_grid(K, step).reshape(-1, 9).astype(np.float32))
+        kw = dict(t_min=-box, t_max=box)
+        dses.register(src, tgt, rot, p.eps, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dses.register(src, tgt, rot, p.eps, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        return {"rotations": int(rot.shape[0]), "ms": ms}
+
+    rot_sweep = [dict(range_deg=2.5 * K, t_box=0.2, **time_one(K, 0.2)) for K in (2, 4, 8, 12, 18)]
+    t_sweep = [dict(range_deg=45.0, t_box=b, **time_one(18, b)) for b in (0.05, 0.1, 0.2, 0.35, 0.5)]
+    total = sum(r["rotations"] for r in rot_sweep + t_sweep)
+    secs = sum(r["ms"] for r in rot_sweep + t_sweep) / 1e3
+    return {"metric": "registration time vs search range (1 GPU)", "value": total / secs,
+            "unit": "candidates/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": secs * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "object-scale registration (717-pt source, 1,024-pt "
+                                   "reference, eps = delta = 0.03) over Euler grids of 2.5 deg "
+                                   "steps; rotation range at +-0.2 translation, translation "
+                                   "range at +-45 deg"},
+            "rotation_range": rot_sweep, "translation_range": t_sweep}
 
 
 def bench_serve(args):
@@ -267,6 +314,9 @@ def main():
     if args.workload == "c4":
         print(json.dumps(bench_serve(args)), flush=True)
         return
+    if args.workload == "fig2":
+        print(json.dumps(bench_fig2(args)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -279,6 +329,11 @@ def main():
     rot = torch.from_numpy(p.rotations).to(dev)
     n, m, k = len(p.src), len(p.tgt), len(p.rotations)
 
+    box = p.meta.get("t_box")
+    if box is not None:                  # a local search: the box of the initial guess
+        box_kw = {"t_min": -box, "t_max": box}
+    else:
+        box_kw = {}
     if args.scorer == "df":
         # distance-field scoring needs the reference resident with its 128^3 field
         target = dses.Target(tgt, df_trunc=p.eps, df_res=128)
@@ -286,10 +341,11 @@ def main():
 
         def run(**kw):
             return dses.register_resident(target, rotset, src, p.eps, scorer="df", q=args.q,
-                                          **kw)
+                                          **box_kw, **kw)
     else:
         def run(**kw):
-            return dses.register(src, tgt, rot, p.eps, scorer=args.scorer, q=args.q, **kw)
+            return dses.register(src, tgt, rot, p.eps, scorer=args.scorer, q=args.q, **box_kw,
+                                 **kw)
     for _ in range(args.warmup):
         run()
     torch.cuda.synchronize()
@@ -345,7 +401,10 @@ def main():
                               if args.scorer == "df" else
                               "algorithmic (11*N*M + 18*N) FLOP per candidate"),
                      "kernel_ms": sweep_ms},
-        "result": {"rot_index": r.rot_index, "inliers": r.inliers, "error": r.error},
+        "result": {"rot_index": r.rot_index, "inliers": r.inliers, "error": r.error,
+                   "rot_err_deg": float(np.rad2deg(np.arccos(np.clip(
+                       (np.trace(r.R.astype(np.float64).T @ p.R_true) - 1.0) / 2.0, -1.0, 1.0)))),
+                   "t_err": float(np.linalg.norm(r.t.astype(np.float64) - p.t_true))},
     }
     if args.q > 0.0:
         out["result"]["scored"] = scored

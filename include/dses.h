@@ -237,6 +237,14 @@ dses_status dses_target_destroy(dses_target *t);
  * buffers; for checking.  Returns DSES_E_STATE if the target has no field. */
 dses_status dses_target_field(const dses_target *t, float *field, float *lo, float *h);
 
+/* Alg. 2's rotation grid: (2K+1)^3 rotations R = C Rz(theta) Ry(phi) Rx(xi) for
+ * theta, phi, xi in {-K step, ..., +K step} (radians), theta slowest and xi
+ * fastest (the loop order of Alg. 2); C = center (row-major 3x3, NULL: identity),
+ * the initial guess of a local registration.  The Euler convention (intrinsic
+ * z-y-x) is this library's reading; the paper does not fix one.  Host only: out
+ * holds (2K+1)^3 x 9 floats; needs no device.  0 <= K <= 200, step > 0. */
+dses_status dses_rotations_euler(const float *center, int32_t K, float step, float *out);
+
 /* Upload a rotation list (k x 9) once. */
 dses_status dses_rotations_create(const float *rotations, int64_t k, uint32_t flags,
                                   dses_rotset **out);

@@ -28,7 +28,7 @@ EXPORTED = [
     "dses_last_error", "dses_init", "dses_version", "dses_kernel_stats", "dses_register",
     "dses_target_create", "dses_target_destroy", "dses_target_field", "dses_rotations_create",
     "dses_rotations_destroy", "dses_register_resident", "dses_register_batch",
-    "dses_batch_last_config", "dses_measure_lds_atomics",
+    "dses_batch_last_config", "dses_measure_lds_atomics", "dses_rotations_euler",
     "dses_server_create", "dses_server_submit", "dses_server_wait", "dses_server_poll",
     "dses_server_timing", "dses_server_destroy",
 ]
@@ -128,6 +128,7 @@ def lib():
         L.dses_register_resident.argtypes = [vp, vp, vp, i64, f, i32, C.POINTER(Options),
                                              C.POINTER(Result)]
         L.dses_batch_last_config.argtypes = [C.POINTER(BatchConfig)]
+        L.dses_rotations_euler.argtypes = [vp, i32, f, vp]
         L.dses_measure_lds_atomics.argtypes = [i32, C.POINTER(C.c_double),
                                                C.POINTER(C.c_double)]
         L.dses_register_batch.argtypes = [C.POINTER(Problem), i32, C.POINTER(BatchOpts),
@@ -432,6 +433,16 @@ def measure_lds_atomics(pattern: str = "random") -> dict:
     _check(lib().dses_measure_lds_atomics({"conflict_free": 0, "random": 1}[pattern],
                                           C.byref(a), C.byref(b)))
     return {"adds_per_s": a.value, "per_cu_per_cycle": b.value}
+
+
+def euler_grid(K: int, step: float, center=None) -> np.ndarray:
+    """Alg. 2's Euler rotation grid ((2K+1)^3 x 9 float32, dses_rotations_euler)."""
+    side = 2 * int(K) + 1
+    out = np.zeros((side ** 3, 9), np.float32)
+    c = None if center is None else np.ascontiguousarray(np.asarray(center, np.float32).reshape(9))
+    _check(lib().dses_rotations_euler(None if c is None else c.ctypes.data, int(K),
+                                      C.c_float(step), out.ctypes.data))
+    return out
 
 
 def batch_last_config() -> dict:

@@ -301,6 +301,30 @@ def _rotlist(R):
     return _f32(np.asarray(R).reshape(-1, 9))
 
 
+def euler_grid(K: int, step: float, center=None) -> np.ndarray:
+    """(2K+1)^3 rotations C Rz(theta) Ry(phi) Rx(xi), theta, phi, xi in
+    {-K step, ..., K step}, theta slowest (the loop order of the Euler
+    parameterisation of Alg. 2; intrinsic z-y-x is the library's reading)."""
+    C = np.eye(3) if center is None else np.asarray(center, np.float64).reshape(3, 3)
+    a = (np.arange(-K, K + 1) * np.float64(np.float32(step)))
+    th, ph, xi = np.meshgrid(a, a, a, indexing="ij")
+    th, ph, xi = th.ravel(), ph.ravel(), xi.ravel()
+    ct, st, cp, sp, cx, sx = np.cos(th), np.sin(th), np.cos(ph), np.sin(ph), np.cos(xi), np.sin(xi)
+    z = np.zeros_like(th)
+    Rz = np.stack([ct, -st, z, st, ct, z, z, z, z + 1], -1).reshape(-1, 3, 3)
+    Ry = np.stack([cp, z, sp, z, z + 1, z, -sp, z, cp], -1).reshape(-1, 3, 3)
+    Rx = np.stack([z + 1, z, z, z, cx, -sx, z, sx, cx], -1).reshape(-1, 3, 3)
+    return C @ Rz @ Ry @ Rx
+
+
+def _euler_one(th, ph, xi):
+    ct, st, cp, sp, cx, sx = np.cos(th), np.sin(th), np.cos(ph), np.sin(ph), np.cos(xi), np.sin(xi)
+    Rz = np.array([[ct, -st, 0], [st, ct, 0], [0, 0, 1]])
+    Ry = np.array([[cp, 0, sp], [0, 1, 0], [-sp, 0, cp]])
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    return Rz @ Ry @ Rx
+
+
 # --------------------------------------------------------------------------
 # workloads
 # --------------------------------------------------------------------------
@@ -427,6 +451,30 @@ def make_c5(seed: int, grid_level: int = 4) -> Problem:
     rots = hopf_grid(grid_level)
     return Problem(_f32(src), _f32(tgt), _rotlist(rots), 0.02, Ra.T, -Ra.T @ ta, -1,
                    f"c5-s{seed}")
+
+
+def make_local(seed: int, K: int = 10, step_deg: float = 0.5) -> Problem:
+    """Local registration with an initial guess (stand-in for the paper's on-robot
+    gripper pose correction, whose clouds are not available): a multi-primitive
+    object of radius 0.1 m (metres), 2,048 reference points, a 70% partial view of
+    an independent 2,048-point sample with 1 mm noise (clipped at 5 mm) and 10%
+    outliers, displaced by a rotation of up to 4 degrees per Euler angle and a
+    translation of up to 1.2 cm per axis.  Rotations: the Euler grid of +-K step
+    around the identity (default +-5 degrees in 0.5-degree steps, 9,261 rotations);
+    translation box +-1.6 cm; eps = delta = 2 mm."""
+    rng = np.random.default_rng(6000 + seed)
+    shape = multi_primitive_shape(rng)
+    tgt = 0.1 * sample_surface(rng, shape, 2048)
+    src = 0.1 * sample_surface(rng, shape, 2048)
+    src = src[halfspace_keep(rng, src, 0.7)]
+    src = jitter(rng, src, 0.001, clip=0.005)
+    src = add_outliers(rng, src, 0.10, src.min(axis=0), src.max(axis=0))
+    Ra = _euler_one(*rng.uniform(-np.deg2rad(4.0), np.deg2rad(4.0), size=3))
+    ta = rng.uniform(-0.012, 0.012, size=3)
+    src = _apply(Ra, ta, src)
+    rots = euler_grid(K, np.deg2rad(step_deg))
+    return Problem(_f32(src), _f32(tgt), _rotlist(rots), 0.002, Ra.T, -Ra.T @ ta, -1,
+                   f"local-s{seed}", {"t_box": 0.016})
 
 
 def make_tiny(seed: int, n: int = 6, m: int = 8, k: int = 4, delta: float = 0.0625,

@@ -91,3 +91,19 @@ def test_no_device_is_a_loud_error(libpath):
     with pytest.raises(dses.DsesError) as e:
         dses.register(np.zeros((3, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05)
     assert e.value.status == dses.DSES_E_DEVICE
+
+
+def test_euler_rotation_grid_needs_no_gpu(libpath):
+    import numpy as np
+    from scipy.spatial.transform import Rotation
+    from paper_2502_00115_amd import dses
+    K, step = 2, float(np.float32(np.deg2rad(3.0)))
+    C = Rotation.from_euler("xyz", [5, 40, -70], degrees=True).as_matrix().astype(np.float32)
+    a = np.arange(-K, K + 1) * step
+    ref = np.stack([C.astype(np.float64) @ Rotation.from_euler("ZYX", [t, p, x]).as_matrix()
+                    for t in a for p in a for x in a])
+    got = dses.euler_grid(K, step, C).reshape(-1, 3, 3)
+    np.testing.assert_allclose(got, ref, atol=1e-6)
+    for bad_step in (0.0, float("nan")):
+        with pytest.raises(dses.DsesError):
+            dses.euler_grid(K, bad_step)

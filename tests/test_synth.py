@@ -85,3 +85,19 @@ def test_generators_are_deterministic():
     a, b = synth.make_c2(1), synth.make_c2(1)
     np.testing.assert_array_equal(a.src, b.src)
     np.testing.assert_array_equal(a.tgt, b.tgt)
+
+
+def test_euler_grid_matches_scipy_intrinsic_zyx():
+    from scipy.spatial.transform import Rotation
+    K, step = 3, float(np.float32(np.deg2rad(2.5)))
+    C = Rotation.from_euler("xyz", [10, -20, 30], degrees=True).as_matrix()
+    a = np.arange(-K, K + 1) * step
+    ref = np.stack([C @ Rotation.from_euler("ZYX", [t, p, x]).as_matrix()
+                    for t in a for p in a for x in a])
+    np.testing.assert_allclose(synth.euler_grid(K, step, C), ref, atol=1e-12)
+
+
+def test_local_workload_truth_is_inside_the_search_range():
+    p = synth.make_local(1)
+    ang = np.rad2deg(np.arccos(np.clip((np.trace(p.R_true) - 1) / 2, -1, 1)))
+    assert ang < 7.0 and np.all(np.abs(p.t_true) < p.meta["t_box"])

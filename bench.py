@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3          # MI355X published FP32 vector peak
-WORKLOADS = ("c2", "c1", "c5", "c3", "c4", "local", "fig2")
+WORKLOADS = ("c2", "c1", "c5", "c3", "c4", "local", "fig2", "exhaustive")
 
 
 # sources that decide what the plain-path sweep launch reads and writes
@@ -177,6 +177,46 @@ def bench_fig2(args):
             "rotation_range": rot_sweep, "translation_range": t_sweep}
 
 
+def bench_exhaustive(args):
+    """Alg. 1 (every rotation x every lattice translation) against DSES on the same
+    small registration: the time DSES's vote saves on the same GPU."""
+    import numpy as np
+    import torch
+    from paper_2502_00115_amd import dses, synth
+
+    p = synth.make_c1(0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    src, tgt, rot = dev(p.src), dev(p.tgt), dev(p.rotations)
+    box = dict(t_min=-0.5, t_max=0.5)
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, r
+
+    t_dses, a = timed(lambda: dses.register(src, tgt, rot, p.eps, **box))
+    t_exh, b = timed(lambda: dses.register_exhaustive(src, tgt, rot, p.eps, **box))
+    bins = int(round(0.5 / p.eps)) * 2 + 1           # lattice points per axis of +-0.5
+    k = len(p.rotations)
+    return {"metric": "candidate poses {R,t} scored/sec (1 GPU), exhaustive Alg. 1 vs DSES",
+            "value": k * bins ** 3 / t_exh, "unit": "candidates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": t_exh * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"64-pt source, 256-pt reference, {k} rotations, translation "
+                                   f"box +-0.5 at delta 0.05 ({bins}^3 lattice points); exact "
+                                   "cell-grid scoring"},
+            "exhaustive": {"ms": t_exh * 1e3, "candidates": k * bins ** 3,
+                           "rot_index": b.rot_index, "error": b.error},
+            "dses": {"ms": t_dses * 1e3, "candidates": k, "rot_index": a.rot_index,
+                     "error": a.error},
+            "speedup_dses": t_exh / t_dses}
+
+
 def bench_serve(args):
     """Poisson arrivals against 8 resident references (with 128^3 distance fields):
     served (continuous batching) versus one launch per request in FIFO order."""
@@ -316,6 +356,9 @@ def main():
         return
     if args.workload == "fig2":
         print(json.dumps(bench_fig2(args)), flush=True)
+        return
+    if args.workload == "exhaustive":
+        print(json.dumps(bench_exhaustive(args)), flush=True)
         return
 
     import numpy as np

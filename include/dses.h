@@ -209,6 +209,18 @@ dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t
                           const float *rotations, int64_t k, float eps, dses_metric metric,
                           const dses_options *opt, dses_result *out);
 
+/* Alg. 1, the pure exhaustive search, as a baseline: every rotation of the list
+ * with every lattice translation b delta_t of the box, each scored like a DSES
+ * candidate (BRUTE or GRID scorer; any metric but DSES_VOTES).  opt->records gets
+ * per rotation its best translation (smaller error, more inliers, lower linear
+ * index of b, x slowest) with votes = 1; *out the best pose overall (ties to the
+ * lower rotation index).  Cost: k x (box bins) x n nearest-neighbour queries.
+ * Requires n <= 12288 and at most 2^31 - 1 bins; top_k and q must be 0. */
+dses_status dses_register_exhaustive(const float *src, int64_t n, const float *tgt, int64_t m,
+                                     const float *rotations, int64_t k, float eps,
+                                     dses_metric metric, const dses_options *opt,
+                                     dses_result *out);
+
 /* ---------------------------------------------------------------------------- */
 /* Resident data: reference clouds (with optional distance field) and rotation   */
 /* lists kept in device memory across calls (the serving workload keeps them).   */

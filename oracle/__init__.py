@@ -56,6 +56,10 @@ def lib():
                                   dp, C.c_int32, fp, fp, C.c_int32, C.c_void_p]
         L.orc_records.restype = C.c_int
         L.orc_select.argtypes = [C.c_void_p, C.c_int32]
+        L.orc_exhaustive.argtypes = [fp, C.c_int32, fp, C.c_int32, fp, C.c_int32, C.c_float,
+                                     C.c_float, C.c_float, fp, fp, C.c_int32, C.c_float,
+                                     C.c_int32, C.c_void_p]
+        L.orc_exhaustive.restype = C.c_int
         L.orc_select.restype = C.c_int32
         _lib = L
     return _lib
@@ -155,6 +159,25 @@ def records(src, tgt, rotations, eps, *, delta=None, tau=None, t_min=None, t_max
                            C.c_float(eps), C.c_float(delta), C.c_float(tau),
                            _p(t_min, C.c_float), _p(t_max, C.c_float), METRICS[metric],
                            C.c_float(p), fld_p, res, lo_p, inv_p, threads, out.ctypes.data)
+    if rc:
+        raise ValueError("oracle rejected the input")
+    return out
+
+
+def exhaustive(src, tgt, rotations, eps, *, delta=None, tau=None, t_min=None, t_max=None,
+               metric="trunc_l2", p=0.5, threads=0):
+    """Alg. 1: per rotation the best lattice translation of the box (records with
+    votes = 1); select() over them gives the exhaustive optimum."""
+    src, tgt = _f32(src, 3), _f32(tgt, 3)
+    rots = _f32(rotations, 9)
+    delta = eps if delta is None else delta
+    tau = eps if tau is None else tau
+    t_min, t_max = _box_args(t_min, t_max)
+    out = np.zeros(len(rots), RECORD_DTYPE)
+    rc = lib().orc_exhaustive(_p(src, C.c_float), len(src), _p(tgt, C.c_float), len(tgt),
+                              _p(rots, C.c_float), len(rots), C.c_float(eps), C.c_float(delta),
+                              C.c_float(tau), _p(t_min, C.c_float), _p(t_max, C.c_float),
+                              METRICS[metric], C.c_float(p), threads, out.ctypes.data)
     if rc:
         raise ValueError("oracle rejected the input")
     return out

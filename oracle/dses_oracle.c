@@ -418,3 +418,77 @@ int32_t orc_select(const orc_record *recs, int32_t count)
     }
     return best;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 1, the pure exhaustive search: every rotation of the list with every  */
+/* lattice translation b delta of the box, each scored as in Alg. 2's error   */
+/* loop (sum over the source, brute-force nearest reference point).  Writes   */
+/* per rotation the best translation (smaller error, then more inliers, then  */
+/* the lower linear index of b, x slowest); `votes` is 1 (Alg. 1 has no vote) */
+/* and `valid` 1.  The best pose overall is orc_select() over these records.  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const float *src; int32_t n; const float *tgt; int32_t m; const float *rots;
+    float delta; const int32_t *k_lo; const int32_t *size;
+    int metric; double eps, tau, lp;
+    orc_record *out; int32_t begin, end;
+} exh_job;
+
+static void *exh_worker(void *arg)
+{
+    exh_job *jb = (exh_job *)arg;
+    for (int32_t k = jb->begin; k < jb->end; ++k) {
+        const float *R = jb->rots + 9 * (size_t)k;
+        orc_record best;
+        memset(&best, 0, sizeof(best));
+        best.error = INFINITY;
+        int have = 0;
+        for (int32_t a = 0; a < jb->size[0]; ++a)
+            for (int32_t b = 0; b < jb->size[1]; ++b)
+                for (int32_t c = 0; c < jb->size[2]; ++c) {
+                    const int32_t bin[3] = {jb->k_lo[0] + a, jb->k_lo[1] + b, jb->k_lo[2] + c};
+                    double t[3];
+                    for (int ax = 0; ax < 3; ++ax) t[ax] = (double)bin[ax] * (double)jb->delta;
+                    orc_record r;
+                    memset(&r, 0, sizeof(r));
+                    score_candidate(jb->src, jb->n, jb->tgt, jb->m, R, t, jb->metric, jb->eps,
+                                    jb->tau, jb->lp, &r);
+                    /* lexicographic order: the first strictly better one wins, so ties
+                       keep the lower linear index */
+                    if (!have || r.error < best.error ||
+                        (r.error == best.error && r.inliers > best.inliers)) {
+                        best = r;
+                        for (int ax = 0; ax < 3; ++ax) best.bin[ax] = bin[ax];
+                        have = 1;
+                    }
+                }
+        best.votes = 1;
+        best.valid = 1;
+        jb->out[k] = best;
+    }
+    return NULL;
+}
+
+int orc_exhaustive(const float *src, int32_t n, const float *tgt, int32_t m, const float *rots,
+                   int32_t k, float eps, float delta, float tau, const float *t_min,
+                   const float *t_max, int32_t metric, float lp, int32_t nthreads,
+                   orc_record *out)
+{
+    int32_t k_lo[3], size[3];
+    if (n <= 0 || m <= 0 || k <= 0 || !(eps > 0.0f)) return -1;
+    if (metric < ORC_TRUNC_L2 || metric > ORC_TRUNC_LP || !(lp > 0.0f && lp <= 1.0f)) return -1;
+    if (orc_box(delta, t_min, t_max, k_lo, size)) return -1;
+    int nt = n_threads(nthreads);
+    if (nt > 256) nt = 256;
+    if (nt > k) nt = k;
+    pthread_t th[256];
+    exh_job jobs[256];
+    for (int w = 0; w < nt; ++w) {
+        jobs[w] = (exh_job){src, n, tgt, m, rots, delta, k_lo, size, metric, (double)eps,
+                            (double)tau, (double)lp, out, (int32_t)((int64_t)k * w / nt),
+                            (int32_t)((int64_t)k * (w + 1) / nt)};
+        pthread_create(&th[w], NULL, exh_worker, &jobs[w]);
+    }
+    for (int w = 0; w < nt; ++w) pthread_join(th[w], NULL);
+    return 0;
+}

@@ -536,7 +536,9 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
                           static_cast<float *>(c->ys.ptr), static_cast<float *>(c->yt.ptr),
                           stream));
     rec_ev(1);
-    if (o.q > 0.0f) {
+    if (job.exhaustive) {
+        DSES_HIP(launch_exhaustive(a, scorer, grid, stream));
+    } else if (o.q > 0.0f) {
         if ((st = c->prune.ensure(64)) != DSES_OK) return st;
         uint32_t *pw = static_cast<uint32_t *>(c->prune.ptr);
         DSES_HIP(launch_sweep(a, kScoreNone, grid, stream));
@@ -671,6 +673,83 @@ dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t
     job.m = (int32_t)m;
     job.k = (int32_t)k;
     job.p = p;
+    if (dev) {
+        job.src = src;
+        job.tgt = tgt;
+        job.rot = rotations;
+    } else {
+        if ((st = c->in_src.ensure(3 * n * sizeof(float))) != DSES_OK) return st;
+        if ((st = c->in_tgt.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
+        if ((st = c->in_rot.ensure(9 * k * sizeof(float))) != DSES_OK) return st;
+        DSES_HIP(hipMemcpyAsync(c->in_src.ptr, src, 3 * n * sizeof(float), hipMemcpyHostToDevice,
+                                stream));
+        DSES_HIP(hipMemcpyAsync(c->in_tgt.ptr, tgt, 3 * m * sizeof(float), hipMemcpyHostToDevice,
+                                stream));
+        DSES_HIP(hipMemcpyAsync(c->in_rot.ptr, rotations, 9 * k * sizeof(float),
+                                hipMemcpyHostToDevice, stream));
+        job.src = static_cast<float *>(c->in_src.ptr);
+        job.tgt = static_cast<float *>(c->in_tgt.ptr);
+        job.rot = static_cast<float *>(c->in_rot.ptr);
+        job.host_tgt = tgt;
+    }
+    return run_plain(c, job, stream, dev, out, o);
+}
+
+dses_status dses_register_exhaustive(const float *src, int64_t n, const float *tgt, int64_t m,
+                                     const float *rotations, int64_t k, float eps,
+                                     dses_metric metric, const dses_options *opt,
+                                     dses_result *out)
+{
+    set_error("");
+    if (!src || !tgt || !rotations || !out) {
+        set_error("NULL pointer argument");
+        return DSES_E_INVAL;
+    }
+    if (n <= 0 || m <= 0 || k <= 0 || k > INT32_MAX || n * m >= ((int64_t)1 << 31) ||
+        n > kExhaustiveMaxSrc) {
+        set_error("n, m, k must be positive with n*m < 2^31 and n <= 12288");
+        return DSES_E_INVAL;
+    }
+    dses_options o{};
+    if (opt) {
+        if (opt->struct_size != 0 && opt->struct_size < sizeof(dses_options)) {
+            set_error("dses_options.struct_size too small");
+            return DSES_E_INVAL;
+        }
+        o = *opt;
+    }
+    if (o.top_k != 0 || o.q != 0.0f) {
+        set_error("top_k and q are not options of the exhaustive search");
+        return DSES_E_INVAL;
+    }
+    Params p;
+    dses_status st = resolve_params(eps, metric, o.delta_t, o.tau, o.t_min, o.t_max, o.scorer, &p);
+    if (st != DSES_OK) return st;
+    if ((st = apply_metric_options(o, &p)) != DSES_OK) return st;
+    if (p.metric == DSES_VOTES || p.scorer == DSES_SCORER_DF) {
+        set_error("the exhaustive search scores with BRUTE or GRID and a robust metric");
+        return DSES_E_INVAL;
+    }
+    if ((int64_t)p.size[0] * p.size[1] * p.size[2] > INT32_MAX) {
+        set_error("the exhaustive search takes at most 2^31 - 1 translations per rotation");
+        return DSES_E_INVAL;
+    }
+    const bool dev = (o.flags & DSES_DEVICE_PTRS) != 0;
+    if (!dev) {
+        st = check_host_inputs(src, n, tgt, m, rotations, k, coord_limit(p));
+        if (st != DSES_OK) return st;
+    }
+    Context *c = ctx();
+    if (!c) return DSES_E_DEVICE;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timing_enabled = (o.flags & DSES_TIMING) != 0;
+    hipStream_t stream = o.stream ? static_cast<hipStream_t>(o.stream) : c->stream;
+    Job job;
+    job.n = (int32_t)n;
+    job.m = (int32_t)m;
+    job.k = (int32_t)k;
+    job.p = p;
+    job.exhaustive = true;
     if (dev) {
         job.src = src;
         job.tgt = tgt;

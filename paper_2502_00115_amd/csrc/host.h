@@ -158,6 +158,7 @@ struct Job {
     Params p{};
     const TargetRes *target = nullptr;   // resident reference (grid / field source)
     const float *host_tgt = nullptr;     // host AoS copy of the reference, if known
+    bool exhaustive = false;             // Alg. 1: every lattice translation per rotation
 };
 
 // Run one registration on `stream` using the context workspace (caller holds c->mu).

@@ -59,6 +59,8 @@ constexpr int kScoreNone = 0;
 // Kernel scorer value of DSES_VOTES: no scoring, records carry error 0 and
 // inliers = the mode count, so the selection ranks candidates by it.
 constexpr int kScoreVotes = 4;
+// Largest source of the exhaustive search (rotated sources held in LDS).
+constexpr int kExhaustiveMaxSrc = 12288;
 
 struct SweepArgs {
     const float *src;      // n x 3 AoS
@@ -149,6 +151,9 @@ hipError_t launch_topk(const dses_record *rec, int32_t K, int32_t k, float delta
 // rotations with M_k >= q M* (both device words, the cursor cleared here).
 hipError_t launch_score_pruned(const SweepArgs &a, int scorer, float q, uint32_t *mstar,
                                uint32_t *cursor, int grid, hipStream_t stream);
+// Alg. 1 (every lattice translation of the box per rotation, scored with the
+// BRUTE or GRID scorer): one record per rotation with its best translation.
+hipError_t launch_exhaustive(const SweepArgs &a, int scorer, int grid, hipStream_t stream);
 hipError_t launch_clear(uint32_t *p, int32_t words, hipStream_t stream);
 hipError_t launch_sweep_batch(const BatchArgs &b, int scorer, int grid, hipStream_t stream);
 // which = 0: batched staging, 1: batched selection

@@ -925,6 +925,108 @@ __global__ void __launch_bounds__(kBlock) k_score_pruned(SweepArgs a, float q,
     }
 }
 
+// --------------------------------------------------------------------------
+// Alg. 1, the pure exhaustive search: every rotation with every lattice
+// translation b delta of the box.  One workgroup per rotation holds the rotated
+// sources in LDS; each thread scores whole translations (the error summed over
+// the source in index order, nearest reference point by the cell grid or by
+// brute force) and keeps its best; a workgroup reduction picks the rotation's
+// best translation (smaller error, then more inliers, then the lower linear
+// index of b).  The record carries votes = 1 (Alg. 1 has no vote).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ bool exh_better(float e, int i, uint32_t u, float oe, int oi,
+                                           uint32_t ou)
+{
+    if (oe < e) return true;
+    if (oe > e) return false;
+    if (oi != i) return oi > i;
+    return ou < u;
+}
+
+template <int SCORER>
+__global__ void __launch_bounds__(kBlock) k_exhaustive(SweepArgs a)
+{
+    __shared__ float sp[3 * kExhaustiveMaxSrc];
+    __shared__ float re[kWaves];
+    __shared__ int ri[kWaves];
+    __shared__ uint32_t ru[kWaves];
+    const Geom &g = a.g;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = g.n;
+    const uint32_t sz = (uint32_t)g.size[2], syz = (uint32_t)g.size[1] * sz;
+    const uint32_t T = (uint32_t)g.size[0] * syz;
+    const bool want_l1 = g.metric == DSES_TRUNC_L1;
+    for (int k = blockIdx.x; k < a.k; k += gridDim.x) {
+        float R[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) R[e] = kc(a.rot)[9 * k + e];
+        for (int i = tid; i < n; i += kBlock)
+            rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], sp[i], sp[n + i],
+                   sp[2 * n + i]);
+        __syncthreads();
+        float be = INFINITY;
+        int bi = 0;
+        uint32_t bu = 0xFFFFFFFFu;
+        for (uint32_t u = (uint32_t)tid; u < T; u += kBlock) {
+            const uint32_t ux = u / syz, uy = (u - ux * syz) / sz, uz = u - ux * syz - uy * sz;
+            const float tx = __fmul_rn((float)(g.klo[0] + (int)ux), g.delta);
+            const float ty = __fmul_rn((float)(g.klo[1] + (int)uy), g.delta);
+            const float tz = __fmul_rn((float)(g.klo[2] + (int)uz), g.delta);
+            float err = 0.0f;
+            int inl = 0;
+            for (int i = 0; i < n; ++i) {
+                const float qx = sp[i] + tx, qy = sp[n + i] + ty, qz = sp[2 * n + i] + tz;
+                NN nn;
+                if (SCORER == DSES_SCORER_GRID)
+                    nn_grid(a.grid, qx, qy, qz, want_l1, nn);
+                else
+                    nn_brute(a.yt, g.m, 0, g.m, qx, qy, qz, want_l1, nn);
+                const float d = sqrtf(nn.d2);
+                err += rho(g.metric, d, want_l1 ? nn.l1 : d, nn.d2, g.eps, g.tau, g.lp);
+                inl += d < g.eps ? 1 : 0;
+            }
+            if (exh_better(be, bi, bu, err, inl, u)) { be = err; bi = inl; bu = u; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const float oe = __shfl_xor(be, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            const uint32_t ou = (uint32_t)__shfl_xor((int)bu, off, 64);
+            if (exh_better(be, bi, bu, oe, oi, ou)) { be = oe; bi = oi; bu = ou; }
+        }
+        if (lane == 0) { re[wave] = be; ri[wave] = bi; ru[wave] = bu; }
+        __syncthreads();
+        if (tid == 0) {
+            float e = re[0];
+            int c = ri[0];
+            uint32_t w = ru[0];
+            for (int q = 1; q < kWaves; ++q)
+                if (exh_better(e, c, w, re[q], ri[q], ru[q])) { e = re[q]; c = ri[q]; w = ru[q]; }
+            const uint32_t ux = w / syz, uy = (w - ux * syz) / sz, uz = w - ux * syz - uy * sz;
+            dses_record rec;
+            rec.bin[0] = g.klo[0] + (int)ux;
+            rec.bin[1] = g.klo[1] + (int)uy;
+            rec.bin[2] = g.klo[2] + (int)uz;
+            rec.votes = 1u;
+            rec.inliers = c;
+            rec.error = e;
+            a.rec[k] = rec;
+        }
+        __syncthreads();                       // sp and the reduction slots are reused
+    }
+}
+
+hipError_t launch_exhaustive(const SweepArgs &a, int scorer, int grid, hipStream_t stream)
+{
+    if (a.k <= 0) return hipSuccess;
+    if (a.g.n > kExhaustiveMaxSrc) return hipErrorInvalidValue;
+    if (grid > a.k) grid = a.k;
+    if (scorer == DSES_SCORER_BRUTE)
+        hipLaunchKernelGGL(k_exhaustive<DSES_SCORER_BRUTE>, dim3(grid), dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_exhaustive<DSES_SCORER_GRID>, dim3(grid), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_score_pruned(const SweepArgs &a, int scorer, float q, uint32_t *mstar,
                                uint32_t *cursor, int grid, hipStream_t stream)
 {

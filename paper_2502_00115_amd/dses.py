@@ -29,6 +29,7 @@ EXPORTED = [
     "dses_target_create", "dses_target_destroy", "dses_target_field", "dses_rotations_create",
     "dses_rotations_destroy", "dses_register_resident", "dses_register_batch",
     "dses_batch_last_config", "dses_measure_lds_atomics", "dses_rotations_euler",
+    "dses_register_exhaustive",
     "dses_server_create", "dses_server_submit", "dses_server_wait", "dses_server_poll",
     "dses_server_timing", "dses_server_destroy",
 ]
@@ -129,6 +130,8 @@ def lib():
                                              C.POINTER(Result)]
         L.dses_batch_last_config.argtypes = [C.POINTER(BatchConfig)]
         L.dses_rotations_euler.argtypes = [vp, i32, f, vp]
+        L.dses_register_exhaustive.argtypes = [vp, i64, vp, i64, vp, i64, f, i32,
+                                               C.POINTER(Options), C.POINTER(Result)]
         L.dses_measure_lds_atomics.argtypes = [i32, C.POINTER(C.c_double),
                                                C.POINTER(C.c_double)]
         L.dses_register_batch.argtypes = [C.POINTER(Problem), i32, C.POINTER(BatchOpts),
@@ -303,6 +306,22 @@ def register(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=N
                                C.byref(o), C.byref(res)))
     return _result(res, _records_out(rbuf) if records else None,
                    _records_out(tbuf, CANDIDATE_DTYPE) if tbuf is not None else None)
+
+
+def register_exhaustive(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=None,
+                        t_min=None, t_max=None, scorer="auto", records=False, lp=0.0,
+                        timing=False, stream=None) -> Registration:
+    """dses_register_exhaustive: Alg. 1 over the rotation list and the box lattice."""
+    args = _Args()
+    ps, n = args.ptr(src, 3)
+    pt, m = args.ptr(tgt, 3)
+    pr, k = args.ptr(rotations, 9)
+    rbuf, rptr = _records_buffer(args, k) if records else (None, None)
+    o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr, 0.0, lp)
+    res = Result()
+    _check(lib().dses_register_exhaustive(ps, n, pt, m, pr, k, C.c_float(eps), METRICS[metric],
+                                          C.byref(o), C.byref(res)))
+    return _result(res, _records_out(rbuf) if records else None)
 
 
 def kernel_stats(reset=False) -> dict:

@@ -166,6 +166,46 @@ def test_theorem3_against_exhaustive_alg1(seed):
     assert best_alg1 == int(recs["votes"].max())
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_exhaustive_alg1_against_kdtree_enumeration(seed):
+    """Alg. 1: every rotation with every lattice translation of the box, scored by a
+    k-d tree here; the best per rotation (error, then inliers, then the lowest linear
+    index, x slowest) matches the oracle's."""
+    p = synth.make_tiny(seed, n=6, m=8, k=3, delta=0.125)
+    box = 0.5
+    recs = oracle.exhaustive(p.src, p.tgt, p.rotations, p.eps, t_min=-box, t_max=box)
+    k_lo, size = oracle.box(p.eps, -box, box)
+    lat = np.stack(np.meshgrid(*[np.arange(k_lo[a], k_lo[a] + size[a]) for a in range(3)],
+                               indexing="ij"), -1).reshape(-1, 3)
+    tree = cKDTree(_f64(p.tgt))
+    eps = float(np.float32(p.eps))
+    for k, r in enumerate(recs):
+        P = _f64(p.src) @ _f64(p.rotations[k]).reshape(3, 3).T
+        q = P[None, :, :] + lat[:, None, :] * eps                      # (T, N, 3)
+        d, _ = tree.query(q.reshape(-1, 3))
+        d = d.reshape(len(lat), -1)
+        err = np.minimum(d, eps).sum(axis=1)
+        inl = (d < eps).sum(axis=1)
+        best = min(range(len(lat)), key=lambda u: (err[u], -inl[u], u))
+        assert abs(r["error"] - err[best]) <= 1e-12
+        # the oracle sums in a different order: compare the chosen bin up to exact ties
+        same = np.nonzero((np.abs(err - err[best]) <= 1e-12) & (inl == inl[best]))[0]
+        assert tuple(r["bin"]) in {tuple(lat[u]) for u in same}
+        assert r["inliers"] == inl[best] and r["votes"] == 1
+
+
+def test_exhaustive_is_never_worse_than_dses():
+    """DSES scores one lattice translation per rotation, Alg. 1 all of them, so its best
+    error per rotation is at most DSES's (the same score function, same arithmetic)."""
+    p = synth.make_c1(2)
+    rots = p.rotations[:40]
+    box = 0.3
+    exh = oracle.exhaustive(p.src, p.tgt, rots, p.eps, t_min=-box, t_max=box)
+    dse = oracle.records(p.src, p.tgt, rots, p.eps, t_min=-box, t_max=box)
+    v = dse["valid"].astype(bool)
+    assert np.all(exh["error"][v] <= dse["error"][v])
+
+
 def test_translation_invariance_exact():
     """Shifting the reference by a lattice vector shifts every mode by it (dyadic data and
     signed-permutation rotations keep all float arithmetic exact)."""

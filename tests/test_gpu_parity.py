@@ -182,3 +182,21 @@ def test_c2_sampled_records_and_selection():
     ang = np.degrees(np.arccos(np.clip((np.trace(got.R.astype(float).T @ p.R_true) - 1) / 2,
                                        -1, 1)))
     print(f"c2: rot {got.rot_index} angle to truth {ang:.2f} deg, t {got.t} vs {p.t_true}")
+
+
+# ---------------------------------------------------------------------------
+# full-size scene-scale registration (294,912-rotation grid), the bench's launch
+# ---------------------------------------------------------------------------
+@pytest.mark.slow
+def test_c5_full_size_sampled_records_and_selection():
+    p = synth.make_c5(0)
+    got = dses.register(_dev(p.src), _dev(p.tgt), _dev(p.rotations), p.eps, records=True)
+    recs = got.records
+    assert int((recs["votes"] > 0).sum()) == got.n_valid
+    rng = np.random.default_rng(5)
+    top = np.argsort(np.where(recs["votes"] > 0, recs["error"], np.inf))[:8]
+    which = np.unique(np.concatenate([rng.choice(len(p.rotations), 24, replace=False), top]))
+    ref = oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which)
+    compare_records(recs[which], ref, len(p.src), label="c5 sample")
+    pos = np.isin(which, top)
+    check_selection(got, ref[pos], len(p.src), p.eps, which=which[pos], label="c5 top8")

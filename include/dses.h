@@ -293,8 +293,9 @@ typedef struct {
     int32_t scorer;           /* dses_scorer for every problem */
     int32_t use_graph;        /* 1: capture the launch in a HIP graph and replay it */
     int32_t tile_rot;         /* rotations per work item; 0 -> tuned or default layout */
-    int32_t parts_max;        /* most reference-window parts per 64-source group in the
-                                 vote (1..8); 0 -> tuned or default (8)               */
+    int32_t vote_parts;       /* vote work units per 64-point lane group (parts of its
+                                 stream window, 1..16); 0 -> tuned or automatic
+                                 (64 / groups, 1..8, per problem)                   */
     void *stream;
 } dses_batch_opts;
 
@@ -304,22 +305,24 @@ typedef struct {
  * Launch layout.  The persistent launch takes (instance, rotation tile) items from
  * one work list, most expensive first.  Two knobs shape it: the work-list
  * granularity (tiles sized so that the list holds about `items_per_cu` items per
- * compute unit, unless tile_rot fixes the tile) and parts_max (how finely the vote
- * splits each 64-source group's reference window over the workgroup's waves).
+ * compute unit, unless tile_rot fixes the tile) and vote_parts (into how many work
+ * units the vote splits each 64-point lane group's stream window: 64 reference
+ * points on the lanes against the window of x-sorted sources; the waves of a
+ * workgroup take units dynamically).
  * With DSES_BATCH_TUNE the call first times the sweep kernel alone on this batch
- * for candidate layouts (items_per_cu in {6, 12, 24, 48, 96}, then parts_max in
+ * for candidate layouts (items_per_cu in {6, 12, 24, 48, 96}, then vote_parts in
  * {1, 2, 4, 8}, one coordinate at a time), keeps the fastest for every later batch
  * of the same class (same count and scorer, same power-of-two bucket of total
  * pairs, of mean source size and of mean rotation count), and then runs the batch
  * with it.  Without the flag a batch uses its class's tuned layout if one exists,
- * else the default (items_per_cu 24, parts_max 8). */
+ * else the default (items_per_cu 24, vote_parts automatic). */
 dses_status dses_register_batch(const dses_problem *probs, int32_t count,
                                 const dses_batch_opts *opt, dses_result *out,
                                 dses_status *status);
 
 typedef struct {
     int32_t items_per_cu;     /* work-list granularity used (0 when tile_rot fixed it) */
-    int32_t parts_max;        /* vote window parts used                                */
+    int32_t vote_parts;       /* vote work units per lane group used (0: automatic)    */
     int32_t n_items;          /* work items in the launch                             */
     int32_t source;           /* 0 default, 1 tuned by this call, 2 tuned earlier for
                                  this class, 3 given by the caller                    */

@@ -335,30 +335,30 @@ void sort_by_x(const float *tgt, int32_t m, std::vector<int32_t> *perm)
                      [tgt](int32_t a, int32_t b) { return tgt[3 * a] < tgt[3 * b]; });
 }
 
-bool build_x_table(const float *tgt, const std::vector<int32_t> &perm, float s, int32_t klo_x,
-                   std::vector<int32_t> *tab, int32_t *tab_lo)
+bool ref_x_range(const float *tgt, const std::vector<int32_t> &perm, float s, int32_t klo_x,
+                 int32_t *ylo, int32_t *yhi)
 {
-    const size_t m = perm.size();
+    if (perm.empty()) return false;
     const float ofs = 0.5f - (float)klo_x;
-    std::vector<float> ysx(m);
-    for (size_t q = 0; q < m; ++q) {
-        const float y = tgt[3 * (size_t)perm[q]];
-        const float scaled = y * s;
-        ysx[q] = scaled + ofs;
-    }
-    const double lo = std::floor((double)ysx.front());
-    const double hi = std::floor((double)ysx.back());
+    const float first = tgt[3 * (size_t)perm.front()] * s;
+    const float last = tgt[3 * (size_t)perm.back()] * s;
+    const double lo = std::floor((double)(first + ofs));
+    const double hi = std::floor((double)(last + ofs));
     if (!(hi - lo < (double)(1 << 20))) return false;
-    *tab_lo = (int32_t)lo;
-    const size_t n = (size_t)kTabPerBin * ((size_t)(hi - lo) + 1) + 1;
-    tab->resize(n);
-    size_t j = 0;
-    for (size_t q = 0; q < n; ++q) {
-        const float v = (float)(lo + (double)q / kTabPerBin);
-        while (j < m && ysx[j] < v) ++j;
-        (*tab)[q] = (int32_t)j;
-    }
+    *ylo = (int32_t)lo;
+    *yhi = (int32_t)hi;
     return true;
+}
+
+void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, float *sb_scale)
+{
+    // a source votes only if some Y - P lies in [0, size_x): P in (ylo - size_x, yhi + 1)
+    const double lo = (double)ylo - size_x - 1;
+    const double range = (double)yhi + 2 - lo;
+    double scale = 4.0;
+    while (range * scale > kSrcBuckets && scale > 1.0 / (1 << 20)) scale *= 0.5;
+    *sb_lo = (float)lo;
+    *sb_scale = (float)scale;
 }
 
 dses_status apply_metric_options(const dses_options &o, Params *p)
@@ -454,20 +454,15 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
         sort_by_x(ht, job.m, &perm_local);
         perm = &perm_local;
     }
-    std::vector<int32_t> tab;
-    int32_t tab_lo = 0;
-    const bool sorted = job.n <= kSortMax &&
-                        build_x_table(ht, *perm, g.s, p.klo[0], &tab, &tab_lo);
+    int32_t ylo = 0, yhi = 0;
+    const bool sorted = job.n <= kSortMax && ref_x_range(ht, *perm, g.s, p.klo[0], &ylo, &yhi);
     const int grid = std::max(1, std::min(job.k, c->n_cu));
     if ((st = c->perm.ensure(m * sizeof(int32_t))) != DSES_OK) return st;
     DSES_HIP(hipMemcpyAsync(c->perm.ptr, perm->data(), m * sizeof(int32_t),
                             hipMemcpyHostToDevice, stream));
-    if (sorted) {
-        if ((st = c->tab.ensure(tab.size() * sizeof(int32_t))) != DSES_OK) return st;
-        if ((st = c->scratch.ensure((size_t)grid * job.n * sizeof(float4))) != DSES_OK) return st;
-        DSES_HIP(hipMemcpyAsync(c->tab.ptr, tab.data(), tab.size() * sizeof(int32_t),
-                                hipMemcpyHostToDevice, stream));
-    }
+    if (sorted &&
+        (st = c->scratch.ensure((size_t)grid * slot_floats(job.n) * sizeof(float))) != DSES_OK)
+        return st;
 
     if ((st = c->ys.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
     if ((st = c->yt.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
@@ -484,11 +479,9 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     a.rec = static_cast<dses_record *>(c->rec.ptr);
     a.k = job.k;
     a.g = g;
-    a.tab = sorted ? static_cast<int32_t *>(c->tab.ptr) : nullptr;
-    a.tab_lo = tab_lo;
-    a.tab_n = sorted ? (int32_t)tab.size() : 0;
-    a.scratch = sorted ? static_cast<float4 *>(c->scratch.ptr) : nullptr;
+    a.scratch = sorted ? static_cast<float *>(c->scratch.ptr) : nullptr;
     a.scratch_stride = job.n;
+    source_buckets(ylo, yhi, g.size[0], &a.sb_lo, &a.sb_scale);
 
     if (scorer == DSES_SCORER_GRID) {
         const TargetRes *t = job.target;

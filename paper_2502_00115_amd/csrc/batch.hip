@@ -39,15 +39,14 @@ struct Prepared {
     const TargetRes *target = nullptr;
     std::vector<int32_t> perm_local;
     const std::vector<int32_t> *perm = nullptr;
-    std::vector<int32_t> tab;
-    int32_t tab_lo = 0;
+    int32_t ylo = 0, yhi = 0;              // ref_x_range of the sorted reference
     bool sorted = false;
     HostGrid grid;                          // GRID scorer (non-resident targets)
     const float *grid_pts = nullptr;        // device (resident cache)
     const int32_t *grid_start = nullptr;
     // offsets into the arena (bytes)
     size_t off_src = 0, off_tgt = 0, off_rot = 0, off_ys = 0, off_yt = 0, off_perm = 0,
-           off_tab = 0, off_rec = 0, off_gpts = 0, off_gstart = 0;
+           off_rec = 0, off_gpts = 0, off_gstart = 0;
     void *records = nullptr;
     bool ready = false;
 };
@@ -79,7 +78,7 @@ BatchState *g_batch = nullptr;
 // Launch layout of a batch: work-list granularity and vote window parts.
 struct Layout {
     int items_per_cu = 24;
-    int parts_max = 8;
+    int vote_parts = 0;                // 0: vote_parts_auto
 };
 
 // Tuned layouts by batch class (count, scorer, log2 buckets of total pairs, mean
@@ -211,7 +210,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
     dses_batch_opts o{};
     if (opt) o = *opt;
     if (o.scorer < DSES_SCORER_AUTO || o.scorer > DSES_SCORER_DF || o.tile_rot < 0 ||
-        o.parts_max < 0 || o.parts_max > 8) {
+        o.vote_parts < 0 || o.vote_parts > 16) {
         set_error("invalid batch options");
         return DSES_E_INVAL;
     }
@@ -309,8 +308,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
             sort_by_x(ht, x.m, &x.perm_local);
             x.perm = &x.perm_local;
         }
-        x.sorted = x.n <= kSortMax && build_x_table(ht, *x.perm, x.g.s, x.p.klo[0], &x.tab,
-                                                    &x.tab_lo);
+        x.sorted = x.n <= kSortMax && ref_x_range(ht, *x.perm, x.g.s, x.p.klo[0], &x.ylo, &x.yhi);
         if (x.scorer == DSES_SCORER_GRID) {
             if (T) {
                 CellGrid cg{};
@@ -362,7 +360,6 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         x.off_ys = bump(arena_bytes, 3 * (size_t)x.m * sizeof(float));
         x.off_yt = bump(arena_bytes, 3 * (size_t)x.m * sizeof(float));
         x.off_perm = bump(arena_bytes, (size_t)x.m * sizeof(int32_t));
-        x.off_tab = bump(arena_bytes, std::max<size_t>(1, x.tab.size()) * sizeof(int32_t));
         x.off_rec = bump(arena_bytes, (size_t)x.k * sizeof(dses_record));
         if (x.scorer == DSES_SCORER_GRID && !T) {
             x.off_gpts = bump(arena_bytes, x.grid.pts.size() * sizeof(float));
@@ -417,9 +414,9 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         for (size_t t = 0; t < tiles.size(); ++t) (*list)[t] = tiles[t].it;
     };
     static const int kItemsPerCu[] = {6, 12, 24, 48, 96};
-    static const int kPartsMax[] = {1, 2, 4, 8};
+    static const int kVoteParts[] = {1, 2, 4, 8};
     const bool tune = (o.flags & DSES_BATCH_TUNE) != 0;
-    const bool caller_layout = o.tile_rot > 0 || o.parts_max > 0;
+    const bool caller_layout = o.tile_rot > 0 || o.vote_parts > 0;
     auto lg = [](double v) { return v >= 1.0 ? (int)std::floor(std::log2(v)) : 0; };
     const ClassKey key{count, batch_scorer, lg(total), lg(sum_n / std::max(1, n_ok)),
                        lg(sum_k / std::max(1, n_ok))};
@@ -434,7 +431,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
             cfg.sweep_ms = it->second.second;
         }
     }
-    if (o.parts_max > 0) lay.parts_max = o.parts_max;
+    if (o.vote_parts > 0) lay.vote_parts = o.vote_parts;
     if (caller_layout && !tune) cfg.source = 3;
     std::vector<BatchItem> items;
     int max_items = 0;
@@ -445,7 +442,8 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
     }
     build_items(lay.items_per_cu, &items);
     int n_items = (int)items.size();
-    if ((st = ensure_capacity(b, count, max_items, (size_t)grid * max_n * sizeof(float4))) != DSES_OK)
+    if ((st = ensure_capacity(b, count, max_items,
+                              (size_t)grid * slot_floats(max_n) * sizeof(float))) != DSES_OK)
         return st;
 
     std::vector<SweepArgs> inst(b->cap_count);
@@ -480,25 +478,19 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         int32_t *perm_dev = reinterpret_cast<int32_t *>(arena + x.off_perm);
         DSES_HIP(hipMemcpyAsync(perm_dev, x.perm->data(), (size_t)x.m * sizeof(int32_t),
                                 hipMemcpyHostToDevice, stream));
-        int32_t *tab_dev = reinterpret_cast<int32_t *>(arena + x.off_tab);
-        if (x.sorted)
-            DSES_HIP(hipMemcpyAsync(tab_dev, x.tab.data(), x.tab.size() * sizeof(int32_t),
-                                    hipMemcpyHostToDevice, stream));
         SweepArgs &a = inst[i];
         a = SweepArgs{};
         a.src = x.src;
         a.rot = x.rot;
         a.ys = reinterpret_cast<float *>(arena + x.off_ys);
         a.yt = reinterpret_cast<float *>(arena + x.off_yt);
-        a.tab = x.sorted ? tab_dev : nullptr;
-        a.tab_lo = x.tab_lo;
-        a.tab_n = x.sorted ? (int32_t)x.tab.size() : 0;
-        a.scratch = x.sorted ? static_cast<float4 *>(b->scratch.ptr) : nullptr;
+        a.scratch = x.sorted ? static_cast<float *>(b->scratch.ptr) : nullptr;
         a.scratch_stride = max_n;
+        source_buckets(x.ylo, x.yhi, x.g.size[0], &a.sb_lo, &a.sb_scale);
         a.g = x.g;
         a.rec = reinterpret_cast<dses_record *>(arena + x.off_rec);
         a.k = x.k;
-        a.parts_max = lay.parts_max;
+        a.vote_parts = lay.vote_parts;
         if (x.scorer == DSES_SCORER_GRID) {
             if (x.target) {
                 a.grid.pts = x.grid_pts;
@@ -564,7 +556,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         auto time_layout = [&](const Layout &L, float *ms) -> dses_status {
             build_items(L.items_per_cu, &items);
             header[0] = (int32_t)items.size();
-            for (int i = 0; i < count; ++i) inst[i].parts_max = L.parts_max;
+            for (int i = 0; i < count; ++i) inst[i].vote_parts = L.vote_parts;
             DSES_HIP(hipMemcpyAsync(b->items.ptr, items.data(), items.size() * sizeof(BatchItem),
                                     hipMemcpyHostToDevice, stream));
             DSES_HIP(hipMemcpyAsync(b->header.ptr, header, sizeof(header), hipMemcpyHostToDevice,
@@ -587,14 +579,14 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         dses_status tst = DSES_OK;
         if (o.tile_rot <= 0)
             for (int f : kItemsPerCu) {
-                Layout L{f, best.parts_max};
+                Layout L{f, best.vote_parts};
                 float ms = 0.0f;
                 if ((tst = time_layout(L, &ms)) != DSES_OK) break;
                 if (ms < best_ms) { best_ms = ms; best = L; }
             }
-        if (tst == DSES_OK && o.parts_max <= 0)
-            for (int gm : kPartsMax) {
-                if (gm == best.parts_max && best_ms < INFINITY) continue;
+        if (tst == DSES_OK && o.vote_parts <= 0)
+            for (int gm : kVoteParts) {
+                if (gm == best.vote_parts && best_ms < INFINITY) continue;
                 Layout L{best.items_per_cu, gm};
                 float ms = 0.0f;
                 if ((tst = time_layout(L, &ms)) != DSES_OK) break;
@@ -611,7 +603,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         build_items(lay.items_per_cu, &items);
         n_items = (int)items.size();
         header[0] = n_items;
-        for (int i = 0; i < count; ++i) inst[i].parts_max = lay.parts_max;
+        for (int i = 0; i < count; ++i) inst[i].vote_parts = lay.vote_parts;
         DSES_HIP(hipMemcpyAsync(b->items.ptr, items.data(), items.size() * sizeof(BatchItem),
                                 hipMemcpyHostToDevice, stream));
         DSES_HIP(hipMemcpyAsync(b->header.ptr, header, sizeof(header), hipMemcpyHostToDevice,
@@ -621,7 +613,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         DSES_HIP(hipStreamSynchronize(stream));
     }
     cfg.items_per_cu = o.tile_rot > 0 ? 0 : lay.items_per_cu;
-    cfg.parts_max = lay.parts_max;
+    cfg.vote_parts = lay.vote_parts;
     cfg.n_items = n_items;
 
     const bool timing = (o.flags & DSES_TIMING) != 0;

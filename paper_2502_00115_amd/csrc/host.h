@@ -46,7 +46,7 @@ struct Context {
     hipStream_t stream = nullptr;
     std::mutex mu;                       // serialises the plain entry points
     // workspace of the plain path
-    DevBuf in_src, in_tgt, in_rot, ys, yt, rec, res, status, grid_pts, grid_start, perm, tab, scratch;
+    DevBuf in_src, in_tgt, in_rot, ys, yt, rec, res, status, grid_pts, grid_start, perm, scratch;
     DevBuf topk_a, topk_b, topk_out;     // top-k passes and output staging
     DevBuf prune;                        // q-pruning: M* and the work cursor
     DevResult *host_res = nullptr;       // pinned
@@ -86,12 +86,14 @@ dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, i
 int64_t ref_block_population(const float *tgt_aos, int32_t m, const Params &p);
 int64_t counter_bound(const float *tgt_aos, int32_t m, int32_t n, const Params &p);
 
-// Reference order sorted by x, and the table tab[q] = first sorted index whose scaled
-// x coordinate is >= tab_lo + q / kTabPerBin (false if the coordinate range is too
-// wide).
+// Reference order sorted by x; the floors of the first and last scaled x
+// coordinates (ys_x = y_x * s + (0.5 - k_lo_x), the staging arithmetic) of that
+// order (false if they are too far apart for the sorted sweep); the source
+// bucket origin and scale of a box of size_x x-planes.
 void sort_by_x(const float *tgt_aos, int32_t m, std::vector<int32_t> *perm);
-bool build_x_table(const float *tgt_aos, const std::vector<int32_t> &perm, float s, int32_t klo_x,
-                   std::vector<int32_t> *tab, int32_t *tab_lo);
+bool ref_x_range(const float *tgt_aos, const std::vector<int32_t> &perm, float s, int32_t klo_x,
+                 int32_t *ylo, int32_t *yhi);
+void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, float *sb_scale);
 
 // Exact cell grid for the GRID scorer, built on the host from reference points.
 struct HostGrid {
@@ -123,8 +125,8 @@ struct TargetRes {
         float delta;
         int32_t klo[3];
         float *ys, *yt;
-        int32_t *tab;
-        int32_t tab_lo, tab_n;
+        bool sorted;                         // ref_x_range succeeded
+        int32_t ylo, yhi;                    // its result
     };
     std::deque<Stage> stages;                // deque: references survive push_back
     struct Population {                      // ref_block_population for (delta, box)

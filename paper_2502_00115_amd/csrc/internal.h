@@ -50,9 +50,20 @@ struct Field {
     float r;               // value outside the grid
 };
 
-constexpr int kSortBuckets = 1024;      // per-rotation source buckets (1 bin unit wide)
+// Per-rotation source sort: kSrcBuckets buckets over the scaled x coordinate,
+// sb_scale buckets per bin (a power of two, 4 when the reachable range fits).
+constexpr int kSrcBuckets = 8192;
 constexpr int kSortMax = 16384;         // largest source cloud that is bucket-sorted
-constexpr int kTabPerBin = 4;           // x-table entries per bin (reference windows)
+// Vote work units per 64-point lane group when not fixed by the caller: enough
+// units for every wave to take several (at most 8 per group).
+__host__ __device__ inline int vote_parts_auto(int groups)
+{
+    const int g = 64 / (groups > 0 ? groups : 1);
+    return g < 1 ? 1 : (g > 8 ? 8 : g);
+}
+constexpr int kUnitCounter = 200;       // LDS scratch word: next vote work unit
+constexpr int kSrcBmin = 210;           // LDS scratch words: lowest and highest occupied
+constexpr int kSrcBmax = 211;           // source bucket of the current rotation
 // Kernel scorer value for a vote-only sweep (records unscored: error +inf,
 // 0 inliers); the public scorers are DSES_SCORER_BRUTE / GRID / DF.
 constexpr int kScoreNone = 0;
@@ -67,17 +78,25 @@ struct SweepArgs {
     const float *rot;      // K x 9
     const float *ys;       // scaled + offset reference, SoA (3 * m), sorted by x
     const float *yt;       // reference, SoA (3 * m), same order
-    const int32_t *tab;    // tab[q] = first j with ys_x[j] >= tab_lo + q / kTabPerBin, q < tab_n
-    int32_t tab_lo, tab_n;
-    float4 *scratch;       // per workgroup slot: n rotated scaled sources, bucket-sorted by x
-    int64_t scratch_stride;   // float4 entries per slot (>= n)
+    float *scratch;        // per workgroup slot: the rotation's sources sorted by x (below)
+    int64_t scratch_stride;   // sources a slot holds (>= n)
+    float sb_lo, sb_scale;    // source bucket of P: floor((P - sb_lo) * sb_scale), clamped
     Geom g;
     CellGrid grid;
     Field field;
     dses_record *rec;      // one record per rotation index
     int32_t k;             // rotations
-    int32_t parts_max;     // most reference-window parts per 64-source group (0: 8)
+    int32_t vote_parts;    // reference-window parts per 64-source group (0: kVotePartsDefault)
 };
+
+// Scratch slot of one workgroup (floats): rotated scaled sources sorted by x as
+// three arrays x, y, z of src_stride(cap) floats each, then the bucket table
+// T[0 .. kSrcBuckets] (int32: T[b] = sources in buckets below b; T[kSrcBuckets] = n).
+__host__ __device__ inline int64_t src_stride(int64_t cap) { return (cap + 3) & ~int64_t(3); }
+__host__ __device__ inline int64_t slot_floats(int64_t cap)
+{
+    return (3 * src_stride(cap) + kSrcBuckets + 1 + 3) & ~int64_t(3);
+}
 
 // Batched registration.
 struct BatchItem {
@@ -91,7 +110,7 @@ struct BatchArgs {
     const BatchItem *items;    // work list, most expensive first
     const int32_t *header;     // header[0] = items, header[1] = instances
     uint32_t *cursor;          // work-list cursor, cleared before each launch
-    float4 *scratch;           // if set: this launch's source-sort scratch (overrides
+    float *scratch;            // if set: this launch's source-sort scratch (overrides
                                // the instances' own, so concurrent launches never share)
 };
 

@@ -251,36 +251,39 @@ __device__ __forceinline__ void vote_pair(uint32_t *hist, int cx, int cy, int cz
 
 typedef uint32_t f4u __attribute__((ext_vector_type(4)));
 
-// Buffer resource over the staged reference (x, y, z arrays of m floats); loads
-// past its end return zero instead of faulting.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t ref_rsrc(const float *ys, int m)
+// Buffer resource over a point set stored as three arrays (x, y, z) of `stride`
+// floats each (the staged reference, or a slot's sorted sources); loads past its
+// end return zero instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t soa_rsrc(const float *base, int64_t stride)
 {
     // word 3: 32-bit data format, no swizzle (raw buffer)
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(ys), 0, 12 * m, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), 0, (int)(12 * stride),
+                                             0x00020000);
 }
 
 // The same descriptor as four scalar words, for the asm loads below.
-__device__ __forceinline__ f4u ref_desc(const float *ys, int m)
+__device__ __forceinline__ f4u soa_desc(const float *base, int64_t stride)
 {
-    const uint64_t p = (uint64_t)(uintptr_t)ys;
+    const uint64_t p = (uint64_t)(uintptr_t)base;
     f4u d;
     d.x = __builtin_amdgcn_readfirstlane((uint32_t)p);
     d.y = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
-    d.z = (uint32_t)(12 * m);
+    d.z = (uint32_t)(12 * stride);
     d.w = 0x00020000u;
     return d;
 }
 
-// Reference points j .. j+3 (x, y, z): three 16-byte loads, the same address on
-// every lane.  Issued from asm together with ref_wait so that each wait covers
+// Points j .. j+3 (x, y, z) of such a set: three 16-byte loads, the same address
+// on every lane.  Issued from asm together with soa_wait so that each wait covers
 // exactly the group it needs: the compiler's own wait placement at this loop
 // depth sometimes drains every load in flight (vmcnt(0)), stalling each group
 // for a full memory round trip.  Every group issued here must be waited for
-// (ref_wait) before its registers die, or a late load could overwrite registers
+// (soa_wait) before its registers die, or a late load could overwrite registers
 // the compiler has reused.
-__device__ __forceinline__ void ref_issue4(const f4u &desc, int m, int j, f4u &x, f4u &y, f4u &z)
+__device__ __forceinline__ void soa_issue4(const f4u &desc, int stride, int j, f4u &x, f4u &y,
+                                           f4u &z)
 {
-    const int o0 = 4 * j, o1 = 4 * (m + j), o2 = 4 * (2 * m + j);
+    const int o0 = 4 * j, o1 = 4 * (stride + j), o2 = 4 * (2 * stride + j);
     asm volatile("buffer_load_dwordx4 %0, off, %3, %4\n\t"
                  "buffer_load_dwordx4 %1, off, %3, %5\n\t"
                  "buffer_load_dwordx4 %2, off, %3, %6"
@@ -291,33 +294,41 @@ __device__ __forceinline__ void ref_issue4(const f4u &desc, int m, int j, f4u &x
 // Wait until all but the newest N vector-memory operations are complete; the
 // group's registers pass through the asm so no use can be scheduled before it.
 template <int N>
-__device__ __forceinline__ void ref_wait(f4u &x, f4u &y, f4u &z)
+__device__ __forceinline__ void soa_wait(f4u &x, f4u &y, f4u &z)
 {
-    static_assert(N == 0 || N == 3, "ref_wait<0> or ref_wait<3>");
+    static_assert(N == 0 || N == 3, "soa_wait<0> or soa_wait<3>");
     if (N == 3)
         asm volatile("s_waitcnt vmcnt(3)" : "+v"(x), "+v"(y), "+v"(z));
     else
         asm volatile("s_waitcnt vmcnt(0)" : "+v"(x), "+v"(y), "+v"(z));
 }
 
-// One float of the staged reference (index into the x, y, z arrays).
-__device__ __forceinline__ float ref_load1(__amdgpu_buffer_rsrc_t rs, int i)
+// One float of such a set (index into the x, y, z arrays).
+__device__ __forceinline__ float soa_load1(__amdgpu_buffer_rsrc_t rs, int i)
 {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 0, 4 * i, 0));
 }
 
-// Votes of one source point (per lane) against four reference points.
-template <int CW>
-__device__ __forceinline__ void vote4(uint32_t *hist, f4u x, f4u y, f4u z, float Px, float Py,
-                                      float Pz, int x0, uint32_t np, uint32_t Sy, uint32_t Sz,
+// Votes of one lane point (Lx, Ly, Lz) against four streamed points (x, y, z).
+// LREF: the lane holds a reference point Y and the stream source points P,
+// else the reverse; either way the bin is floor(Y - P) per axis.
+template <int CW, bool LREF>
+__device__ __forceinline__ void vote4(uint32_t *hist, f4u x, f4u y, f4u z, float Lx, float Ly,
+                                      float Lz, int x0, uint32_t np, uint32_t Sy, uint32_t Sz,
                                       uint32_t sx4, uint32_t sy4, uint32_t negc)
 {
     int cx[4], cy[4], cz[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        cx[q] = cvt_flr(__uint_as_float(x[q]) - Px);
-        cy[q] = cvt_flr(__uint_as_float(y[q]) - Py);
-        cz[q] = cvt_flr(__uint_as_float(z[q]) - Pz);
+        if (LREF) {
+            cx[q] = cvt_flr(Lx - __uint_as_float(x[q]));
+            cy[q] = cvt_flr(Ly - __uint_as_float(y[q]));
+            cz[q] = cvt_flr(Lz - __uint_as_float(z[q]));
+        } else {
+            cx[q] = cvt_flr(__uint_as_float(x[q]) - Lx);
+            cy[q] = cvt_flr(__uint_as_float(y[q]) - Ly);
+            cz[q] = cvt_flr(__uint_as_float(z[q]) - Lz);
+        }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -336,163 +347,266 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-// Parts per 64-source group so that sw groups x G parts spread evenly over the
-// kWaves waves (fewest parts among the best spreads; at most gmax, itself <= 8).
-__device__ __forceinline__ int vote_parts(int sw, int gmax)
+// Votes of the lane point L against the streamed points [j0, j1) of a three-array
+// point set: groups of 4 points with two groups in flight, then single points.
+// The streamed coordinates come through the vector memory path (buffer loads):
+// scalar loads would share the LDS counter, and waiting for them would also wait
+// for every outstanding ds_add of the wave.
+template <int CW, bool LREF>
+__device__ __forceinline__ void vote_span(uint32_t *hist, const f4u &desc,
+                                          __amdgpu_buffer_rsrc_t rs, int stride, int j0, int j1,
+                                          float Lx, float Ly, float Lz, int x0, uint32_t np,
+                                          uint32_t Sy, uint32_t Sz, uint32_t sx4, uint32_t sy4,
+                                          uint32_t negc)
 {
-    gmax = gmax > 0 ? min(gmax, 8) : 8;
-    int best = 1, best_num = sw, best_den = kWaves * ((sw + kWaves - 1) / kWaves);
-    for (int G = 2; G <= gmax; ++G) {
-        const int num = sw * G, den = kWaves * ((num + kWaves - 1) / kWaves);
-        if (num * best_den > best_num * den) { best = G; best_num = num; best_den = den; }
+    int j = j0;
+    if (j + 4 <= j1) {
+        f4u ax, ay, az, bx, by, bz;
+        soa_issue4(desc, stride, j, ax, ay, az);
+        for (; j + 8 <= j1; j += 8) {
+            soa_issue4(desc, stride, j + 4, bx, by, bz);
+            soa_wait<3>(ax, ay, az);
+            vote4<CW, LREF>(hist, ax, ay, az, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
+            soa_issue4(desc, stride, min(j + 8, j1 - 4), ax, ay, az);
+            soa_wait<3>(bx, by, bz);
+            vote4<CW, LREF>(hist, bx, by, bz, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
+        }
+        soa_wait<0>(ax, ay, az);          // the last group issued, used or not
+        if (j + 4 <= j1) {
+            vote4<CW, LREF>(hist, ax, ay, az, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
+            j += 4;
+        }
     }
-    return best;
+    for (; j < j1; ++j) {
+        const float ux = soa_load1(rs, j), uy = soa_load1(rs, stride + j);
+        const float uz = soa_load1(rs, 2 * stride + j);
+        if (LREF)
+            vote_pair<CW>(hist, cvt_flr(Lx - ux), cvt_flr(Ly - uy), cvt_flr(Lz - uz), x0, np,
+                          Sy, Sz, sx4, sy4, negc);
+        else
+            vote_pair<CW>(hist, cvt_flr(ux - Lx), cvt_flr(uy - Ly), cvt_flr(uz - Lz), x0, np,
+                          Sy, Sz, sx4, sy4, negc);
+    }
 }
 
-// Reference index range [lo, hi) of the x-sorted reference whose pairs with any
-// source of x coordinate in [pmin, pmax] can fall in box x-planes [x0, x1):
-// floor(Y - P) in [x0, x1) implies Y in [P + x0, P + x1), widened by a margin that
-// exceeds the float rounding of Y - P and of the bounds; the table has kTabPerBin
-// entries per bin.  The per-pair x test stays exact, so the window only has to
-// contain every voting pair.
-__device__ __forceinline__ void ref_window(const SweepArgs &a, float pmin, float pmax, int x0,
+// Source bucket of a scaled x coordinate: floor((P - sb_lo) * sb_scale), clamped
+// to the table.  Monotone in P, which is all the vote windows rely on.
+__device__ __forceinline__ int src_bucket(const SweepArgs &a, float P)
+{
+    return min(max(cvt_flr(__fmul_rn(__fsub_rn(P, a.sb_lo), a.sb_scale)), 0), kSrcBuckets - 1);
+}
+
+// Index range [lo, hi) of the rotation's x-sorted sources whose pairs with any
+// reference point of x coordinate in [ymin, ymax] can fall in box x-planes
+// [x0, x1): floor(Y - P) in [x0, x1) implies P in (Y - x1, Y - x0], widened by a
+// margin that exceeds the float rounding of Y - P and of the bounds.  Bucketing
+// is monotone in P, so buckets b(ymin - x1 - e) .. b(ymax - x0 + e) hold every
+// voting source; the per-pair x test stays exact, so the range only has to
+// contain them.
+__device__ __forceinline__ void src_window(const SweepArgs &a, __amdgpu_buffer_rsrc_t trs,
+                                           int bmin, int bmax, float ymin, float ymax, int x0,
                                            int x1, int &lo, int &hi)
 {
-    const kint tab = kc(a.tab);
-    const float tl = (float)a.tab_lo;
-    // margin: 1/64 bin plus a bound on the float rounding of the sums below and of
-    // the per-pair subtraction (relative 2^-24 each, at most a few terms)
-    const float e = 0.015625f + 3.8e-6f * (fabsf(pmin) + fabsf(pmax) + fabsf((float)x0) +
-                                           fabsf((float)x1) + fabsf(tl));
-    const int qlo = cvt_flr((pmin + (float)x0 - tl - e) * (float)kTabPerBin);
-    const int qhi = cvt_flr((pmax + (float)x1 - tl + e) * (float)kTabPerBin) + 1;
-    lo = qlo <= 0 ? 0 : (qlo >= a.tab_n ? a.g.m : tab[qlo]);
-    hi = qhi <= 0 ? 0 : (qhi >= a.tab_n ? a.g.m : tab[qhi]);
+    const float e = 0.015625f + 3.8e-6f * (fabsf(ymin) + fabsf(ymax) + fabsf((float)x0) +
+                                           fabsf((float)x1) + fabsf(a.sb_lo));
+    // the table is written for buckets bmin .. bmax + 1 only (0 below, n above)
+    const int blo = min(max(src_bucket(a, ymin - (float)x1 - e), bmin), bmax + 1);
+    const int bhi = min(max(src_bucket(a, ymax - (float)x0 + e) + 1, bmin), bmax + 1);
+    lo = (int)__builtin_amdgcn_raw_buffer_load_b32(trs, 4 * blo, 0, 0);
+    hi = (int)__builtin_amdgcn_raw_buffer_load_b32(trs, 4 * bhi, 0, 0);
 }
 
+// Votes of all pairs whose bin falls in the box x-planes [x0, x0 + np) into the
+// LDS counters.  Work units are (64-point lane group, part of the group's stream
+// range), G parts per group; waves take units one at a time from an LDS counter
+// (cleared with the slab), so a wave whose ranges were short takes more units
+// instead of idling at the slab's closing barrier.
+//   sorted: lanes hold 64 consecutive points of the x-sorted reference, the
+//           stream is the window of the rotation's x-sorted sources;
+//   else:   lanes hold 64 rotated sources, the stream is the whole reference.
 template <int CW>
 __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, uint32_t *hist,
                           bool sorted, int slot)
 {
     const Geom &g = a.g;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
     const uint32_t Sy = g.size[1], Sz = g.size[2];
     const uint32_t sy4 = 4u * (uint32_t)g.row_words, sx4 = sy4 * Sy;
     const uint32_t negc = 0u - (uint32_t)x0 * sx4;
     const int m = g.m;
-    const __amdgpu_buffer_rsrc_t rs = ref_rsrc(a.ys, m);
-    const f4u desc = ref_desc(a.ys, m);
-    const float4 *mine = a.scratch + (size_t)slot * a.scratch_stride;
-    for (int c0 = 0; c0 < g.n; c0 += kBlock) {
-        // work units of this chunk: (64-source group, part of its reference window);
-        // the waves take units round-robin, so all kWaves vote even when the chunk
-        // has fewer than kWaves source groups
-        const int sw = (min(kBlock, g.n - c0) + 63) >> 6;
-        const int G = vote_parts(sw, a.parts_max);
-        for (int u = wave; u < sw * G; u += kWaves) {
-            const int part = u / sw;
-            const int i = c0 + (u - part * sw) * 64 + lane;
-            float Px = 1.0e7f, Py = 1.0e7f, Pz = 1.0e7f;      // padding lanes never vote
-            if (i < g.n) {
-                if (sorted) {
-                    const float4 P = mine[i];
-                    Px = P.x;
-                    Py = P.y;
-                    Pz = P.z;
-                } else {
-                    float px, py, pz;
-                    rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
-                    Px = __fmul_rn(px, g.s);
-                    Py = __fmul_rn(py, g.s);
-                    Pz = __fmul_rn(pz, g.s);
-                }
+    uint32_t *ctr = hist + kHistWordsMax + kUnitCounter;
+    if (sorted) {
+        const int ngr = (m + 63) >> 6;
+        const int G = a.vote_parts > 0 ? a.vote_parts : vote_parts_auto(ngr);
+        const int total = ngr * G;
+        const int64_t ns = src_stride(a.scratch_stride);
+        const float *sp = a.scratch + (size_t)slot * slot_floats(a.scratch_stride);
+        const f4u sdesc = soa_desc(sp, ns);
+        const __amdgpu_buffer_rsrc_t srs = soa_rsrc(sp, ns);
+        const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(sp + 3 * ns), 0, 4 * (kSrcBuckets + 1), 0x00020000);
+        const uint32_t *scr = hist + kHistWordsMax;
+        const int bmin = (int)__builtin_amdgcn_readfirstlane(scr[kSrcBmin]);
+        const int bmax = (int)__builtin_amdgcn_readfirstlane(scr[kSrcBmax]);
+        for (;;) {
+            int u = 0;
+            if (lane == 0) u = (int)atomicAdd(ctr, 1u);
+            u = __builtin_amdgcn_readfirstlane(u);
+            if (u >= total) break;
+            const int part = u / ngr;
+            const int gi = u - part * ngr;
+            const int j = gi * 64 + lane;
+            float Yx = -1.0e7f, Yy = -1.0e7f, Yz = -1.0e7f;   // padding lanes never vote
+            if (j < m) {
+                Yx = a.ys[j];
+                Yy = a.ys[m + j];
+                Yz = a.ys[2 * m + j];
             }
-            int lo = 0, hi = m;
-            if (sorted) {
-                const bool real = i < g.n;
-                const float pmin = wave_min(real ? Px : INFINITY);
-                const float pmax = wave_max(real ? Px : -INFINITY);
-                ref_window(a, pmin, pmax, x0, x0 + np, lo, hi);
-                lo = uni(lo);
-                hi = uni(max(hi, lo));
-            }
+            // the group's x range: its first and last point (the reference is sorted)
+            const float ymin = a.ys[gi * 64];
+            const float ymax = a.ys[min(m, gi * 64 + 64) - 1];
+            int lo, hi;
+            src_window(a, trs, bmin, bmax, ymin, ymax, x0, x0 + np, lo, hi);
+            lo = uni(lo);
+            hi = uni(max(hi, lo));
             const int j0 = uni(lo + (int)((int64_t)(hi - lo) * part / G));
             const int j1 = uni(lo + (int)((int64_t)(hi - lo) * (part + 1) / G));
-            // reference coordinates come through the vector memory path (buffer
-            // loads, two 4-point groups in flight): scalar loads would share the
-            // LDS counter, and waiting for them would also wait for every
-            // outstanding ds_add of the wave
-            int j = j0;
-            if (j + 4 <= j1) {
-                f4u ax, ay, az, bx, by, bz;
-                ref_issue4(desc, m, j, ax, ay, az);
-                for (; j + 8 <= j1; j += 8) {
-                    ref_issue4(desc, m, j + 4, bx, by, bz);
-                    ref_wait<3>(ax, ay, az);
-                    vote4<CW>(hist, ax, ay, az, Px, Py, Pz, x0, np, Sy, Sz, sx4, sy4, negc);
-                    ref_issue4(desc, m, min(j + 8, j1 - 4), ax, ay, az);
-                    ref_wait<3>(bx, by, bz);
-                    vote4<CW>(hist, bx, by, bz, Px, Py, Pz, x0, np, Sy, Sz, sx4, sy4, negc);
-                }
-                ref_wait<0>(ax, ay, az);          // the last group issued, used or not
-                if (j + 4 <= j1) {
-                    vote4<CW>(hist, ax, ay, az, Px, Py, Pz, x0, np, Sy, Sz, sx4, sy4, negc);
-                    j += 4;
-                }
+            vote_span<CW, true>(hist, sdesc, srs, (int)ns, j0, j1, Yx, Yy, Yz, x0, (uint32_t)np,
+                                Sy, Sz, sx4, sy4, negc);
+        }
+    } else {
+        const int nsg = (g.n + 63) >> 6;
+        const int G = a.vote_parts > 0 ? a.vote_parts : vote_parts_auto(nsg);
+        const int total = nsg * G;
+        const f4u rdesc = soa_desc(a.ys, m);
+        const __amdgpu_buffer_rsrc_t rrs = soa_rsrc(a.ys, m);
+        for (;;) {
+            int u = 0;
+            if (lane == 0) u = (int)atomicAdd(ctr, 1u);
+            u = __builtin_amdgcn_readfirstlane(u);
+            if (u >= total) break;
+            const int part = u / nsg;
+            const int i = (u - part * nsg) * 64 + lane;
+            float Px = 1.0e7f, Py = 1.0e7f, Pz = 1.0e7f;      // padding lanes never vote
+            if (i < g.n) {
+                float px, py, pz;
+                rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
+                Px = __fmul_rn(px, g.s);
+                Py = __fmul_rn(py, g.s);
+                Pz = __fmul_rn(pz, g.s);
             }
-            for (; j < j1; ++j) {
-                const float yx = ref_load1(rs, j), yy = ref_load1(rs, m + j);
-                const float yz = ref_load1(rs, 2 * m + j);
-                vote_pair<CW>(hist, cvt_flr(yx - Px), cvt_flr(yy - Py), cvt_flr(yz - Pz), x0,
-                              (uint32_t)np, Sy, Sz, sx4, sy4, negc);
-            }
+            const int j0 = uni((int)((int64_t)m * part / G));
+            const int j1 = uni((int)((int64_t)m * (part + 1) / G));
+            vote_span<CW, false>(hist, rdesc, rrs, m, j0, j1, Px, Py, Pz, x0, (uint32_t)np, Sy,
+                                 Sz, sx4, sy4, negc);
         }
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // asm-issued LDS atomics
 }
 
 // Bucket-sort the rotated, scaled source points of one rotation by x into this
-// workgroup's scratch slot (buckets one bin unit wide), so that each wave's 64
-// consecutive points span a narrow x range and can skip reference points whose
-// pairs cannot land in the current slab.
+// workgroup's scratch slot (x, y, z arrays) and write the bucket table after
+// them, so that the vote can restrict each 64-reference lane group to the sources
+// whose pairs can land in the current slab.
 __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, uint32_t *scr,
                              int slot)
 {
     const Geom &g = a.g;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint32_t *cnt = lds;                       // kSortBuckets counters
-    uint32_t *key = lds + kSortBuckets;        // per source: bucket << 20 | rank
-    float4 *out = a.scratch + (size_t)slot * a.scratch_stride;
-    for (int b = tid; b < kSortBuckets; b += kBlock) cnt[b] = 0u;
-    __syncthreads();
-    for (int i = tid; i < g.n; i += kBlock) {
-        float px, py, pz;
-        rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
-        const float Px = __fmul_rn(px, g.s);
-        const int b = min(max(cvt_flr(Px) + kSortBuckets / 2, 0), kSortBuckets - 1);
-        const uint32_t rank = atomicAdd(&cnt[b], 1u);
-        key[i] = ((uint32_t)b << 20) | rank;
+    uint32_t *cnt = lds;                       // kSrcBuckets counters
+    uint32_t *key = lds + kSrcBuckets;         // per source: bucket << 16 | rank
+    const int64_t ns = src_stride(a.scratch_stride);
+    float *ox = a.scratch + (size_t)slot * slot_floats(a.scratch_stride);
+    float *oy = ox + ns, *oz = ox + 2 * ns;
+    int32_t *T = reinterpret_cast<int32_t *>(ox + 3 * ns);
+    for (int b = tid; b < kSrcBuckets; b += kBlock) cnt[b] = 0u;
+    if (tid == 0) {
+        scr[kSrcBmin] = kSrcBuckets;
+        scr[kSrcBmax] = 0u;
     }
     __syncthreads();
-    // exclusive prefix sum of the bucket counts (one bucket per thread)
-    const uint32_t v = tid < kSortBuckets ? cnt[tid] : 0u;
-    uint32_t incl = v;
+    // the first kCarry points of each thread stay in registers between the two
+    // passes (no second load and rotation)
+    constexpr int kCarry = 4;
+    float cpx[kCarry], cpy[kCarry], cpz[kCarry];
+    uint32_t ckey[kCarry];
+#pragma unroll
+    for (int r = 0; r < kCarry; ++r) {
+        const int i = tid + r * kBlock;
+        if (i < g.n) {
+            float px, py, pz;
+            rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
+            cpx[r] = __fmul_rn(px, g.s);
+            cpy[r] = __fmul_rn(py, g.s);
+            cpz[r] = __fmul_rn(pz, g.s);
+            const int b = src_bucket(a, cpx[r]);
+            ckey[r] = ((uint32_t)b << 16) | atomicAdd(&cnt[b], 1u);
+        }
+    }
+    for (int i = tid + kCarry * kBlock; i < g.n; i += kBlock) {
+        float px, py, pz;
+        rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
+        const int b = src_bucket(a, __fmul_rn(px, g.s));
+        key[i] = ((uint32_t)b << 16) | atomicAdd(&cnt[b], 1u);
+    }
+    __syncthreads();
+    // exclusive prefix sum of the bucket counts: each thread owns kPer consecutive
+    // buckets; the offsets stay in LDS, and the table entries from the lowest to one
+    // past the highest occupied bucket go to the slot (below that range the table
+    // is 0 and above it n, which the vote gets by clamping)
+    constexpr int kPer = kSrcBuckets / kBlock;
+    uint32_t loc[kPer], sum = 0;
+    int first = kSrcBuckets, last = -1;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        loc[q] = cnt[kPer * tid + q];
+        sum += loc[q];
+        if (loc[q] != 0u) {
+            first = min(first, kPer * tid + q);
+            last = kPer * tid + q;
+        }
+    }
+    if (last >= 0) {
+        atomicMin(&scr[kSrcBmin], (uint32_t)first);
+        atomicMax(&scr[kSrcBmax], (uint32_t)last);
+    }
+    uint32_t incl = sum;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t o = __shfl_up(incl, off, 64);
         if (lane >= off) incl += o;
     }
     if (lane == 63) scr[160 + wave] = incl;
     __syncthreads();
-    uint32_t base = 0;
-    for (int w = 0; w < wave; ++w) base += scr[160 + w];
-    if (tid < kSortBuckets) cnt[tid] = base + incl - v;
+    uint32_t run = incl - sum;
+    for (int w = 0; w < wave; ++w) run += scr[160 + w];
+    const int bmin = (int)scr[kSrcBmin], bmax = (int)scr[kSrcBmax];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int b = kPer * tid + q;
+        cnt[b] = run;
+        if (b >= bmin && b <= bmax + 1) T[b] = (int32_t)run;
+        run += loc[q];
+    }
+    if (tid == kBlock - 1) T[kSrcBuckets] = (int32_t)run;
     __syncthreads();
-    for (int i = tid; i < g.n; i += kBlock) {
+#pragma unroll
+    for (int r = 0; r < kCarry; ++r) {
+        const int i = tid + r * kBlock;
+        if (i < g.n) {
+            const uint32_t pos = cnt[ckey[r] >> 16] + (ckey[r] & 0xFFFFu);
+            ox[pos] = cpx[r];
+            oy[pos] = cpy[r];
+            oz[pos] = cpz[r];
+        }
+    }
+    for (int i = tid + kCarry * kBlock; i < g.n; i += kBlock) {
         float px, py, pz;
         rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
         const uint32_t kk = key[i];
-        const uint32_t pos = cnt[kk >> 20] + (kk & 0xFFFFFu);
-        out[pos] = make_float4(__fmul_rn(px, g.s), __fmul_rn(py, g.s), __fmul_rn(pz, g.s), 0.0f);
+        const uint32_t pos = cnt[kk >> 16] + (kk & 0xFFFFu);
+        ox[pos] = __fmul_rn(px, g.s);
+        oy[pos] = __fmul_rn(py, g.s);
+        oz[pos] = __fmul_rn(pz, g.s);
     }
     __syncthreads();
 }
@@ -782,7 +896,7 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
     const Geom &g = a.g;
     uint32_t *hist = lds;
     uint32_t *scr = lds + kHistWordsMax;          // kScratchWords words
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const uint32_t Sy = g.size[1];
     const uint32_t RW = (uint32_t)g.row_words;
     const bool sorted = a.scratch != nullptr;
@@ -801,6 +915,7 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
         const int words4 = (words + 3) >> 2;
         uint4 *h4 = reinterpret_cast<uint4 *>(hist);
         for (int w = tid; w < words4; w += kBlock) h4[w] = make_uint4(0, 0, 0, 0);
+        if (tid == 0) scr[kUnitCounter] = 0u;
         __syncthreads();
         vote_slab<CW>(a, R, x0, np, hist, sorted, slot);
         __syncthreads();

@@ -92,18 +92,11 @@ dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stre
         DSES_HIP(hipMalloc(&tm->d_perm, 4 * m));
         DSES_HIP(hipMemcpy(tm->d_perm, tm->perm_x.data(), 4 * m, hipMemcpyHostToDevice));
     }
-    std::vector<int32_t> tab;
-    int32_t tab_lo = 0;
     const float s = 1.0f / p.delta;
-    const bool sorted = build_x_table(tm->host_aos.data(), tm->perm_x, s, p.klo[0], &tab, &tab_lo);
-    TargetRes::Stage st{p.delta, {p.klo[0], p.klo[1], p.klo[2]}, nullptr, nullptr, nullptr,
-                        tab_lo, sorted ? (int32_t)tab.size() : 0};
+    TargetRes::Stage st{p.delta, {p.klo[0], p.klo[1], p.klo[2]}, nullptr, nullptr, false, 0, 0};
+    st.sorted = ref_x_range(tm->host_aos.data(), tm->perm_x, s, p.klo[0], &st.ylo, &st.yhi);
     DSES_HIP(hipMalloc(&st.ys, 12 * m));
     DSES_HIP(hipMalloc(&st.yt, 12 * m));
-    if (sorted) {
-        DSES_HIP(hipMalloc(&st.tab, 4 * tab.size()));
-        DSES_HIP(hipMemcpy(st.tab, tab.data(), 4 * tab.size(), hipMemcpyHostToDevice));
-    }
     DSES_HIP(launch_stage(tm->aos, tm->d_perm, tm->m, s, p.klo, st.ys, st.yt, stream));
     DSES_HIP(hipStreamSynchronize(stream));
     tm->stages.push_back(st);
@@ -216,7 +209,7 @@ dses_status dses_target_destroy(dses_target *t)
     if (!t) return DSES_E_INVAL;
     TargetRes &T = t->res;
     for (auto &st : T.stages)
-        for (void *q : {(void *)st.ys, (void *)st.yt, (void *)st.tab})
+        for (void *q : {(void *)st.ys, (void *)st.yt})
             if (q) (void)hipFree(q);
     for (auto &g : T.grids) {
         if (g.pts) (void)hipFree(g.pts);

@@ -109,7 +109,7 @@ struct SliceSet {
     SelectDesc *h_sel = nullptr;             // pinned
     int32_t *h_header = nullptr;             // pinned
     void *d_items = nullptr, *d_sel = nullptr, *d_header = nullptr, *d_cursor = nullptr;
-    float4 *d_scratch = nullptr;             // source-sort scratch of this slice's launch
+    float *d_scratch = nullptr;              // source-sort scratch of this slice's launch
     hipEvent_t done = nullptr;
     hipStream_t stream = nullptr;            // stream the slice ran on
     bool busy = false;
@@ -223,7 +223,7 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
         DSES_HIP(hipMalloc(&s.d_sel, max_slots * sizeof(SelectDesc)));
         DSES_HIP(hipMalloc(&s.d_header, 64));
         DSES_HIP(hipMalloc(&s.d_cursor, 64));
-        DSES_HIP(hipMalloc(&s.d_scratch, (size_t)grid * kServeMaxSrc * sizeof(float4)));
+        DSES_HIP(hipMalloc(&s.d_scratch, (size_t)grid * slot_floats(kServeMaxSrc) * sizeof(float)));
         DSES_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
     }
     for (int i = max_slots - 1; i >= 0; --i) free_slots.push_back(i);
@@ -298,12 +298,10 @@ dses_status ServerImpl::prepare(Request *r)
     a.rot = r->rots->rot;
     a.ys = stg->ys;
     a.yt = stg->yt;
-    const bool sorted = r->n <= kSortMax && stg->tab_n > 0;
-    a.tab = sorted ? stg->tab : nullptr;
-    a.tab_lo = stg->tab_lo;
-    a.tab_n = sorted ? stg->tab_n : 0;
-    a.scratch = sorted ? reinterpret_cast<float4 *>(1) : nullptr;   // per-slice scratch at launch
+    const bool sorted = r->n <= kSortMax && stg->sorted;
+    a.scratch = sorted ? reinterpret_cast<float *>(4) : nullptr;   // per-slice scratch at launch
     a.scratch_stride = kServeMaxSrc;
+    source_buckets(stg->ylo, stg->yhi, g.size[0], &a.sb_lo, &a.sb_scale);
     a.g = g;
     a.grid = cg;
     if (r->scorer == DSES_SCORER_DF) {

@@ -81,12 +81,12 @@ class Problem(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("flags", C.c_uint32), ("scorer", C.c_int32),
-                ("use_graph", C.c_int32), ("tile_rot", C.c_int32), ("parts_max", C.c_int32),
+                ("use_graph", C.c_int32), ("tile_rot", C.c_int32), ("vote_parts", C.c_int32),
                 ("stream", C.c_void_p)]
 
 
 class BatchConfig(C.Structure):
-    _fields_ = [("items_per_cu", C.c_int32), ("parts_max", C.c_int32), ("n_items", C.c_int32),
+    _fields_ = [("items_per_cu", C.c_int32), ("vote_parts", C.c_int32), ("n_items", C.c_int32),
                 ("source", C.c_int32), ("candidates", C.c_int32), ("sweep_ms", C.c_float)]
 
 
@@ -401,7 +401,7 @@ def register_resident(target: Target, rotset: RotationSet, src, eps, metric="tru
                    _records_out(tbuf, CANDIDATE_DTYPE) if tbuf is not None else None)
 
 
-def register_batch(problems, *, scorer="auto", use_graph=True, tile_rot=0, parts_max=0,
+def register_batch(problems, *, scorer="auto", use_graph=True, tile_rot=0, vote_parts=0,
                    autotune=False, records=False, timing=False, stream=None):
     """dses_register_batch over dicts with keys src, tgt/target, rotations/rotset, eps,
     and optionally metric, delta_t, tau, t_min, t_max.  Returns (results, statuses).
@@ -436,7 +436,7 @@ def register_batch(problems, *, scorer="auto", use_graph=True, tile_rot=0, parts
             bufs.append(None)
     o = BatchOpts(C.sizeof(BatchOpts), (DEVICE_PTRS if args.device else 0) |
                   (TIMING if timing else 0) | (BATCH_TUNE if autotune else 0), SCORERS[scorer],
-                  int(bool(use_graph)), int(tile_rot), int(parts_max),
+                  int(bool(use_graph)), int(tile_rot), int(vote_parts),
                   _stream_of(stream) if args.device else None)
     res = (Result * len(problems))()
     st = (C.c_int32 * len(problems))()
@@ -469,7 +469,7 @@ def batch_last_config() -> dict:
     cfg = BatchConfig()
     _check(lib().dses_batch_last_config(C.byref(cfg)))
     source = {0: "default", 1: "tuned", 2: "tuned-cache", 3: "caller"}[cfg.source]
-    return {"items_per_cu": cfg.items_per_cu, "parts_max": cfg.parts_max,
+    return {"items_per_cu": cfg.items_per_cu, "vote_parts": cfg.vote_parts,
             "n_items": cfg.n_items, "source": source, "candidates": cfg.candidates,
             "sweep_ms": cfg.sweep_ms}
 

@@ -73,7 +73,7 @@ def test_argument_errors_need_no_gpu(libpath):
         assert e.value.status == dses.DSES_E_INVAL, (q, e.value)
     item = {"src": np.zeros((3, 3)), "tgt": np.zeros((4, 3)),
             "rotations": np.eye(3).reshape(1, 9), "eps": 0.05}
-    for kw in ({"parts_max": 9}, {"parts_max": -1}, {"tile_rot": -2}):
+    for kw in ({"vote_parts": 17}, {"vote_parts": -1}, {"tile_rot": -2}):
         with pytest.raises(dses.DsesError) as e:
             dses.register_batch([item], **kw)
         assert e.value.status == dses.DSES_E_INVAL, (kw, e.value)

@@ -220,7 +220,7 @@ def test_autotune_keeps_results_and_caches_the_layout():
     assert st == [0] * len(probs)
     cfg = dses.batch_last_config()
     assert cfg["source"] == "tuned" and cfg["candidates"] >= 8
-    assert cfg["items_per_cu"] in (6, 12, 24, 48, 96) and cfg["parts_max"] in (1, 2, 4, 8)
+    assert cfg["items_per_cu"] in (6, 12, 24, 48, 96) and cfg["vote_parts"] in (0, 1, 2, 4, 8)
     assert cfg["sweep_ms"] > 0.0
     for a, b in zip(base, tuned):
         _same(a, b)
@@ -230,20 +230,21 @@ def test_autotune_keeps_results_and_caches_the_layout():
     assert st == [0] * len(probs)
     cfg2 = dses.batch_last_config()
     assert cfg2["source"] == "tuned-cache"
-    assert (cfg2["items_per_cu"], cfg2["parts_max"]) == (cfg["items_per_cu"], cfg["parts_max"])
+    assert (cfg2["items_per_cu"], cfg2["vote_parts"]) == (cfg["items_per_cu"], cfg["vote_parts"])
     for a, b in zip(base, again):
         assert a.records.tobytes() == b.records.tobytes()
 
 
-@pytest.mark.parametrize("parts_max", [1, 2, 3, 8])
-def test_vote_window_split_does_not_change_results(parts_max):
-    # sources of 150..900 points: 3..15 groups of 64, split into up to parts_max parts
+@pytest.mark.parametrize("vote_parts", [1, 2, 3, 8, 16])
+def test_vote_window_split_does_not_change_results(vote_parts):
+    # references of 512..4096 points: 8..64 lane groups of 64, each group's source
+    # window split into vote_parts units (an uneven 3 and more parts than points included)
     probs = _small_c3(count=4, k=256, seed=8)
     alone = [dses.register(p.src, p.tgt, p.rotations, p.eps, records=True) for p in probs]
-    got, st = dses.register_batch([_as_dict(p) for p in probs], parts_max=parts_max,
+    got, st = dses.register_batch([_as_dict(p) for p in probs], vote_parts=vote_parts,
                                   tile_rot=7, records=True)
     assert st == [0] * len(probs)
     cfg = dses.batch_last_config()
-    assert cfg["source"] == "caller" and cfg["parts_max"] == parts_max
+    assert cfg["source"] == "caller" and cfg["vote_parts"] == vote_parts
     for a, b in zip(alone, got):
         assert a.records.tobytes() == b.records.tobytes()

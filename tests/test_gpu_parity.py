@@ -95,7 +95,10 @@ def test_runs_on_a_side_stream():
 # ragged sizes, boxes and counter widths
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n,m,k", [(1, 1, 1), (1, 300, 7), (65, 1, 5), (65, 1023, 33),
-                                   (130, 77, 9), (1025, 40, 3), (2100, 260, 4)])
+                                   (130, 77, 9), (1025, 40, 3), (2100, 260, 4),
+                                   # past the points each thread keeps in registers while
+                                   # sorting, the largest sorted source, the first unsorted
+                                   (4200, 700, 3), (16384, 130, 2), (16385, 100, 2)])
 def test_ragged_sizes(n, m, k):
     rng = np.random.default_rng(n * 7 + m)
     tgt = rng.uniform(-0.8, 0.8, (m, 3)).astype(np.float32)
@@ -122,6 +125,23 @@ def test_asymmetric_box():
     p = synth.make_c1(8)
     got, ref = run_both(p, t_min=[-0.3, -1.0, 0.0], t_max=[0.9, 0.2, 0.75])
     compare_records(got.records, ref, len(p.src))
+
+
+@pytest.mark.parametrize("spread", [0.5, 3.0])
+def test_coarse_source_buckets(spread):
+    """A box 4,001 bins long in x (delta 1 mm) and references spread over +-spread:
+    the sources' reachable x range (about 5,000 or 10,000 bins) no longer fits 4
+    buckets per bin, so the sort uses 1 or 1/2 bucket per bin."""
+    rng = np.random.default_rng(31)
+    tgt = rng.uniform(-0.5, 0.5, (300, 3)).astype(np.float32)
+    tgt[:, 0] *= 2 * spread
+    src = (tgt[rng.integers(0, 300, 200)] + rng.normal(0, 0.0005, (200, 3))).astype(np.float32)
+    rots = np.vstack([np.eye(3).reshape(1, 9), synth.random_rotations(rng, 3).reshape(-1, 9)])
+    p = synth.Problem(src, tgt, rots.astype(np.float32), 0.02, np.eye(3), np.zeros(3))
+    box = dict(delta_t=0.001, t_min=[-2.0, -0.02, -0.02], t_max=[2.0, 0.02, 0.02])
+    got, ref = run_both(p, **box)
+    assert ref["votes"][0] > 50
+    compare_records(got.records, ref, len(src), label=f"spread {spread}")
 
 
 def test_32bit_counters_when_16bit_could_overflow():

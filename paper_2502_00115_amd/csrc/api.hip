@@ -350,7 +350,8 @@ bool ref_x_range(const float *tgt, const std::vector<int32_t> &perm, float s, in
     return true;
 }
 
-void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, float *sb_scale)
+void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, float *sb_scale,
+                    int32_t *sb_n)
 {
     // a source votes only if some Y - P lies in [0, size_x): P in (ylo - size_x, yhi + 1)
     const double lo = (double)ylo - size_x - 1;
@@ -359,6 +360,9 @@ void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, floa
     while (range * scale > kSrcBuckets && scale > 1.0 / (1 << 20)) scale *= 0.5;
     *sb_lo = (float)lo;
     *sb_scale = (float)scale;
+    // only as many buckets as the range needs (the sort clears and scans them all)
+    const int need = (int)std::ceil(range * scale) + 1;
+    *sb_n = std::min(kSrcBuckets, (need + kBlock - 1) / kBlock * kBlock);
 }
 
 dses_status apply_metric_options(const dses_options &o, Params *p)
@@ -481,7 +485,7 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     a.g = g;
     a.scratch = sorted ? static_cast<float *>(c->scratch.ptr) : nullptr;
     a.scratch_stride = job.n;
-    source_buckets(ylo, yhi, g.size[0], &a.sb_lo, &a.sb_scale);
+    source_buckets(ylo, yhi, g.size[0], &a.sb_lo, &a.sb_scale, &a.sb_n);
 
     if (scorer == DSES_SCORER_GRID) {
         const TargetRes *t = job.target;

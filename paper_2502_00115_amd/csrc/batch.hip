@@ -486,7 +486,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         a.yt = reinterpret_cast<float *>(arena + x.off_yt);
         a.scratch = x.sorted ? static_cast<float *>(b->scratch.ptr) : nullptr;
         a.scratch_stride = max_n;
-        source_buckets(x.ylo, x.yhi, x.g.size[0], &a.sb_lo, &a.sb_scale);
+        source_buckets(x.ylo, x.yhi, x.g.size[0], &a.sb_lo, &a.sb_scale, &a.sb_n);
         a.g = x.g;
         a.rec = reinterpret_cast<dses_record *>(arena + x.off_rec);
         a.k = x.k;

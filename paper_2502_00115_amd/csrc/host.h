@@ -93,7 +93,8 @@ int64_t counter_bound(const float *tgt_aos, int32_t m, int32_t n, const Params &
 void sort_by_x(const float *tgt_aos, int32_t m, std::vector<int32_t> *perm);
 bool ref_x_range(const float *tgt_aos, const std::vector<int32_t> &perm, float s, int32_t klo_x,
                  int32_t *ylo, int32_t *yhi);
-void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, float *sb_scale);
+void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, float *sb_scale,
+                    int32_t *sb_n);
 
 // Exact cell grid for the GRID scorer, built on the host from reference points.
 struct HostGrid {

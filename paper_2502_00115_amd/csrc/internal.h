@@ -50,8 +50,9 @@ struct Field {
     float r;               // value outside the grid
 };
 
-// Per-rotation source sort: kSrcBuckets buckets over the scaled x coordinate,
-// sb_scale buckets per bin (a power of two, 4 when the reachable range fits).
+// Per-rotation source sort: sb_n buckets (a multiple of the block size, at most
+// kSrcBuckets) over the scaled x coordinate, sb_scale buckets per bin (a power
+// of two, 4 when the reachable range fits).
 constexpr int kSrcBuckets = 8192;
 constexpr int kSortMax = 16384;         // largest source cloud that is bucket-sorted
 // Vote work units per 64-point lane group when not fixed by the caller: enough
@@ -81,6 +82,7 @@ struct SweepArgs {
     float *scratch;        // per workgroup slot: the rotation's sources sorted by x (below)
     int64_t scratch_stride;   // sources a slot holds (>= n)
     float sb_lo, sb_scale;    // source bucket of P: floor((P - sb_lo) * sb_scale), clamped
+    int32_t sb_n;             // to [0, sb_n)
     Geom g;
     CellGrid grid;
     Field field;

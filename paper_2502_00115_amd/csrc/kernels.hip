@@ -393,7 +393,7 @@ __device__ __forceinline__ void vote_span(uint32_t *hist, const f4u &desc,
 // to the table.  Monotone in P, which is all the vote windows rely on.
 __device__ __forceinline__ int src_bucket(const SweepArgs &a, float P)
 {
-    return min(max(cvt_flr(__fmul_rn(__fsub_rn(P, a.sb_lo), a.sb_scale)), 0), kSrcBuckets - 1);
+    return min(max(cvt_flr(__fmul_rn(__fsub_rn(P, a.sb_lo), a.sb_scale)), 0), a.sb_n - 1);
 }
 
 // Index range [lo, hi) of the rotation's x-sorted sources whose pairs with any
@@ -409,11 +409,14 @@ __device__ __forceinline__ void src_window(const SweepArgs &a, __amdgpu_buffer_r
 {
     const float e = 0.015625f + 3.8e-6f * (fabsf(ymin) + fabsf(ymax) + fabsf((float)x0) +
                                            fabsf((float)x1) + fabsf(a.sb_lo));
-    // the table is written for buckets bmin .. bmax + 1 only (0 below, n above)
-    const int blo = min(max(src_bucket(a, ymin - (float)x1 - e), bmin), bmax + 1);
-    const int bhi = min(max(src_bucket(a, ymax - (float)x0 + e) + 1, bmin), bmax + 1);
-    lo = (int)__builtin_amdgcn_raw_buffer_load_b32(trs, 4 * blo, 0, 0);
-    hi = (int)__builtin_amdgcn_raw_buffer_load_b32(trs, 4 * bhi, 0, 0);
+    // the table holds buckets bmin .. bmax only (0 below, n above)
+    const int blo = max(src_bucket(a, ymin - (float)x1 - e), bmin);
+    const int bhi = max(src_bucket(a, ymax - (float)x0 + e) + 1, bmin);
+    // both loads issued unconditionally (one memory round trip), then n selected
+    const int tlo = (int)__builtin_amdgcn_raw_buffer_load_b32(trs, 4 * min(blo, bmax), 0, 0);
+    const int thi = (int)__builtin_amdgcn_raw_buffer_load_b32(trs, 4 * min(bhi, bmax), 0, 0);
+    lo = blo > bmax ? a.g.n : tlo;
+    hi = bhi > bmax ? a.g.n : thi;
 }
 
 // Votes of all pairs whose bin falls in the box x-planes [x0, x0 + np) into the
@@ -519,11 +522,7 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
     float *ox = a.scratch + (size_t)slot * slot_floats(a.scratch_stride);
     float *oy = ox + ns, *oz = ox + 2 * ns;
     int32_t *T = reinterpret_cast<int32_t *>(ox + 3 * ns);
-    for (int b = tid; b < kSrcBuckets; b += kBlock) cnt[b] = 0u;
-    if (tid == 0) {
-        scr[kSrcBmin] = kSrcBuckets;
-        scr[kSrcBmax] = 0u;
-    }
+    for (int b = tid; b < a.sb_n; b += kBlock) cnt[b] = 0u;
     __syncthreads();
     // the first kCarry points of each thread stay in registers between the two
     // passes (no second load and rotation)
@@ -550,25 +549,18 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
         key[i] = ((uint32_t)b << 16) | atomicAdd(&cnt[b], 1u);
     }
     __syncthreads();
-    // exclusive prefix sum of the bucket counts: each thread owns kPer consecutive
-    // buckets; the offsets stay in LDS, and the table entries from the lowest to one
-    // past the highest occupied bucket go to the slot (below that range the table
-    // is 0 and above it n, which the vote gets by clamping)
-    constexpr int kPer = kSrcBuckets / kBlock;
-    uint32_t loc[kPer], sum = 0;
-    int first = kSrcBuckets, last = -1;
+    // exclusive prefix sum of the bucket counts: each thread owns `per` consecutive
+    // buckets; the offsets stay in LDS, and the table entries of the lowest to the
+    // highest occupied bucket go to the slot (below that range the table is 0 and
+    // above it n, which the vote takes without reading it).  The two bounds are
+    // the unique buckets where the prefix leaves 0 and where it reaches n.
+    constexpr int kPerMax = kSrcBuckets / kBlock;
+    const int per = a.sb_n / kBlock;
+    uint32_t loc[kPerMax], sum = 0;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        loc[q] = cnt[kPer * tid + q];
+    for (int q = 0; q < kPerMax; ++q) {
+        loc[q] = q < per ? cnt[per * tid + q] : 0u;
         sum += loc[q];
-        if (loc[q] != 0u) {
-            first = min(first, kPer * tid + q);
-            last = kPer * tid + q;
-        }
-    }
-    if (last >= 0) {
-        atomicMin(&scr[kSrcBmin], (uint32_t)first);
-        atomicMax(&scr[kSrcBmax], (uint32_t)last);
     }
     uint32_t incl = sum;
     for (int off = 1; off < 64; off <<= 1) {
@@ -579,15 +571,20 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
     __syncthreads();
     uint32_t run = incl - sum;
     for (int w = 0; w < wave; ++w) run += scr[160 + w];
-    const int bmin = (int)scr[kSrcBmin], bmax = (int)scr[kSrcBmax];
+    const uint32_t n = (uint32_t)g.n;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int b = kPer * tid + q;
-        cnt[b] = run;
-        if (b >= bmin && b <= bmax + 1) T[b] = (int32_t)run;
-        run += loc[q];
+    for (int q = 0; q < kPerMax; ++q) {
+        if (q < per) {
+            const int b = per * tid + q;
+            cnt[b] = run;
+            if (loc[q] != 0u) {
+                if (run == 0u) scr[kSrcBmin] = (uint32_t)b;
+                if (run + loc[q] == n) scr[kSrcBmax] = (uint32_t)b;
+            }
+            if (run + loc[q] != 0u && run < n) T[b] = (int32_t)run;
+            run += loc[q];
+        }
     }
-    if (tid == kBlock - 1) T[kSrcBuckets] = (int32_t)run;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kCarry; ++r) {

@@ -301,7 +301,7 @@ dses_status ServerImpl::prepare(Request *r)
     const bool sorted = r->n <= kSortMax && stg->sorted;
     a.scratch = sorted ? reinterpret_cast<float *>(4) : nullptr;   // per-slice scratch at launch
     a.scratch_stride = kServeMaxSrc;
-    source_buckets(stg->ylo, stg->yhi, g.size[0], &a.sb_lo, &a.sb_scale);
+    source_buckets(stg->ylo, stg->yhi, g.size[0], &a.sb_lo, &a.sb_scale, &a.sb_n);
     a.g = g;
     a.grid = cg;
     if (r->scorer == DSES_SCORER_DF) {

@@ -13,6 +13,7 @@ on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -29,12 +30,21 @@ WORKLOADS = ("c2", "c1", "c5", "c3", "c4", "local", "fig2", "exhaustive")
 SWEEP_SOURCES = ("api.hip", "internal.h", "kernels.hip")
 
 
+def _code_only(text):
+    """Source text without comments and with whitespace collapsed (string literals
+    in these files hold no comment markers), so that editing a comment does not
+    invalidate counters taken on the same code."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
     for name in SWEEP_SOURCES:
-        with open(os.path.join(ROOT, "paper_2502_00115_amd", "csrc", name), "rb") as f:
+        with open(os.path.join(ROOT, "paper_2502_00115_amd", "csrc", name), encoding="utf-8") as f:
             h.update(name.encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

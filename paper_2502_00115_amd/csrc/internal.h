@@ -88,7 +88,7 @@ struct SweepArgs {
     Field field;
     dses_record *rec;      // one record per rotation index
     int32_t k;             // rotations
-    int32_t vote_parts;    // reference-window parts per 64-source group (0: kVotePartsDefault)
+    int32_t vote_parts;    // stream-window parts per 64-point lane group (0: vote_parts_auto)
 };
 
 // Scratch slot of one workgroup (floats): rotated scaled sources sorted by x as

@@ -3,11 +3,12 @@
 //
 // Sweep design (one workgroup of 16 wave64s per rotation, one workgroup per CU):
 //  * Source points are rotated and scaled once per rotation and bucket-sorted by
-//    x into a per-workgroup scratch slot; in the vote each lane holds one source.
-//  * Reference points are wave-uniform: every lane of a wave walks the same
-//    reference index of the x-sorted reference, restricted to the window whose
-//    pairs can land in the current slab.  They arrive through 16-byte buffer
-//    loads (same address on every lane), two groups of 4 in flight.
+//    x into a per-workgroup scratch slot (x, y, z arrays and a bucket table).
+//  * In the vote each lane holds one point of the x-sorted reference (64
+//    consecutive points per work unit) and the sources are wave-uniform: every
+//    lane walks the same source index, restricted to the window whose pairs can
+//    land in the current slab.  They arrive through 16-byte buffer loads (same
+//    address on every lane), two groups of 4 in flight.
 //  * The vote array of Alg. 2 lives in LDS as 16-bit counters packed two per
 //    32-bit word (incremented with ds_add_u32 of 1 or 1<<16), so the 41^3 box of
 //    delta = 0.05 fits one allocation.  Larger boxes are swept in x-slabs that
@@ -16,8 +17,9 @@
 //    counter is 32-bit.
 //  * The mode per slab: the largest count by a packed 16-bit max over the slab,
 //    then, only when it beats the earlier slabs, its lowest linear index.
-//  * Scoring reuses the rotated sources; the error sum is a fixed-order tree,
-//    so a rotation's record does not depend on what else runs on the GPU.
+//  * Scoring rotates the sources again, in input order; the error sum is a
+//    fixed-order tree, so a rotation's record does not depend on what else runs
+//    on the GPU.
 #include <hip/hip_runtime.h>
 
 #include <utility>

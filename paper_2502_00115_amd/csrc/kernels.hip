@@ -612,9 +612,10 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
-// Largest counter of a slab (words4 uint4 of counters), workgroup-uniform.
+// Largest counter of a slab (words4 uint4 of counters), workgroup-uniform;
+// `mine` receives the largest counter among this thread's own words.
 template <int CW>
-__device__ uint32_t slab_max(const uint32_t *hist, int words4, uint32_t *scr)
+__device__ uint32_t slab_max(const uint32_t *hist, int words4, uint32_t *scr, uint32_t &mine)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint4 *h4 = reinterpret_cast<const uint4 *>(hist);
@@ -635,6 +636,7 @@ __device__ uint32_t slab_max(const uint32_t *hist, int words4, uint32_t *scr)
             mx = max(mx, max(max(v.x, v.y), max(v.z, v.w)));
         }
     }
+    mine = mx;
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
     if (lane == 0) scr[8 + wave] = mx;
     __syncthreads();
@@ -646,14 +648,17 @@ __device__ uint32_t slab_max(const uint32_t *hist, int words4, uint32_t *scr)
 }
 
 // Lowest position (word index * 2 + half for 16-bit counters) whose count is c.
+// Only threads whose own largest counter (`mine` of slab_max) is c can hold it,
+// so the others skip the scan.
 template <int CW>
 __device__ uint32_t slab_first(const uint32_t *hist, int words4, uint32_t c, uint32_t pos0,
-                               uint32_t *scr)
+                               uint32_t *scr, uint32_t mine)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint4 *h4 = reinterpret_cast<const uint4 *>(hist);
     uint32_t best = 0xFFFFFFFFu;
-    for (int w = tid; w < words4 && best == 0xFFFFFFFFu; w += kBlock) {
+    const int wend = mine == c ? words4 : 0;
+    for (int w = tid; w < wend && best == 0xFFFFFFFFu; w += kBlock) {
         const uint4 v = h4[w];
         const uint32_t e[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -922,9 +927,10 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
         // the earlier slabs its lowest position (a later slab never wins a tie: its
         // positions are higher)
         const uint32_t pos0 = (uint32_t)x0 * Sy * RW * (CW == 16 ? 2u : 1u);
-        const uint32_t smax = slab_max<CW>(hist, words4, scr);
+        uint32_t mine;
+        const uint32_t smax = slab_max<CW>(hist, words4, scr, mine);
         if (smax > best_c) {
-            best_p = slab_first<CW>(hist, words4, smax, pos0, scr);
+            best_p = slab_first<CW>(hist, words4, smax, pos0, scr, mine);
             best_c = smax;
         }
         __syncthreads();                      // scr / hist reused by the next slab

@@ -262,10 +262,10 @@ dses_status build_grid(const float *tgt, int32_t m, float r, HostGrid *out)
     }
     for (int64_t q = 0; q < ncell; ++q) out->start[q + 1] += out->start[q];
     std::vector<int32_t> cur(out->start.begin(), out->start.end() - 1);
-    out->pts.assign((size_t)3 * m, 0.0f);
+    out->pts.assign((size_t)4 * m, 0.0f);
     for (int32_t j = 0; j < m; ++j) {
         const int32_t at = cur[cell[j]]++;
-        for (int a = 0; a < 3; ++a) out->pts[(size_t)a * m + at] = tgt[3 * j + a];
+        for (int a = 0; a < 3; ++a) out->pts[(size_t)4 * at + a] = tgt[3 * j + a];
     }
     return DSES_OK;
 }

@@ -21,12 +21,11 @@ __device__ __forceinline__ int flr_i(float x)
 }
 
 struct DfArgs {
-    const float *pts;        // SoA, cell order
+    const float *pts;        // x y z and a pad per point (16 B), cell order
     const int32_t *start;    // ncell + 1
     float glo[3];
     float ginv;
     int32_t gdim[3];
-    int32_t m;
     int32_t res;
     float lo[3], h[3];
     float r2, r;
@@ -47,7 +46,7 @@ __global__ void __launch_bounds__(256) k_df_build(DfArgs a)
         const int gx = flr_i(__fmul_rn(cx - a.glo[0], a.ginv));
         const int gy = flr_i(__fmul_rn(cy - a.glo[1], a.ginv));
         const int gz = flr_i(__fmul_rn(cz - a.glo[2], a.ginv));
-        const float *yx = a.pts, *yy = a.pts + a.m, *yz = a.pts + 2 * a.m;
+        const float4 *pt = reinterpret_cast<const float4 *>(a.pts);
         float best = a.r2;
         const int zlo = max(gz - 1, 0), zhi = min(gz + 1, a.gdim[2] - 1);
         if (zlo <= zhi)
@@ -56,7 +55,8 @@ __global__ void __launch_bounds__(256) k_df_build(DfArgs a)
                     const int row = (x * a.gdim[1] + y) * a.gdim[2];
                     const int b = a.start[row + zlo], e = a.start[row + zhi + 1];
                     for (int j = b; j < e; ++j) {
-                        const float dx = cx - yx[j], dy = cy - yy[j], dz = cz - yz[j];
+                        const float4 y = pt[j];
+                        const float dx = cx - y.x, dy = cy - y.y, dz = cz - y.z;
                         best = fminf(best, fmaf(dz, dz, fmaf(dy, dy, __fmul_rn(dx, dx))));
                     }
                 }
@@ -78,7 +78,6 @@ hipError_t launch_df_build(const float *pts_soa, const int32_t *start, const Hos
         a.h[q] = h[q];
     }
     a.ginv = grid.inv;
-    a.m = grid.start.empty() ? 0 : grid.start.back();
     a.res = res;
     a.r = r;
     a.r2 = r * r;

@@ -98,7 +98,7 @@ void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, floa
 
 // Exact cell grid for the GRID scorer, built on the host from reference points.
 struct HostGrid {
-    std::vector<float> pts;      // SoA, cell order
+    std::vector<float> pts;      // x y z and a pad per point (16 B), cell order
     std::vector<int32_t> start;  // ncell + 1
     float lo[3];
     float inv;

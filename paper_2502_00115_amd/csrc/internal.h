@@ -34,7 +34,7 @@ struct Geom {
 
 // Uniform cell grid over the reference for the exact GRID scorer.
 struct CellGrid {
-    const float *pts;      // reference points in cell order, SoA (3 * m floats)
+    const float *pts;      // reference points in cell order, x y z and a pad per point (4 * m floats)
     const int32_t *start;  // cell start offsets, ncell + 1 entries
     float lo[3];           // grid origin
     float inv;             // 1 / cell pitch

@@ -746,8 +746,7 @@ __device__ __forceinline__ void nn_grid(const CellGrid &cg, float qx, float qy, 
     const int cy = cvt_flr(__fmul_rn(qy - cg.lo[1], cg.inv));
     const int cz = cvt_flr(__fmul_rn(qz - cg.lo[2], cg.inv));
     float best = INFINITY, bl1 = INFINITY;
-    const int m = cg.start[cg.dim[0] * cg.dim[1] * cg.dim[2]];
-    const float *yx = cg.pts, *yy = cg.pts + m, *yz = cg.pts + 2 * m;
+    const float4 *pt = reinterpret_cast<const float4 *>(cg.pts);
     const int zlo = max(cz - 1, 0), zhi = min(cz + 1, cg.dim[2] - 1);
     if (zlo <= zhi) {
         for (int ix = max(cx - 1, 0); ix <= min(cx + 1, cg.dim[0] - 1); ++ix)
@@ -755,7 +754,8 @@ __device__ __forceinline__ void nn_grid(const CellGrid &cg, float qx, float qy, 
                 const int row = (ix * cg.dim[1] + iy) * cg.dim[2];
                 const int b = cg.start[row + zlo], e = cg.start[row + zhi + 1];
                 for (int j = b; j < e; ++j) {
-                    const float dx = qx - yx[j], dy = qy - yy[j], dz = qz - yz[j];
+                    const float4 y = pt[j];
+                    const float dx = qx - y.x, dy = qy - y.y, dz = qz - y.z;
                     best = fminf(best, fmaf(dz, dz, fmaf(dy, dy, __fmul_rn(dx, dx))));
                     if (want_l1) bl1 = fminf(bl1, fabsf(dx) + fabsf(dy) + fabsf(dz));
                 }

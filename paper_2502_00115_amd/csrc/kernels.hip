@@ -748,11 +748,19 @@ __device__ __forceinline__ void nn_grid(const CellGrid &cg, float qx, float qy, 
     float best = INFINITY, bl1 = INFINITY;
     const float4 *pt = reinterpret_cast<const float4 *>(cg.pts);
     const int zlo = max(cz - 1, 0), zhi = min(cz + 1, cg.dim[2] - 1);
+    const int ncell = cg.dim[0] * cg.dim[1] * cg.dim[2];
+    const __amdgpu_buffer_rsrc_t st = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int32_t *>(cg.start), 0, 4 * (ncell + 1), 0x00020000);
+    // a row's start and end offsets are at most 3 entries apart: one 16-byte load
+    // (bounds-checked by the descriptor) brings both; ez (1..3) indexes the end
+    const int ez = zhi - zlo + 1;
     if (zlo <= zhi) {
         for (int ix = max(cx - 1, 0); ix <= min(cx + 1, cg.dim[0] - 1); ++ix)
             for (int iy = max(cy - 1, 0); iy <= min(cy + 1, cg.dim[1] - 1); ++iy) {
                 const int row = (ix * cg.dim[1] + iy) * cg.dim[2];
-                const int b = cg.start[row + zlo], e = cg.start[row + zhi + 1];
+                const f4u s4 = __builtin_amdgcn_raw_buffer_load_b128(st, 4 * (row + zlo), 0, 0);
+                const int b = (int)s4.x;
+                const int e = (int)(ez == 1 ? s4.y : (ez == 2 ? s4.z : s4.w));
                 for (int j = b; j < e; ++j) {
                     const float4 y = pt[j];
                     const float dx = qx - y.x, dy = qy - y.y, dz = qz - y.z;

@@ -42,6 +42,29 @@ void DevBuf::release()
     bytes = 0;
 }
 
+dses_status PinnedBuf::ensure(size_t want)
+{
+    if (want <= bytes && ptr) return DSES_OK;
+    release();
+    const size_t b = (std::max<size_t>(want, 4096) + 4095) & ~size_t(4095);
+    if (hipHostMalloc(&ptr, b, hipHostMallocDefault) != hipSuccess) {
+        ptr = nullptr;
+        bytes = 0;
+        (void)hipGetLastError();
+        set_error("pinned host allocation of " + std::to_string(b) + " bytes failed");
+        return DSES_E_NOMEM;
+    }
+    bytes = b;
+    return DSES_OK;
+}
+
+void PinnedBuf::release()
+{
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
 static std::mutex g_init_mu;
 static Context *g_ctx = nullptr;
 
@@ -194,14 +217,54 @@ int64_t ref_block_population(const float *tgt, int32_t m, const Params &p)
     auto key = [](int64_t x, int64_t y, int64_t z) {
         return ((x + (1 << 20)) << 42) | ((y + (1 << 20)) << 21) | (z + (1 << 20));
     };
-    // points per cell of pitch h, then each cell's count added to the 8 blocks of
-    // 2 x 2 x 2 cells that contain it; the bound is the largest block total
+    // points per cell of pitch h; the bound is the largest total of a block of
+    // 2 x 2 x 2 cells.  When the cells span a modest box, counts go to a dense
+    // array with a one-cell margin and each point's 8 blocks are summed there;
+    // otherwise a hash map of cells and blocks gives the same number.
+    std::vector<int64_t> ci(3 * (size_t)m);
+    int64_t lo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, hi[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
+    for (int32_t j = 0; j < m; ++j)
+        for (int a = 0; a < 3; ++a) {
+            const int64_t c = (int64_t)std::floor((double)tgt[3 * j + a] / h);
+            ci[3 * (size_t)j + a] = c;
+            lo[a] = std::min(lo[a], c);
+            hi[a] = std::max(hi[a], c);
+        }
+    if (m > 0 && hi[0] - lo[0] < (1 << 12) && hi[1] - lo[1] < (1 << 12) &&
+        hi[2] - lo[2] < (1 << 12)) {
+        const int64_t D1 = hi[1] - lo[1] + 3, D2 = hi[2] - lo[2] + 3;
+        const int64_t cells = (hi[0] - lo[0] + 3) * D1 * D2;
+        if (cells <= ((int64_t)1 << 21)) {
+            thread_local std::vector<int32_t> cnt;       // all zero between calls
+            if ((int64_t)cnt.size() < cells) cnt.assign((size_t)cells, 0);
+            auto at = [&](int32_t j) {
+                return ((ci[3 * (size_t)j] - lo[0] + 1) * D1 + (ci[3 * (size_t)j + 1] - lo[1] + 1)) * D2 +
+                       (ci[3 * (size_t)j + 2] - lo[2] + 1);
+            };
+            for (int32_t j = 0; j < m; ++j) cnt[(size_t)at(j)] += 1;
+            int64_t best = 0;
+            for (int32_t j = 0; j < m; ++j) {
+                const int64_t c = at(j);
+                for (int ox = -1; ox <= 0; ++ox)
+                    for (int oy = -1; oy <= 0; ++oy)
+                        for (int oz = -1; oz <= 0; ++oz) {
+                            const int64_t o = c + (ox * D1 + oy) * D2 + oz;    // block origin
+                            int64_t sum = 0;
+                            for (int dx = 0; dx <= 1; ++dx)
+                                for (int dy = 0; dy <= 1; ++dy)
+                                    for (int dz = 0; dz <= 1; ++dz)
+                                        sum += cnt[(size_t)(o + (dx * D1 + dy) * D2 + dz)];
+                            best = std::max(best, sum);
+                        }
+            }
+            for (int32_t j = 0; j < m; ++j) cnt[(size_t)at(j)] = 0;
+            return best;
+        }
+    }
     std::unordered_map<int64_t, int32_t> cell;
     cell.reserve((size_t)m * 2);
     for (int32_t j = 0; j < m; ++j)
-        cell[key((int64_t)std::floor((double)tgt[3 * j] / h),
-                 (int64_t)std::floor((double)tgt[3 * j + 1] / h),
-                 (int64_t)std::floor((double)tgt[3 * j + 2] / h))] += 1;
+        cell[key(ci[3 * (size_t)j], ci[3 * (size_t)j + 1], ci[3 * (size_t)j + 2])] += 1;
     std::unordered_map<int64_t, int64_t> block;
     block.reserve(cell.size() * 16);
     for (const auto &kv : cell) {
@@ -329,10 +392,12 @@ void add_stats(Context *c, double vote_ms, double score_ms, double select_ms, do
 
 void sort_by_x(const float *tgt, int32_t m, std::vector<int32_t> *perm)
 {
+    // (x, index) pairs: ascending x, equal x in index order (a stable sort by x)
+    std::vector<std::pair<float, int32_t>> kv((size_t)m);
+    for (int32_t j = 0; j < m; ++j) kv[j] = {tgt[3 * (size_t)j], j};
+    std::sort(kv.begin(), kv.end());
     perm->resize(m);
-    for (int32_t j = 0; j < m; ++j) (*perm)[j] = j;
-    std::stable_sort(perm->begin(), perm->end(),
-                     [tgt](int32_t a, int32_t b) { return tgt[3 * a] < tgt[3 * b]; });
+    for (int32_t j = 0; j < m; ++j) (*perm)[j] = kv[j].second;
 }
 
 bool ref_x_range(const float *tgt, const std::vector<int32_t> &perm, float s, int32_t klo_x,
@@ -495,15 +560,17 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
         } else {
             HostGrid hg;
             if ((st = build_grid(ht, job.m, p.r, &hg)) != DSES_OK) return st;
-            if ((st = c->grid_pts.ensure(hg.pts.size() * sizeof(float))) != DSES_OK) return st;
-            if ((st = c->grid_start.ensure(hg.start.size() * sizeof(int32_t))) != DSES_OK)
-                return st;
-            DSES_HIP(hipMemcpyAsync(c->grid_pts.ptr, hg.pts.data(), hg.pts.size() * sizeof(float),
-                                    hipMemcpyHostToDevice, stream));
-            DSES_HIP(hipMemcpyAsync(c->grid_start.ptr, hg.start.data(),
-                                    hg.start.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                    stream));
-            DSES_HIP(hipStreamSynchronize(stream));     // host vectors go out of scope
+            const size_t pb = hg.pts.size() * sizeof(float), sb = hg.start.size() * sizeof(int32_t);
+            if ((st = c->grid_pts.ensure(pb)) != DSES_OK) return st;
+            if ((st = c->grid_start.ensure(sb)) != DSES_OK) return st;
+            // through pinned staging: the copies stay asynchronous (the buffer is
+            // reused by the next call only after this call's final synchronisation)
+            if ((st = c->host_stage.ensure(pb + sb)) != DSES_OK) return st;
+            char *hs = static_cast<char *>(c->host_stage.ptr);
+            std::memcpy(hs, hg.pts.data(), pb);
+            std::memcpy(hs + pb, hg.start.data(), sb);
+            DSES_HIP(hipMemcpyAsync(c->grid_pts.ptr, hs, pb, hipMemcpyHostToDevice, stream));
+            DSES_HIP(hipMemcpyAsync(c->grid_start.ptr, hs + pb, sb, hipMemcpyHostToDevice, stream));
             a.grid.pts = static_cast<float *>(c->grid_pts.ptr);
             a.grid.start = static_cast<int32_t *>(c->grid_start.ptr);
             for (int q = 0; q < 3; ++q) { a.grid.lo[q] = hg.lo[q]; a.grid.dim[q] = hg.dim[q]; }

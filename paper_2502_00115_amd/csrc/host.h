@@ -38,6 +38,15 @@ struct DevBuf {
     ~DevBuf() { release(); }
 };
 
+// Pinned host buffer (hipHostMalloc), grown on demand.
+struct PinnedBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    dses_status ensure(size_t want);
+    void release();
+    ~PinnedBuf() { release(); }
+};
+
 struct Context {
     int device = -1;
     int n_cu = 0;
@@ -50,6 +59,7 @@ struct Context {
     DevBuf topk_a, topk_b, topk_out;     // top-k passes and output staging
     DevBuf prune;                        // q-pruning: M* and the work cursor
     DevResult *host_res = nullptr;       // pinned
+    PinnedBuf host_stage;                // staging of host-built uploads (cell grid)
     // timing
     bool timing_enabled = false;
     std::mutex stats_mu;

@@ -355,8 +355,9 @@ def main():
                                           for pat in ("conflict_free", "random")}}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the sweep shards by rotation, see DESIGN.md.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the sweep "
+              "would shard by rotation, one slice of the rotation list per GPU, which is "
+              "not built.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "c3":
         print(json.dumps(bench_batch(args)), flush=True)

@@ -209,7 +209,7 @@ __device__ __forceinline__ ChunkLayout chunk_layout(int c0, int n, int wave, int
 // against the current slab [x0, x0 + np).  LDS byte address (16-bit counters):
 //   ((cx - x0) * Sy + cy) * row_words * 4 + (cz >> 1) * 4, half = cz & 1
 // (32-bit: ((cx - x0) * Sy + cy) * Sz * 4 + cz * 4).
-// The 16-bit path is one asm block: three v_cmpx narrow EXEC to the in-box lanes,
+// Each width is one asm block: three v_cmpx narrow EXEC to the in-box lanes,
 // the address arithmetic and the ds_add_u32 run on those lanes only, and EXEC is
 // restored.  Compared with a compiler-generated branch this removes the per-pair
 // VALU -> SALU -> branch round trip (v_cmp, s_and, s_and_saveexec, s_cbranch,
@@ -244,11 +244,26 @@ __device__ __forceinline__ void vote_pair(uint32_t *hist, int cx, int cy, int cz
             : "vcc", "memory");
         return;
     }
-    if ((uint32_t)(cx - x0) < np && (uint32_t)cy < Sy && (uint32_t)cz < Sz) {
-        const uint32_t zb = lshl2_add((uint32_t)cz, negc);
-        const uint32_t addr = mad24((uint32_t)cx, sx4, mad24((uint32_t)cy, sy4, zb));
-        atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(hist) + addr), 1u);
-    }
+    // 32-bit counters: the same single block, address cz * 4 and increment 1
+    const uint32_t base =
+        negc + (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t *)hist;
+    uint64_t save;
+    uint32_t t0, t1;
+    asm volatile(
+        "s_mov_b64 %[save], exec\n\t"
+        "v_subrev_u32 %[t0], %[x0], %[cx]\n\t"
+        "v_cmpx_gt_u32 vcc, %[np], %[t0]\n\t"
+        "v_cmpx_gt_u32 vcc, %[sy], %[cy]\n\t"
+        "v_cmpx_gt_u32 vcc, %[sz], %[cz]\n\t"
+        "v_lshl_add_u32 %[t1], %[cz], 2, %[base]\n\t"
+        "v_mad_u32_u24 %[t1], %[cy], %[sy4], %[t1]\n\t"
+        "v_mad_u32_u24 %[t1], %[cx], %[sx4], %[t1]\n\t"
+        "ds_add_u32 %[t1], %[one]\n\t"
+        "s_mov_b64 exec, %[save]"
+        : [save] "=&s"(save), [t0] "=&v"(t0), [t1] "=&v"(t1)
+        : [cx] "v"(cx), [cy] "v"(cy), [cz] "v"(cz), [x0] "s"(x0), [np] "s"(np), [sy] "s"(Sy),
+          [sz] "s"(Sz), [sx4] "s"(sx4), [sy4] "s"(sy4), [base] "s"(base), [one] "v"(1u)
+        : "vcc", "memory");
 }
 
 typedef uint32_t f4u __attribute__((ext_vector_type(4)));

@@ -459,6 +459,9 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
         const int ngr = (m + 63) >> 6;
         const int G = a.vote_parts > 0 ? a.vote_parts : vote_parts_auto(ngr);
         const int total = ngr * G;
+        // part boundaries lo + span * p * gmul / 8192: spans are at most kSortMax
+        // sources here and G at most 8, so the product stays below 2^32
+        const uint32_t gmul = 8192u / (uint32_t)G;
         const int64_t ns = src_stride(a.scratch_stride);
         const float *sp = a.scratch + (size_t)slot * slot_floats(a.scratch_stride);
         const f4u sdesc = soa_desc(sp, ns);
@@ -489,8 +492,11 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             src_window(a, trs, bmin, bmax, ymin, ymax, x0, x0 + np, lo, hi);
             lo = uni(lo);
             hi = uni(max(hi, lo));
-            const int j0 = uni(lo + (int)((int64_t)(hi - lo) * part / G));
-            const int j1 = uni(lo + (int)((int64_t)(hi - lo) * (part + 1) / G));
+            const uint32_t span = (uint32_t)(hi - lo);
+            const int j0 = uni(lo + (int)((span * (uint32_t)part * gmul) >> 13));
+            const int j1 = part + 1 == G
+                               ? hi
+                               : uni(lo + (int)((span * (uint32_t)(part + 1) * gmul) >> 13));
             vote_span<CW, true>(hist, sdesc, srs, (int)ns, j0, j1, Yx, Yy, Yz, x0, (uint32_t)np,
                                 Sy, Sz, sx4, sy4, negc);
         }

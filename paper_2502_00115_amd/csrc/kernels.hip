@@ -352,18 +352,6 @@ __device__ __forceinline__ void vote4(uint32_t *hist, f4u x, f4u y, f4u z, float
         vote_pair<CW>(hist, cx[q], cy[q], cz[q], x0, np, Sy, Sz, sx4, sy4, negc);
 }
 
-__device__ __forceinline__ float wave_min(float v)
-{
-    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-__device__ __forceinline__ float wave_max(float v)
-{
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
 // Votes of the lane point L against the streamed points [j0, j1) of a three-array
 // point set: groups of 4 points with two groups in flight, then single points.
 // The streamed coordinates come through the vector memory path (buffer loads):

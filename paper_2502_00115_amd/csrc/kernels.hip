@@ -756,28 +756,37 @@ __device__ __forceinline__ void nn_grid(const CellGrid &cg, float qx, float qy, 
     const int cz = cvt_flr(__fmul_rn(qz - cg.lo[2], cg.inv));
     float best = INFINITY, bl1 = INFINITY;
     const float4 *pt = reinterpret_cast<const float4 *>(cg.pts);
-    const int zlo = max(cz - 1, 0), zhi = min(cz + 1, cg.dim[2] - 1);
+    // (written without cz - 1 / cz + 1 overflowing when the conversion saturates)
+    const int zlo = cz > 0 ? cz - 1 : 0, zhi = cz < cg.dim[2] - 1 ? cz + 1 : cg.dim[2] - 1;
     const int ncell = cg.dim[0] * cg.dim[1] * cg.dim[2];
     const __amdgpu_buffer_rsrc_t st = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<int32_t *>(cg.start), 0, 4 * (ncell + 1), 0x00020000);
     // a row's start and end offsets are at most 3 entries apart: one 16-byte load
     // (bounds-checked by the descriptor) brings both; ez (1..3) indexes the end
     const int ez = zhi - zlo + 1;
-    if (zlo <= zhi) {
-        for (int ix = max(cx - 1, 0); ix <= min(cx + 1, cg.dim[0] - 1); ++ix)
-            for (int iy = max(cy - 1, 0); iy <= min(cy + 1, cg.dim[1] - 1); ++iy) {
-                const int row = (ix * cg.dim[1] + iy) * cg.dim[2];
-                const f4u s4 = __builtin_amdgcn_raw_buffer_load_b128(st, 4 * (row + zlo), 0, 0);
-                const int b = (int)s4.x;
-                const int e = (int)(ez == 1 ? s4.y : (ez == 2 ? s4.z : s4.w));
-                for (int j = b; j < e; ++j) {
-                    const float4 y = pt[j];
-                    const float dx = qx - y.x, dy = qy - y.y, dz = qz - y.z;
-                    best = fminf(best, fmaf(dz, dz, fmaf(dy, dy, __fmul_rn(dx, dx))));
-                    if (want_l1) bl1 = fminf(bl1, fabsf(dx) + fabsf(dy) + fabsf(dz));
-                }
-            }
+    // the bounds of all nine rows first, so their loads are in flight together; a
+    // row outside the grid reads at an offset past the table, which the descriptor
+    // turns into zeros (an empty row)
+    int rb[9], re[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        const uint32_t ix = (uint32_t)cx + (uint32_t)(r / 3) - 1u;
+        const uint32_t iy = (uint32_t)cy + (uint32_t)(r % 3) - 1u;
+        const bool ok = zlo <= zhi && ix < (uint32_t)cg.dim[0] && iy < (uint32_t)cg.dim[1];
+        const int off =
+            ok ? 4 * (((int)ix * cg.dim[1] + (int)iy) * cg.dim[2] + zlo) : 0x7FFFFFF0;
+        const f4u s4 = __builtin_amdgcn_raw_buffer_load_b128(st, off, 0, 0);
+        rb[r] = (int)s4.x;
+        re[r] = (int)(ez == 1 ? s4.y : (ez == 2 ? s4.z : s4.w));
     }
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+        for (int j = rb[r]; j < re[r]; ++j) {
+            const float4 y = pt[j];
+            const float dx = qx - y.x, dy = qy - y.y, dz = qz - y.z;
+            best = fminf(best, fmaf(dz, dz, fmaf(dy, dy, __fmul_rn(dx, dx))));
+            if (want_l1) bl1 = fminf(bl1, fabsf(dx) + fabsf(dy) + fabsf(dz));
+        }
     nn.d2 = best;
     nn.l1 = bl1;
 }

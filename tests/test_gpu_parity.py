@@ -67,6 +67,32 @@ def test_brute_and_grid_scorers_are_bitwise_equal():
     assert a.records.tobytes() == b.records.tobytes()
 
 
+@pytest.mark.parametrize("case", ["far_outliers", "saturating_cell_index"])
+def test_grid_scorer_queries_far_outside_the_grid(case):
+    """Queries whose cell index lies far outside the cell grid (or saturates the
+    float-to-int conversion) find no neighbours there, exactly as brute force."""
+    rng = np.random.default_rng(77)
+    if case == "far_outliers":
+        p = synth.make_c1(5)
+        src = p.src.copy()
+        src[::7] = rng.uniform(-300.0, 300.0, size=src[::7].shape).astype(np.float32)
+        eps, kw = p.eps, {}
+        tgt, rots = p.tgt, p.rotations[:64]
+    else:
+        # a 1e-4-wide reference cluster, cell pitch ~1e-6: sources a few thousand
+        # units away put (q - lo) / pitch near 1e10, beyond the int32 range
+        tgt = (rng.uniform(0.0, 1.0e-4, size=(64, 3)) + 0.1).astype(np.float32)
+        src = np.concatenate([tgt[:24] - 0.1, rng.uniform(-5.0e3, 5.0e3, size=(24, 3))])
+        src = src.astype(np.float32)
+        eps, kw = 1.0e-6, {"delta_t": 0.25}
+        rots = synth.hopf_grid(0)[:24].reshape(-1, 9).astype(np.float32)
+    pb = synth.Problem(src, tgt, rots, eps, np.eye(3), np.zeros(3))
+    g, ref = run_both(pb, scorer="grid", **kw)
+    b = dses.register(src, tgt, rots, eps, scorer="brute", records=True, **kw)
+    assert g.records.tobytes() == b.records.tobytes()
+    compare_records(g.records, ref, len(src), label=case)
+
+
 def test_host_and_device_pointers_agree():
     p = synth.make_c1(4)
     a = dses.register(p.src, p.tgt, p.rotations, p.eps, records=True)

@@ -652,7 +652,8 @@ __device__ uint32_t slab_max(const uint32_t *hist, int words4, uint32_t *scr, ui
     uint32_t r = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) r = max(r, scr[8 + w]);
-    __syncthreads();
+    // no closing barrier: every hist read came before the barrier above, and
+    // scr[8..23] is written next by the next slab's scan, two barriers later
     return r;
 }
 
@@ -681,12 +682,12 @@ __device__ uint32_t slab_first(const uint32_t *hist, int words4, uint32_t c, uin
         }
     }
     for (int off = 32; off > 0; off >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, off, 64));
-    if (lane == 0) scr[8 + wave] = best;
+    if (lane == 0) scr[24 + wave] = best;
     __syncthreads();
     uint32_t r = 0xFFFFFFFFu;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) r = min(r, scr[8 + w]);
-    __syncthreads();
+    for (int w = 0; w < kWaves; ++w) r = min(r, scr[24 + w]);
+    // no closing barrier (its own scratch words, hist reads before the barrier)
     return pos0 + r;
 }
 
@@ -937,6 +938,9 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
     if (sorted) sort_sources(a, R, lds, scr, slot);
 
     // ---------------- vote + mode over the slabs ----------------
+    // Barriers per slab: after the clear, after the vote, and one inside each
+    // scan (after its per-wave partials); the scans read hist only before theirs,
+    // so the next slab's clear (or the scoring) needs no further barrier.
     uint32_t best_c = 0, best_p = 0xFFFFFFFFu;
     for (int slab = 0; slab < g.nslabs; ++slab) {
         const int x0 = slab * g.pps;
@@ -959,7 +963,6 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
             best_p = slab_first<CW>(hist, words4, smax, pos0, scr, mine);
             best_c = smax;
         }
-        __syncthreads();                      // scr / hist reused by the next slab
     }
 
     dses_record rec;

@@ -136,6 +136,13 @@ typedef struct {
                                  0 inliers and are never selected (not with
                                  DSES_VOTES)                                          */
     float p;                  /* exponent of DSES_TRUNC_LP, in (0, 1]; 0 -> 0.5        */
+    int32_t lane_group;       /* vote layout (sources up to 16,384 points): reference
+                                 points per lane group, 16, 32 or 64 (a wave holds
+                                 64 / lane_group copies of the group, each streaming
+                                 alternate 4-source pieces of its window); 0 ->
+                                 chosen per call from the sizes and the reference's
+                                 extent.  Results do not depend on it; other values
+                                 are DSES_E_INVAL                                     */
 } dses_options;
 
 #define DSES_TOPK_MAX 64
@@ -293,7 +300,7 @@ typedef struct {
     int32_t scorer;           /* dses_scorer for every problem */
     int32_t use_graph;        /* 1: capture the launch in a HIP graph and replay it */
     int32_t tile_rot;         /* rotations per work item; 0 -> tuned or default layout */
-    int32_t vote_parts;       /* vote work units per 64-point lane group (parts of its
+    int32_t vote_parts;       /* vote work units per lane group (parts of its
                                  stream window, 1..16); 0 -> tuned or automatic
                                  (64 / groups, 1..8, per problem)                   */
     void *stream;
@@ -306,9 +313,9 @@ typedef struct {
  * one work list, most expensive first.  Two knobs shape it: the work-list
  * granularity (tiles sized so that the list holds about `items_per_cu` items per
  * compute unit, unless tile_rot fixes the tile) and vote_parts (into how many work
- * units the vote splits each 64-point lane group's stream window: 64 reference
- * points on the lanes against the window of x-sorted sources; the waves of a
- * workgroup take units dynamically).
+ * units the vote splits each lane group's stream window: 16, 32 or 64 reference
+ * points, chosen per problem as with dses_options.lane_group = 0, against the
+ * window of x-sorted sources; the waves of a workgroup take units dynamically).
  * With DSES_BATCH_TUNE the call first times the sweep kernel alone on this batch
  * for candidate layouts (items_per_cu in {6, 12, 24, 48, 96}, then vote_parts in
  * {1, 2, 4, 8}, one coordinate at a time), keeps the fastest for every later batch

@@ -441,6 +441,10 @@ dses_status apply_metric_options(const dses_options &o, Params *p)
         set_error("q-pruning has no effect with DSES_VOTES");
         return DSES_E_INVAL;
     }
+    if (o.lane_group != 0 && o.lane_group != 16 && o.lane_group != 32 && o.lane_group != 64) {
+        set_error("lane_group must be 0 (automatic), 16, 32 or 64");
+        return DSES_E_INVAL;
+    }
     return DSES_OK;
 }
 
@@ -551,6 +555,8 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     a.scratch = sorted ? static_cast<float *>(c->scratch.ptr) : nullptr;
     a.scratch_stride = job.n;
     source_buckets(ylo, yhi, g.size[0], &a.sb_lo, &a.sb_scale, &a.sb_n);
+    a.lane_group = o.lane_group;
+    a.ref_x_extent = (float)(yhi - ylo) + 1.0f;
 
     if (scorer == DSES_SCORER_GRID) {
         const TargetRes *t = job.target;

@@ -487,6 +487,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         a.scratch = x.sorted ? static_cast<float *>(b->scratch.ptr) : nullptr;
         a.scratch_stride = max_n;
         source_buckets(x.ylo, x.yhi, x.g.size[0], &a.sb_lo, &a.sb_scale, &a.sb_n);
+        a.ref_x_extent = (float)(x.yhi - x.ylo) + 1.0f;
         a.g = x.g;
         a.rec = reinterpret_cast<dses_record *>(arena + x.off_rec);
         a.k = x.k;

@@ -79,7 +79,8 @@ struct Params {
 };
 
 // Applies the plain-path options that resolve_params does not see (the Lp
-// exponent; q has no meaning with DSES_VOTES).  Host-side check, no device use.
+// exponent; q has no meaning with DSES_VOTES; lane_group is 0, 16, 32 or 64).
+// Host-side check, no device use.
 dses_status apply_metric_options(const dses_options &o, Params *p);
 
 dses_status resolve_params(float eps, int metric, float delta_t, float tau, const float *t_min,
@@ -137,7 +138,7 @@ struct TargetRes {
         int32_t klo[3];
         float *ys, *yt;
         bool sorted;                         // ref_x_range succeeded
-        int32_t ylo, yhi;                    // its result
+        int32_t ylo = 0, yhi = 0;            // its result
     };
     std::deque<Stage> stages;                // deque: references survive push_back
     struct Population {                      // ref_block_population for (delta, box)

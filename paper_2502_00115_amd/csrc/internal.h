@@ -62,6 +62,36 @@ __host__ __device__ inline int vote_parts_auto(int groups)
     const int g = 64 / (groups > 0 ? groups : 1);
     return g < 1 ? 1 : (g > 8 ? 8 : g);
 }
+// Lane groups of the sorted-source vote: 2^lg reference points (64, 32 or 16),
+// each held by 64 >> lg sub-groups of lanes that take alternate 4-source pieces of
+// the same stream window, so a wave step covers 2^lg points x (64 >> lg) sources.
+// Smaller groups span less x, so their windows carry less slack (about
+// 2^lg * X source-bins per slab over all groups, X the reference's x extent in
+// bins), but there are more work units, each costing about kUnitSteps wave steps
+// of set-up and block padding; rho = n / (X + size_x) sources per bin turns a
+// step into 64 / rho source-bins.  The size with the least modelled cost wins
+// (ties: the larger group).  It picks 16 for a 717-point source against a
+// 1,024-point reference with eps 0.03 (measured fastest, 10% below 64) and 64 for
+// 64 / 256 points and for 4,096 / 16,384 points (both measured fastest).
+constexpr float kUnitSteps = 4.9f;
+__host__ __device__ inline int lane_group_log2(int m, int n, int size_x, float x_extent,
+                                               int vote_parts)
+{
+    const float per_unit = kUnitSteps * 64.0f * (x_extent + (float)size_x) /
+                           (float)(n > 0 ? n : 1);
+    int best = 6;
+    float best_cost = 0.0f;
+    for (int lg = 6; lg >= 4; --lg) {
+        const int groups = (m + (1 << lg) - 1) >> lg;
+        const int parts = vote_parts > 0 ? vote_parts : vote_parts_auto(groups);
+        const float cost = (float)(1 << lg) * x_extent + per_unit * (float)(groups * parts);
+        if (lg == 6 || cost < best_cost) {
+            best_cost = cost;
+            best = lg;
+        }
+    }
+    return best;
+}
 constexpr int kUnitCounter = 200;       // LDS scratch word: next vote work unit
 constexpr int kSrcBmin = 210;           // LDS scratch words: lowest and highest occupied
 constexpr int kSrcBmax = 211;           // source bucket of the current rotation
@@ -88,13 +118,16 @@ struct SweepArgs {
     Field field;
     dses_record *rec;      // one record per rotation index
     int32_t k;             // rotations
-    int32_t vote_parts;    // stream-window parts per 64-point lane group (0: vote_parts_auto)
+    int32_t vote_parts;    // stream-window parts per lane group (0: vote_parts_auto)
+    int32_t lane_group;    // reference points per lane group: 16, 32, 64 (0: lane_group_log2)
+    float ref_x_extent;    // x extent of the scaled reference in bins (lane-group choice)
 };
 
 // Scratch slot of one workgroup (floats): rotated scaled sources sorted by x as
-// three arrays x, y, z of src_stride(cap) floats each, then the bucket table
-// T[0 .. kSrcBuckets] (int32: T[b] = sources in buckets below b; T[kSrcBuckets] = n).
-__host__ __device__ inline int64_t src_stride(int64_t cap) { return (cap + 3) & ~int64_t(3); }
+// three arrays x, y, z of src_stride(cap) floats each (entries n .. stride-1 hold
+// sentinels that never vote, so windows can be padded to blocks of 16), then the
+// bucket table T[0 .. kSrcBuckets] (int32: T[b] = sources in buckets below b).
+__host__ __device__ inline int64_t src_stride(int64_t cap) { return (cap + 15) & ~int64_t(15); }
 __host__ __device__ inline int64_t slot_floats(int64_t cap)
 {
     return (3 * src_stride(cap) + kSrcBuckets + 1 + 3) & ~int64_t(3);

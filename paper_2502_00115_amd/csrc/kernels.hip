@@ -4,11 +4,12 @@
 // Sweep design (one workgroup of 16 wave64s per rotation, one workgroup per CU):
 //  * Source points are rotated and scaled once per rotation and bucket-sorted by
 //    x into a per-workgroup scratch slot (x, y, z arrays and a bucket table).
-//  * In the vote each lane holds one point of the x-sorted reference (64
-//    consecutive points per work unit) and the sources are wave-uniform: every
-//    lane walks the same source index, restricted to the window whose pairs can
-//    land in the current slab.  They arrive through 16-byte buffer loads (same
-//    address on every lane), two groups of 4 in flight.
+//  * In the vote each lane holds one point of the x-sorted reference (a work
+//    unit's lane group: 64, 32 or 16 consecutive points, the smaller groups
+//    repeated on the wave's lane sub-groups) and streams the sources of the
+//    window whose pairs can land in the current slab; the sub-groups take
+//    alternate 4-source pieces of it.  Sources arrive through 16-byte buffer
+//    loads (one address per sub-group), two blocks in flight.
 //  * The vote array of Alg. 2 lives in LDS as 16-bit counters packed two per
 //    32-bit word (incremented with ds_add_u32 of 1 or 1<<16), so the 41^3 box of
 //    delta = 0.05 fits one allocation.  Larger boxes are swept in x-slabs that
@@ -269,8 +270,9 @@ __device__ __forceinline__ void vote_pair(uint32_t *hist, int cx, int cy, int cz
 typedef uint32_t f4u __attribute__((ext_vector_type(4)));
 
 // Buffer resource over a point set stored as three arrays (x, y, z) of `stride`
-// floats each (the staged reference, or a slot's sorted sources); loads past its
-// end return zero instead of faulting.
+// floats each (the staged reference, or a slot's sorted sources).  The hardware
+// range check covers the per-lane (VGPR) offset only; the stream loads below
+// address by scalar offset and stay inside the arrays by construction.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t soa_rsrc(const float *base, int64_t stride)
 {
     // word 3: 32-bit data format, no swizzle (raw buffer)
@@ -306,6 +308,18 @@ __device__ __forceinline__ void soa_issue4(const f4u &desc, int stride, int j, f
                  "buffer_load_dwordx4 %2, off, %3, %6"
                  : "=&v"(x), "=&v"(y), "=&v"(z)
                  : "s"(desc), "s"(o0), "s"(o1), "s"(o2));
+}
+
+// Points j + 4h .. j + 4h + 3 of such a set, h = hoff / 16 per lane.
+__device__ __forceinline__ void soa_issue_lanes(const f4u &desc, int stride, int j,
+                                                uint32_t hoff, f4u &x, f4u &y, f4u &z)
+{
+    const int o0 = 4 * j, o1 = 4 * (stride + j), o2 = 4 * (2 * stride + j);
+    asm volatile("buffer_load_dwordx4 %0, %3, %4, %5 offen\n\t"
+                 "buffer_load_dwordx4 %1, %3, %4, %6 offen\n\t"
+                 "buffer_load_dwordx4 %2, %3, %4, %7 offen"
+                 : "=&v"(x), "=&v"(y), "=&v"(z)
+                 : "v"(hoff), "s"(desc), "s"(o0), "s"(o1), "s"(o2));
 }
 
 // Wait until all but the newest N vector-memory operations are complete; the
@@ -394,6 +408,33 @@ __device__ __forceinline__ void vote_span(uint32_t *hist, const f4u &desc,
     }
 }
 
+// Votes of the lane point L against the streamed points [j0, j1), j1 - j0 a
+// multiple of the block B = 4 * 64 / (lane-group size): within each block, lane
+// sub-group h (its hoff = 16 h bytes) takes points 4h .. 4h + 3.
+template <int CW>
+__device__ __forceinline__ void vote_span_lanes(uint32_t *hist, const f4u &desc, int stride,
+                                                int j0, int j1, int B, uint32_t hoff, float Lx,
+                                                float Ly, float Lz, int x0, uint32_t np,
+                                                uint32_t Sy, uint32_t Sz, uint32_t sx4,
+                                                uint32_t sy4, uint32_t negc)
+{
+    if (j0 >= j1) return;
+    f4u ax, ay, az, bx, by, bz;
+    int j = j0;
+    soa_issue_lanes(desc, stride, j, hoff, ax, ay, az);
+    for (; j + 2 * B <= j1; j += 2 * B) {
+        soa_issue_lanes(desc, stride, j + B, hoff, bx, by, bz);
+        soa_wait<3>(ax, ay, az);
+        vote4<CW, true>(hist, ax, ay, az, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
+        soa_issue_lanes(desc, stride, min(j + 2 * B, j1 - B), hoff, ax, ay, az);
+        soa_wait<3>(bx, by, bz);
+        vote4<CW, true>(hist, bx, by, bz, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
+    }
+    soa_wait<0>(ax, ay, az);              // the last block issued, used or not
+    if (j + B <= j1)
+        vote4<CW, true>(hist, ax, ay, az, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
+}
+
 // Source bucket of a scaled x coordinate: floor((P - sb_lo) * sb_scale), clamped
 // to the table.  Monotone in P, which is all the vote windows rely on.
 __device__ __forceinline__ int src_bucket(const SweepArgs &a, float P)
@@ -425,16 +466,20 @@ __device__ __forceinline__ void src_window(const SweepArgs &a, __amdgpu_buffer_r
 }
 
 // Votes of all pairs whose bin falls in the box x-planes [x0, x0 + np) into the
-// LDS counters.  Work units are (64-point lane group, part of the group's stream
-// range), G parts per group; waves take units one at a time from an LDS counter
+// LDS counters.  Work units are (lane group, part of the group's stream range),
+// G parts per group; waves take units one at a time from an LDS counter
 // (cleared with the slab), so a wave whose ranges were short takes more units
 // instead of idling at the slab's closing barrier.
-//   sorted: lanes hold 64 consecutive points of the x-sorted reference, the
-//           stream is the window of the rotation's x-sorted sources;
+//   sorted: a lane group is 2^lg consecutive points of the x-sorted reference,
+//           held by each of the wave's 64 >> lg lane sub-groups; the stream is
+//           the window of the rotation's x-sorted sources, padded to blocks of
+//           B = 256 >> lg sources of which sub-group h takes 4h .. 4h + 3;
 //   else:   lanes hold 64 rotated sources, the stream is the whole reference.
-template <int CW>
+// lg is a template constant (one instantiation per lane-group size): as a
+// run-time value it cost 1.5% of the sweep.
+template <int CW, int LG, bool SORTED>
 __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, uint32_t *hist,
-                          bool sorted, int slot)
+                          int slot)
 {
     const Geom &g = a.g;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -443,17 +488,20 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
     const uint32_t negc = 0u - (uint32_t)x0 * sx4;
     const int m = g.m;
     uint32_t *ctr = hist + kHistWordsMax + kUnitCounter;
-    if (sorted) {
-        const int ngr = (m + 63) >> 6;
+    if (SORTED) {
+        constexpr int lg = LG;
+        const int gsz = 1 << lg;
+        const int B = 256 >> lg;
+        const int ngr = (m + gsz - 1) >> lg;
         const int G = a.vote_parts > 0 ? a.vote_parts : vote_parts_auto(ngr);
         const int total = ngr * G;
-        // part boundaries lo + span * p * gmul / 8192: spans are at most kSortMax
-        // sources here and G at most 8, so the product stays below 2^32
+        const uint32_t hoff = 16u * (uint32_t)(lane >> lg);
+        // part boundaries lo + B * (nb * p * gmul / 8192), nb the window's blocks:
+        // nb <= kSortMax / 4 and p * gmul < 8192, so the product stays below 2^32
         const uint32_t gmul = 8192u / (uint32_t)G;
         const int64_t ns = src_stride(a.scratch_stride);
         const float *sp = a.scratch + (size_t)slot * slot_floats(a.scratch_stride);
         const f4u sdesc = soa_desc(sp, ns);
-        const __amdgpu_buffer_rsrc_t srs = soa_rsrc(sp, ns);
         const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(sp + 3 * ns), 0, 4 * (kSrcBuckets + 1), 0x00020000);
         const uint32_t *scr = hist + kHistWordsMax;
@@ -466,7 +514,7 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             if (u >= total) break;
             const int part = u / ngr;
             const int gi = u - part * ngr;
-            const int j = gi * 64 + lane;
+            const int j = gi * gsz + (lane & (gsz - 1));
             float Yx = -1.0e7f, Yy = -1.0e7f, Yz = -1.0e7f;   // padding lanes never vote
             if (j < m) {
                 Yx = a.ys[j];
@@ -474,19 +522,22 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
                 Yz = a.ys[2 * m + j];
             }
             // the group's x range: its first and last point (the reference is sorted)
-            const float ymin = a.ys[gi * 64];
-            const float ymax = a.ys[min(m, gi * 64 + 64) - 1];
+            const float ymin = a.ys[gi * gsz];
+            const float ymax = a.ys[min(m, gi * gsz + gsz) - 1];
             int lo, hi;
             src_window(a, trs, bmin, bmax, ymin, ymax, x0, x0 + np, lo, hi);
             lo = uni(lo);
             hi = uni(max(hi, lo));
-            const uint32_t span = (uint32_t)(hi - lo);
-            const int j0 = uni(lo + (int)((span * (uint32_t)part * gmul) >> 13));
+            const int lenB = (hi - lo + B - 1) & -B;
+            hi = min((int)ns, lo + lenB);
+            lo = hi - lenB;
+            const uint32_t nb = (uint32_t)(lenB / B);
+            const int j0 = uni(lo + B * (int)((nb * (uint32_t)part * gmul) >> 13));
             const int j1 = part + 1 == G
                                ? hi
-                               : uni(lo + (int)((span * (uint32_t)(part + 1) * gmul) >> 13));
-            vote_span<CW, true>(hist, sdesc, srs, (int)ns, j0, j1, Yx, Yy, Yz, x0, (uint32_t)np,
-                                Sy, Sz, sx4, sy4, negc);
+                               : uni(lo + B * (int)((nb * (uint32_t)(part + 1) * gmul) >> 13));
+            vote_span_lanes<CW>(hist, sdesc, (int)ns, j0, j1, B, hoff, Yx, Yy, Yz, x0,
+                                (uint32_t)np, Sy, Sz, sx4, sy4, negc);
         }
     } else {
         const int nsg = (g.n + 63) >> 6;
@@ -520,7 +571,7 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
 
 // Bucket-sort the rotated, scaled source points of one rotation by x into this
 // workgroup's scratch slot (x, y, z arrays) and write the bucket table after
-// them, so that the vote can restrict each 64-reference lane group to the sources
+// them, so that the vote can restrict each reference lane group to the sources
 // whose pairs can land in the current slab.
 __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, uint32_t *scr,
                              int slot)
@@ -615,6 +666,13 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
         ox[pos] = __fmul_rn(px, g.s);
         oy[pos] = __fmul_rn(py, g.s);
         oz[pos] = __fmul_rn(pz, g.s);
+    }
+    // sentinels up to the padded stride: windows padded to whole blocks may
+    // stream them, and no pair with them passes the range tests
+    if (tid < (int)(ns - g.n)) {
+        ox[g.n + tid] = 1.0e7f;
+        oy[g.n + tid] = 1.0e7f;
+        oz[g.n + tid] = 1.0e7f;
     }
     __syncthreads();
 }
@@ -931,6 +989,11 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
     const uint32_t Sy = g.size[1];
     const uint32_t RW = (uint32_t)g.row_words;
     const bool sorted = a.scratch != nullptr;
+    const int lg = a.lane_group == 16   ? 4
+                   : a.lane_group == 32 ? 5
+                   : a.lane_group == 64 ? 6
+                                        : lane_group_log2(g.m, g.n, g.size[0], a.ref_x_extent,
+                                                          a.vote_parts);
   {
     float R[9];
 #pragma unroll
@@ -951,7 +1014,14 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
         for (int w = tid; w < words4; w += kBlock) h4[w] = make_uint4(0, 0, 0, 0);
         if (tid == 0) scr[kUnitCounter] = 0u;
         __syncthreads();
-        vote_slab<CW>(a, R, x0, np, hist, sorted, slot);
+        if (!sorted)
+            vote_slab<CW, 6, false>(a, R, x0, np, hist, slot);
+        else if (lg == 4)
+            vote_slab<CW, 4, true>(a, R, x0, np, hist, slot);
+        else if (lg == 5)
+            vote_slab<CW, 5, true>(a, R, x0, np, hist, slot);
+        else
+            vote_slab<CW, 6, true>(a, R, x0, np, hist, slot);
         __syncthreads();
         // the slab's largest count first (cheap), and only when it beats the best of
         // the earlier slabs its lowest position (a later slab never wins a tie: its

@@ -302,6 +302,7 @@ dses_status ServerImpl::prepare(Request *r)
     a.scratch = sorted ? reinterpret_cast<float *>(4) : nullptr;   // per-slice scratch at launch
     a.scratch_stride = kServeMaxSrc;
     source_buckets(stg->ylo, stg->yhi, g.size[0], &a.sb_lo, &a.sb_scale, &a.sb_n);
+    a.ref_x_extent = (float)(stg->yhi - stg->ylo) + 1.0f;
     a.g = g;
     a.grid = cg;
     if (r->scorer == DSES_SCORER_DF) {

@@ -49,7 +49,7 @@ class Options(C.Structure):
                 ("tau", C.c_float), ("t_min", C.c_float * 3), ("t_max", C.c_float * 3),
                 ("scorer", C.c_int32), ("top_k", C.c_int32), ("stream", C.c_void_p),
                 ("records", C.c_void_p), ("topk", C.c_void_p), ("q", C.c_float),
-                ("p", C.c_float)]
+                ("p", C.c_float), ("lane_group", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -233,10 +233,11 @@ def _stream_of(stream):
 
 
 def _options(args: _Args, delta_t, tau, t_min, t_max, scorer, timing, stream, records_ptr,
-             q=0.0, lp=0.0):
+             q=0.0, lp=0.0, lane_group=0):
     o = Options()
     o.q = float(q)
     o.p = float(lp)
+    o.lane_group = int(lane_group)
     o.struct_size = C.sizeof(Options)
     o.flags = (DEVICE_PTRS if args.device else 0) | (TIMING if timing else 0)
     o.delta_t = 0.0 if delta_t is None else float(delta_t)
@@ -290,16 +291,18 @@ def _topk_buffer(args: _Args, k: int, o: Options):
 
 def register(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=None,
              t_min=None, t_max=None, scorer="auto", records=False, top_k=0, q=0.0,
-             lp=0.0, timing=False, stream=None) -> Registration:
+             lp=0.0, timing=False, stream=None, lane_group=0) -> Registration:
     """dses_register: the full sweep over the rotation list (top_k > 0: also the best
     top_k candidates in selection order, Registration.top; q > 0: score only the
-    rotations with M_k >= q M*; lp: exponent of metric "trunc_lp")."""
+    rotations with M_k >= q M*; lp: exponent of metric "trunc_lp"; lane_group: vote
+    layout, 16, 32 or 64 reference points per lane group, 0 automatic)."""
     args = _Args()
     ps, n = args.ptr(src, 3)
     pt, m = args.ptr(tgt, 3)
     pr, k = args.ptr(rotations, 9)
     rbuf, rptr = _records_buffer(args, k) if records else (None, None)
-    o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr, q, lp)
+    o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr, q, lp,
+                 lane_group)
     tbuf = _topk_buffer(args, int(top_k), o)
     res = Result()
     _check(lib().dses_register(ps, n, pt, m, pr, k, C.c_float(eps), METRICS[metric],

@@ -71,6 +71,11 @@ def test_argument_errors_need_no_gpu(libpath):
         with pytest.raises(dses.DsesError) as e:
             dses.register(np.zeros((3, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05, q=q)
         assert e.value.status == dses.DSES_E_INVAL, (q, e.value)
+    for lg in (-1, 8, 48, 128):
+        with pytest.raises(dses.DsesError) as e:
+            dses.register(np.zeros((3, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05,
+                          lane_group=lg)
+        assert e.value.status == dses.DSES_E_INVAL, (lg, e.value)
     item = {"src": np.zeros((3, 3)), "tgt": np.zeros((4, 3)),
             "rotations": np.eye(3).reshape(1, 9), "eps": 0.05}
     for kw in ({"vote_parts": 17}, {"vote_parts": -1}, {"tile_rot": -2}):

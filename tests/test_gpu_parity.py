@@ -118,6 +118,31 @@ def test_runs_on_a_side_stream():
 
 
 # ---------------------------------------------------------------------------
+# vote layouts: 16, 32 or 64 reference points per lane group
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,m,k", [(1, 1, 2), (37, 15, 5), (717, 1024, 24), (300, 1000, 9),
+                                   (16384, 130, 2), (4100, 1777, 3)])
+def test_lane_group_layouts(n, m, k):
+    """Every lane-group size gives the oracle's records, bit-identical to the
+    others (ragged group counts, windows shorter than a block, one point)."""
+    rng = np.random.default_rng(n * 13 + m)
+    tgt = rng.uniform(-0.8, 0.8, (m, 3)).astype(np.float32)
+    src = (tgt[rng.integers(0, m, n)] + rng.normal(0, 0.01, (n, 3))).astype(np.float32)
+    rots = synth.random_rotations(rng, k).reshape(-1, 9).astype(np.float32)
+    rots[0] = np.eye(3, dtype=np.float32).reshape(9)
+    p = synth.Problem(src, tgt, rots, 0.03, np.eye(3), np.zeros(3))
+    ref = oracle.records(p.src, p.tgt, p.rotations, p.eps)
+    first = None
+    for lg in (16, 32, 64, 0):
+        got = dses.register(_dev(p.src), _dev(p.tgt), _dev(p.rotations), p.eps,
+                            records=True, lane_group=lg)
+        compare_records(got.records, ref, n, label=f"lane_group={lg}")
+        if first is None:
+            first = got.records.tobytes()
+        assert got.records.tobytes() == first, lg
+
+
+# ---------------------------------------------------------------------------
 # ragged sizes, boxes and counter widths
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n,m,k", [(1, 1, 1), (1, 300, 7), (65, 1, 5), (65, 1023, 33),

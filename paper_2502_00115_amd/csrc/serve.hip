@@ -181,11 +181,11 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     opt = o;
     if (opt.memory_budget <= 0) opt.memory_budget = (int64_t)1 << 30;
     if (opt.max_inflight <= 0) opt.max_inflight = 64;
-    if (opt.aging == 0.0f) opt.aging = 4.0f;
+    if (opt.aging == 0.0f) opt.aging = 2.0f;
     if (opt.aging < 0.0f) opt.aging = 0.0f;
     max_slots = opt.max_inflight;
     grid = std::max(1, c->n_cu);
-    slice_pairs = 1.0e6 * (opt.slice_mpairs > 0 ? opt.slice_mpairs : 6000);
+    slice_pairs = 1.0e6 * (opt.slice_mpairs > 0 ? opt.slice_mpairs : 12000);
     DSES_HIP(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
     // The slice streams must sit on two different hardware queues: kernels of one
     // queue never overlap, and streams created the ordinary way share a small

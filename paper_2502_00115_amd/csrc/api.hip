@@ -421,7 +421,11 @@ void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, floa
     // a source votes only if some Y - P lies in [0, size_x): P in (ylo - size_x, yhi + 1)
     const double lo = (double)ylo - size_x - 1;
     const double range = (double)yhi + 2 - lo;
-    double scale = 4.0;
+    // 16 buckets per bin when the range fits: window ends are rounded to a bucket,
+    // and finer buckets measured faster up to 16 (4,096-point sources against
+    // 16,384 points: 2.4% against 4 per bin; 717 against 1,024: 0.3%; 32 per bin
+    // no better, 64 slower)
+    double scale = 16.0;
     while (range * scale > kSrcBuckets && scale > 1.0 / (1 << 20)) scale *= 0.5;
     *sb_lo = (float)lo;
     *sb_scale = (float)scale;

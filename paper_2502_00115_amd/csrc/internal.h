@@ -52,7 +52,7 @@ struct Field {
 
 // Per-rotation source sort: sb_n buckets (a multiple of the block size, at most
 // kSrcBuckets) over the scaled x coordinate, sb_scale buckets per bin (a power
-// of two, 4 when the reachable range fits).
+// of two, 16 when the reachable range fits).
 constexpr int kSrcBuckets = 8192;
 constexpr int kSortMax = 16384;         // largest source cloud that is bucket-sorted
 // Vote work units per 64-point lane group when not fixed by the caller: enough

@@ -125,7 +125,7 @@ struct SweepArgs {
 
 // Scratch slot of one workgroup (floats): rotated scaled sources sorted by x as
 // three arrays x, y, z of src_stride(cap) floats each (entries n .. stride-1 hold
-// sentinels that never vote, so windows can be padded to blocks of 16), then the
+// sentinels that never vote, so windows can be padded to a multiple of 4), then the
 // bucket table T[0 .. kSrcBuckets] (int32: T[b] = sources in buckets below b).
 __host__ __device__ inline int64_t src_stride(int64_t cap) { return (cap + 15) & ~int64_t(15); }
 __host__ __device__ inline int64_t slot_floats(int64_t cap)

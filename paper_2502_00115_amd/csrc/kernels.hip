@@ -409,15 +409,30 @@ __device__ __forceinline__ void vote_span(uint32_t *hist, const f4u &desc,
 }
 
 // Votes of the lane point L against the streamed points [j0, j1), j1 - j0 a
-// multiple of the block B = 4 * 64 / (lane-group size): within each block, lane
-// sub-group h (its hoff = 16 h bytes) takes points 4h .. 4h + 3.
+// multiple of 4: in each whole block of B = 4 * 64 / (lane-group size) points,
+// lane sub-group h (its hoff = 16 h bytes) takes points 4h .. 4h + 3; the r < B
+// points after the last whole block go in r / S steps (S = B / 4 sub-groups),
+// sub-group h taking point S q + h in step q (every index stays below j1).
 template <int CW>
-__device__ __forceinline__ void vote_span_lanes(uint32_t *hist, const f4u &desc, int stride,
-                                                int j0, int j1, int B, uint32_t hoff, float Lx,
+__device__ __forceinline__ void vote_span_lanes(uint32_t *hist, const f4u &desc,
+                                                __amdgpu_buffer_rsrc_t rs, int stride, int j0,
+                                                int j1, int B, uint32_t hoff, float Lx,
                                                 float Ly, float Lz, int x0, uint32_t np,
                                                 uint32_t Sy, uint32_t Sz, uint32_t sx4,
                                                 uint32_t sy4, uint32_t negc)
 {
+    const int jb = B > 4 ? j0 + (j1 - j0) / B * B : j1;   // B == 4: no tail
+    for (int t = jb; t < j1; t += B >> 2) {
+        const uint32_t vo = 4u * (uint32_t)(t - jb) + (hoff >> 2);
+        const float ux = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, 4 * jb, 0));
+        const float uy = __uint_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(rs, vo, 4 * (stride + jb), 0));
+        const float uz = __uint_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(rs, vo, 4 * (2 * stride + jb), 0));
+        vote_pair<CW>(hist, cvt_flr(Lx - ux), cvt_flr(Ly - uy), cvt_flr(Lz - uz), x0, np, Sy,
+                      Sz, sx4, sy4, negc);
+    }
+    j1 = jb;
     if (j0 >= j1) return;
     f4u ax, ay, az, bx, by, bz;
     int j = j0;
@@ -472,8 +487,9 @@ __device__ __forceinline__ void src_window(const SweepArgs &a, __amdgpu_buffer_r
 // instead of idling at the slab's closing barrier.
 //   sorted: a lane group is 2^lg consecutive points of the x-sorted reference,
 //           held by each of the wave's 64 >> lg lane sub-groups; the stream is
-//           the window of the rotation's x-sorted sources, padded to blocks of
-//           B = 256 >> lg sources of which sub-group h takes 4h .. 4h + 3;
+//           the window of the rotation's x-sorted sources, padded to a multiple
+//           of 4 and taken in blocks of B = 256 >> lg sources (sub-group h takes
+//           4h .. 4h + 3) plus a strided tail (vote_span_lanes);
 //   else:   lanes hold 64 rotated sources, the stream is the whole reference.
 // lg is a template constant (one instantiation per lane-group size): as a
 // run-time value it cost 1.5% of the sweep.
@@ -502,6 +518,7 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
         const int64_t ns = src_stride(a.scratch_stride);
         const float *sp = a.scratch + (size_t)slot * slot_floats(a.scratch_stride);
         const f4u sdesc = soa_desc(sp, ns);
+        const __amdgpu_buffer_rsrc_t srs = soa_rsrc(sp, ns);
         const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(sp + 3 * ns), 0, 4 * (kSrcBuckets + 1), 0x00020000);
         const uint32_t *scr = hist + kHistWordsMax;
@@ -528,15 +545,17 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             src_window(a, trs, bmin, bmax, ymin, ymax, x0, x0 + np, lo, hi);
             lo = uni(lo);
             hi = uni(max(hi, lo));
-            const int lenB = (hi - lo + B - 1) & -B;
-            hi = min((int)ns, lo + lenB);
-            lo = hi - lenB;
-            const uint32_t nb = (uint32_t)(lenB / B);
-            const int j0 = uni(lo + B * (int)((nb * (uint32_t)part * gmul) >> 13));
+            // a multiple of 4 inside the padded arrays: the extra points are
+            // sources outside the window or sentinels, rejected by the range tests
+            const int len4 = (hi - lo + 3) & ~3;
+            hi = min((int)ns, lo + len4);
+            lo = hi - len4;
+            const uint32_t nb = (uint32_t)(len4 >> 2);
+            const int j0 = uni(lo + 4 * (int)((nb * (uint32_t)part * gmul) >> 13));
             const int j1 = part + 1 == G
                                ? hi
-                               : uni(lo + B * (int)((nb * (uint32_t)(part + 1) * gmul) >> 13));
-            vote_span_lanes<CW>(hist, sdesc, (int)ns, j0, j1, B, hoff, Yx, Yy, Yz, x0,
+                               : uni(lo + 4 * (int)((nb * (uint32_t)(part + 1) * gmul) >> 13));
+            vote_span_lanes<CW>(hist, sdesc, srs, (int)ns, j0, j1, B, hoff, Yx, Yy, Yz, x0,
                                 (uint32_t)np, Sy, Sz, sx4, sy4, negc);
         }
     } else {
@@ -667,7 +686,7 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
         oy[pos] = __fmul_rn(py, g.s);
         oz[pos] = __fmul_rn(pz, g.s);
     }
-    // sentinels up to the padded stride: windows padded to whole blocks may
+    // sentinels up to the padded stride: windows padded to a multiple of 4 may
     // stream them, and no pair with them passes the range tests
     if (tid < (int)(ns - g.n)) {
         ox[g.n + tid] = 1.0e7f;

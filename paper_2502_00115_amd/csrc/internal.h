@@ -68,8 +68,8 @@ __host__ __device__ inline int vote_parts_auto(int groups)
 // Smaller groups span less x, so their windows carry less slack (about
 // 2^lg * X source-bins per slab over all groups, X the reference's x extent in
 // bins), but there are more work units, each costing about kUnitSteps wave steps
-// of set-up and block padding; rho = n / (X + size_x) sources per bin turns a
-// step into 64 / rho source-bins.  The size with the least modelled cost wins
+// of set-up, padding and slab-end imbalance (fitted); rho = n / (X + size_x)
+// sources per bin turns a step into 64 / rho source-bins.  The size with the least modelled cost wins
 // (ties: the larger group).  It picks 16 for a 717-point source against a
 // 1,024-point reference with eps 0.03 (measured fastest, 10% below 64) and 64 for
 // 64 / 256 points and for 4,096 / 16,384 points (both measured fastest).

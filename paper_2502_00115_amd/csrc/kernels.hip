@@ -529,7 +529,7 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             if (lane == 0) u = (int)atomicAdd(ctr, 1u);
             u = __builtin_amdgcn_readfirstlane(u);
             if (u >= total) break;
-            const int part = u / ngr;
+            const int part = G == 1 ? 0 : u / ngr;
             const int gi = u - part * ngr;
             const int j = gi * gsz + (lane & (gsz - 1));
             float Yx = -1.0e7f, Yy = -1.0e7f, Yz = -1.0e7f;   // padding lanes never vote
@@ -538,9 +538,11 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
                 Yy = a.ys[m + j];
                 Yz = a.ys[2 * m + j];
             }
-            // the group's x range: its first and last point (the reference is sorted)
-            const float ymin = a.ys[gi * gsz];
-            const float ymax = a.ys[min(m, gi * gsz + gsz) - 1];
+            // the group's x range: its first and last point (the reference is sorted),
+            // read from lanes 0 and gsz - 1 of the first lane sub-group
+            const float ymin = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Yx), 0));
+            const float ymax = __int_as_float(
+                __builtin_amdgcn_readlane(__float_as_int(Yx), min(m - gi * gsz, gsz) - 1));
             int lo, hi;
             src_window(a, trs, bmin, bmax, ymin, ymax, x0, x0 + np, lo, hi);
             lo = uni(lo);

@@ -519,6 +519,7 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
         const float *sp = a.scratch + (size_t)slot * slot_floats(a.scratch_stride);
         const f4u sdesc = soa_desc(sp, ns);
         const __amdgpu_buffer_rsrc_t srs = soa_rsrc(sp, ns);
+        const __amdgpu_buffer_rsrc_t yrs = soa_rsrc(a.ys, m);
         const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(sp + 3 * ns), 0, 4 * (kSrcBuckets + 1), 0x00020000);
         const uint32_t *scr = hist + kHistWordsMax;
@@ -532,12 +533,12 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             const int part = G == 1 ? 0 : u / ngr;
             const int gi = u - part * ngr;
             const int j = gi * gsz + (lane & (gsz - 1));
-            float Yx = -1.0e7f, Yy = -1.0e7f, Yz = -1.0e7f;   // padding lanes never vote
-            if (j < m) {
-                Yx = a.ys[j];
-                Yy = a.ys[m + j];
-                Yz = a.ys[2 * m + j];
-            }
+            // padding lanes (j >= m) never vote; their loads stay inside ys (clamped)
+            const uint32_t yo = 4u * (uint32_t)min(j, m - 1);
+            float Yx = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(yrs, yo, 0, 0));
+            float Yy = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(yrs, yo, 4 * m, 0));
+            float Yz = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(yrs, yo, 8 * m, 0));
+            if (j >= m) Yx = Yy = Yz = -1.0e7f;
             // the group's x range: its first and last point (the reference is sorted),
             // read from lanes 0 and gsz - 1 of the first lane sub-group
             const float ymin = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Yx), 0));

@@ -8,17 +8,34 @@
  * Nothing in the product links or calls this file.  It shares no code, header or
  * constant with the HIP library.
  *
- * Precision.  All geometry that produces a real-valued result (rotated points,
- * nearest-neighbour distances, errors, distance-field values) is computed in
- * IEEE double.  Two steps turn floating point into an integer: the translation
- * bin of a point pair (ROUND in Alg. 2) and the voxel a query falls in for
- * distance-field scoring.  The paper fixes no precision for them, so both take
- * the decision in the kernel's precision, IEEE single, by the formulas written
- * out in bin_of_pair() and df_voxel_of() (the same formulas the library's
- * header documents).  Counts, modes and voxel indices are then exact integers.
+ * Precision.  Everything is computed in IEEE double from the float32 input bits,
+ * which promote exactly.  The translation bin of a point pair is the plain
+ * definition of ROUND in Alg. 2 (Lemma 2, Eq. (5)):
+ *     u = (y_j - R x_i) / delta    (per axis, true division),   b = floor(u + 1/2),
+ * the nearest lattice point b*delta, halves rounded up.  A pair whose u + 1/2 lies
+ * within mu bin units of an integer on some axis is *fragile*: any evaluation of u
+ * that is accurate to mu (a float32 kernel is, by orders of magnitude) may put it
+ * in the neighbouring bin across that face instead.  For every bin the vote keeps
+ * the count cnt(b) by the definition and two fragility counts,
+ *     out(b): fragile pairs counted in b that may belong elsewhere,
+ *     in(b):  fragile pairs counted elsewhere (or outside the box) that may belong to b,
+ * so any such evaluation counts a number of pairs in [cnt - out, cnt + in] in b.
+ * From these the mode is *pinned* (every such evaluation has the same mode b*,
+ * tie-break included) or ambiguous; an ambiguous rotation's admissible modes are
+ * the bins with cnt + in >= max over bins of (cnt - out).
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared -pthread -lm
- * (-ffp-contract=off keeps the single-precision steps exactly as written).
+ * The same reading applies to the voxel of a distance-field lookup (the field is
+ * this library's own scorer variant, not the paper's): the voxel of q is
+ * floor((q - lo)/h) in double, and a coordinate within mu_df voxel units of a
+ * voxel face makes the point's value an interval over the voxels it may fall in.
+ *
+ * A secondary mode (vote_f32 = 1) takes both decisions instead by the library's
+ * documented single-precision formulas (bin_of_pair_f32, df_voxel_of_f32 below).
+ * It exists only for a labelled, secondary bit-exactness check; every parity
+ * claim rests on the double-precision definition.
+ *
+ * Build: gcc -O2 -std=gnu11 -ffp-contract=off -fPIC -shared -pthread -lm
+ * (-ffp-contract=off keeps every rounding step exactly as written).
  */
 #include <math.h>
 #include <pthread.h>
@@ -29,16 +46,27 @@
 
 enum { ORC_TRUNC_L2 = 0, ORC_INLIERS = 1, ORC_TLS = 2, ORC_TRUNC_L1 = 3, ORC_TRUNC_LP = 4,
        ORC_VOTES = 5 };
+enum { ORC_DF_NEAREST = 0, ORC_DF_TRILINEAR = 1 };
 
-/* Per-rotation outcome of Alg. 2, one row of the candidate list. */
+/* Per-rotation outcome of Alg. 2, one row of the candidate list (80 bytes). */
 typedef struct {
     int32_t bin[3];     /* mode bin b* (t* = delta * b*), lattice units            */
-    uint32_t votes;     /* M: vote count of the mode bin                           */
-    int32_t inliers;    /* #{i : d_i < eps}                                        */
+    uint32_t votes;     /* M = cnt(b*): vote count of the mode bin                  */
+    int32_t inliers;    /* #{i : d_i < eps} at t*                                   */
     int32_t boundary;   /* #{i : |d_i - eps| <= 1e-6}, reported, not compared      */
     double error;       /* e(R, t*) under the chosen metric                        */
     int32_t valid;      /* 0 when no pair voted inside the translation box         */
-    int32_t pad;
+    int32_t rot;        /* index of the rotation in the caller's list              */
+    uint32_t votes_lo;  /* cnt(b*) - out(b*)                                       */
+    uint32_t votes_hi;  /* cnt(b*) + in(b*)                                        */
+    uint32_t lo_max;    /* max over bins of cnt - out                              */
+    int32_t pinned;     /* 1: the mode (and validity) is the same for every        */
+                        /*    evaluation accurate to mu                            */
+    int32_t frag;       /* fragile pairs with an effect inside the box             */
+    int32_t inl_frag;   /* points whose distance-field value is fragile and whose  */
+                        /*    inlier decision depends on the voxel taken           */
+    double err_lo;      /* error range over the fragile voxel choices              */
+    double err_hi;      /*   (both equal error for the exact scorer)               */
 } orc_record;
 
 /* ------------------------------------------------------------------------ */
@@ -60,15 +88,157 @@ int orc_box(float delta, const float *t_min, const float *t_max, int32_t *k_lo, 
     return 0;
 }
 
+static size_t lin_of(const int32_t *b, const int32_t *k_lo, const int32_t *size)
+{
+    return ((size_t)(b[0] - k_lo[0]) * size[1] + (size_t)(b[1] - k_lo[1])) * size[2] +
+           (size_t)(b[2] - k_lo[2]);
+}
+
+static int in_box(const int32_t *b, const int32_t *k_lo, const int32_t *size)
+{
+    for (int a = 0; a < 3; ++a)
+        if (b[a] < k_lo[a] || b[a] >= k_lo[a] + size[a]) return 0;
+    return 1;
+}
+
+static void bin_of_lin(size_t l, const int32_t *k_lo, const int32_t *size, int32_t *b)
+{
+    b[2] = (int32_t)(l % (size_t)size[2]) + k_lo[2];
+    b[1] = (int32_t)((l / (size_t)size[2]) % (size_t)size[1]) + k_lo[1];
+    b[0] = (int32_t)(l / ((size_t)size[1] * size[2])) + k_lo[0];
+}
+
+/* R x in double: row a of R dotted with x, left to right. */
+static void rotate64(const float *R, const float *x, double *p)
+{
+    for (int a = 0; a < 3; ++a)
+        p[a] = (double)R[3 * a] * x[0] + (double)R[3 * a + 1] * x[1] + (double)R[3 * a + 2] * x[2];
+}
+
 /* ------------------------------------------------------------------------ */
-/* ROUND(y_j - R x_i, delta) of Alg. 2, taken in single precision:          */
-/*   s      = 1/delta                                   (float division)     */
-/*   p_a    = fma(R_a2, x_z, fma(R_a1, x_y, R_a0 * x_x)) (float)             */
-/*   Y_a    = (y_a * s) + (0.5 - k_lo_a)                (two float roundings)*/
-/*   P_a    = p_a * s                                   (float)              */
-/*   c_a    = floor(Y_a - P_a)                          (float subtract)     */
-/* so c_a = floor((y_a - p_a)/delta + 1/2) - k_lo_a, the box-relative index   */
-/* of the nearest lattice point.  The pair votes iff 0 <= c_a < size_a.      */
+/* Lemma 2 / Alg. 2 first loop, by the definition: for one rotation, every   */
+/* pair (i, j) votes for b = floor((y_j - R x_i)/delta + 1/2); the mode is    */
+/* the bin with the largest count, ties to the lowest linear index (x         */
+/* slowest; the paper is silent).  Fills the dense count and fragility arrays */
+/* (each nbins long) and the summary below.                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t mode[3];
+    uint32_t M, lo, hi, lo_max;
+    int32_t pinned, frag;
+} vote_info;
+
+static void vote64(const float *src, int32_t n, const float *tgt, int32_t m, const float *R,
+                   double delta, double mu, const int32_t *k_lo, const int32_t *size,
+                   uint32_t *cnt, uint32_t *outf, uint32_t *inf, vote_info *vi)
+{
+    const size_t nbins = (size_t)size[0] * size[1] * size[2];
+    memset(cnt, 0, nbins * sizeof(uint32_t));
+    memset(outf, 0, nbins * sizeof(uint32_t));
+    memset(inf, 0, nbins * sizeof(uint32_t));
+    int32_t frag = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        double p[3];
+        rotate64(R, src + 3 * i, p);
+        for (int32_t j = 0; j < m; ++j) {
+            const float *y = tgt + 3 * j;
+            int32_t b[3], alt[3];
+            int mask = 0, far = 0;
+            for (int a = 0; a < 3; ++a) {
+                double u = ((double)y[a] - p[a]) / delta;
+                double w = u + 0.5;
+                double f = floor(w);
+                /* two bins or more outside the box: neither b nor a neighbour is in it */
+                if (!(f >= k_lo[a] - 1.5 && f <= (double)k_lo[a] + size[a] + 0.5)) {
+                    far = 1;
+                    break;
+                }
+                b[a] = (int32_t)f;
+                double frac = w - f;            /* in [0, 1) */
+                alt[a] = b[a];
+                if (frac < mu) { alt[a] = b[a] - 1; mask |= 1 << a; }
+                else if (frac > 1.0 - mu) { alt[a] = b[a] + 1; mask |= 1 << a; }
+            }
+            if (far) continue;
+            if (!mask) {
+                if (in_box(b, k_lo, size)) cnt[lin_of(b, k_lo, size)] += 1;
+                continue;
+            }
+            /* a fragile pair: the definition's bin (combination 0) and every bin
+               reached by moving across some of its near faces */
+            int effect = 0;
+            for (int c = 0; c < 8; ++c) {
+                if (c & ~mask) continue;
+                int32_t v[3];
+                for (int a = 0; a < 3; ++a) v[a] = ((c >> a) & 1) ? alt[a] : b[a];
+                if (!in_box(v, k_lo, size)) continue;
+                size_t l = lin_of(v, k_lo, size);
+                effect = 1;
+                if (c == 0) { cnt[l] += 1; outf[l] += 1; }
+                else inf[l] += 1;
+            }
+            frag += effect;
+        }
+    }
+    /* mode: the first largest count; `before` / `after` track the largest count
+       at lower / higher linear index than the current best */
+    uint32_t best = 0, before = 0, after = 0;
+    size_t arg = 0;
+    for (size_t l = 0; l < nbins; ++l) {
+        if (cnt[l] > best) { before = best; best = cnt[l]; arg = l; after = 0; }
+        else if (cnt[l] > after && l > arg) after = cnt[l];
+    }
+    int any_in = 0;
+    for (size_t l = 0; l < nbins; ++l) {
+        if (!inf[l]) continue;
+        any_in = 1;
+        uint32_t h = cnt[l] + inf[l];
+        if (l < arg && h > before) before = h;
+        if (l > arg && h > after) after = h;
+    }
+    bin_of_lin(arg, k_lo, size, vi->mode);
+    vi->M = best;
+    vi->lo = best - outf[arg];
+    vi->hi = best + inf[arg];
+    vi->frag = frag;
+    if (best == 0)
+        vi->pinned = !any_in;         /* no pair can vote in the box */
+    else
+        vi->pinned = vi->lo > before && vi->lo >= after;
+    if (vi->pinned) {
+        vi->lo_max = vi->lo;          /* lo(b*) >= hi(b) >= lo(b) for every b */
+    } else {
+        uint32_t L = 0;
+        for (size_t l = 0; l < nbins; ++l)
+            if (cnt[l] - outf[l] > L) L = cnt[l] - outf[l];
+        vi->lo_max = L;
+    }
+}
+
+/* Exported for the pins and for admissibility queries: one rotation, dense arrays
+   (cnt, out, in) of size[0]*size[1]*size[2] entries each, x slowest.
+   info = {mode_x, mode_y, mode_z, M, lo, hi, lo_max, pinned, frag}. */
+int orc_vote64(const float *src, int32_t n, const float *tgt, int32_t m, const float *R,
+               float delta, double mu, const int32_t *k_lo, const int32_t *size, uint32_t *cnt,
+               uint32_t *outf, uint32_t *inf, int32_t *info)
+{
+    if (n < 0 || m < 0 || !(delta > 0.0f) || !(mu >= 0.0 && mu < 0.5)) return -1;
+    vote_info vi;
+    vote64(src, n, tgt, m, R, (double)delta, mu, k_lo, size, cnt, outf, inf, &vi);
+    info[0] = vi.mode[0]; info[1] = vi.mode[1]; info[2] = vi.mode[2];
+    info[3] = (int32_t)vi.M; info[4] = (int32_t)vi.lo; info[5] = (int32_t)vi.hi;
+    info[6] = (int32_t)vi.lo_max; info[7] = vi.pinned; info[8] = vi.frag;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* SECONDARY CHECK ONLY: the library's documented single-precision form of   */
+/* the bin decision,                                                         */
+/*   s = 1/delta, p_a = fma(R_a2, x_z, fma(R_a1, x_y, R_a0 * x_x)),           */
+/*   Y_a = (y_a * s) + (0.5 - k_lo_a), c_a = floor(Y_a - p_a * s)             */
+/* (box-relative).  It agrees with the definition except for pairs within    */
+/* float rounding of a face; it is used for a labelled bit-exactness check   */
+/* of the kernel's arithmetic, never for parity.                             */
 /* ------------------------------------------------------------------------ */
 static void rotate_f32(const float *R, const float *x, float *p)
 {
@@ -80,8 +250,8 @@ static void rotate_f32(const float *R, const float *x, float *p)
     }
 }
 
-static int bin_of_pair(const float *y, const float *p, float s, const int32_t *k_lo,
-                       const int32_t *size, int32_t *c)
+static int bin_of_pair_f32(const float *y, const float *p, float s, const int32_t *k_lo,
+                           const int32_t *size, int32_t *c)
 {
     int inside = 1;
     for (int a = 0; a < 3; ++a) {
@@ -96,15 +266,9 @@ static int bin_of_pair(const float *y, const float *p, float s, const int32_t *k
     return inside;
 }
 
-/* ------------------------------------------------------------------------ */
-/* Lemma 2 / Alg. 2 first loop: for one rotation, count every rotated pair   */
-/* translation into the dense vote array over the box and take its mode.    */
-/* Mode tie-break (the paper is silent): the lowest linear index, x slowest. */
-/* Returns the mode count M (0 if no pair voted).                            */
-/* ------------------------------------------------------------------------ */
-uint32_t orc_vote(const float *src, int32_t n, const float *tgt, int32_t m, const float *R,
-                  float delta, const int32_t *k_lo, const int32_t *size, uint32_t *hist,
-                  int32_t *mode_bin)
+uint32_t orc_vote_f32(const float *src, int32_t n, const float *tgt, int32_t m, const float *R,
+                      float delta, const int32_t *k_lo, const int32_t *size, uint32_t *hist,
+                      int32_t *mode_bin)
 {
     const size_t nbins = (size_t)size[0] * size[1] * size[2];
     const float s = 1.0f / delta;
@@ -114,7 +278,7 @@ uint32_t orc_vote(const float *src, int32_t n, const float *tgt, int32_t m, cons
         rotate_f32(R, src + 3 * i, p);
         for (int32_t j = 0; j < m; ++j) {
             int32_t c[3];
-            if (bin_of_pair(tgt + 3 * j, p, s, k_lo, size, c))
+            if (bin_of_pair_f32(tgt + 3 * j, p, s, k_lo, size, c))
                 hist[((size_t)c[0] * size[1] + c[1]) * size[2] + c[2]] += 1;
         }
     }
@@ -122,9 +286,7 @@ uint32_t orc_vote(const float *src, int32_t n, const float *tgt, int32_t m, cons
     size_t arg = 0;
     for (size_t l = 0; l < nbins; ++l)
         if (hist[l] > best) { best = hist[l]; arg = l; }
-    mode_bin[2] = (int32_t)(arg % size[2]) + k_lo[2];
-    mode_bin[1] = (int32_t)((arg / size[2]) % size[1]) + k_lo[1];
-    mode_bin[0] = (int32_t)(arg / ((size_t)size[1] * size[2])) + k_lo[0];
+    bin_of_lin(arg, k_lo, size, mode_bin);
     return best;
 }
 
@@ -151,8 +313,8 @@ void orc_nn(const double *q, int32_t nq, const float *tgt, int32_t m, int32_t l1
 }
 
 /* Robust per-point error rho(d) for the metrics of Sec. III / IV-B; lp is the */
-/* exponent of the truncated Lp objective (p < 1: the sparsity norms the paper */
-/* admits as "any desired norm").                                             */
+/* exponent of the truncated Lp objective (p < 1: the sparsity norms that the */
+/* paper allows in place of the L1 norm).                                     */
 static double rho(int metric, double d, double tau, double eps, double lp)
 {
     switch (metric) {
@@ -177,11 +339,9 @@ static void score_candidate(const float *src, int32_t n, const float *tgt, int32
     double err = 0.0;
     int32_t inl = 0, bnd = 0;
     for (int32_t i = 0; i < n; ++i) {
-        const float *x = src + 3 * i;
         double q[3];
-        for (int a = 0; a < 3; ++a)
-            q[a] = (double)R[3 * a] * x[0] + (double)R[3 * a + 1] * x[1] +
-                   (double)R[3 * a + 2] * x[2] + t[a];
+        rotate64(R, src + 3 * i, q);
+        for (int a = 0; a < 3; ++a) q[a] += t[a];
         double d2 = nn_dist(q, tgt, m, 0);
         double d = metric == ORC_TRUNC_L1 ? nn_dist(q, tgt, m, 1) : d2;
         if (d2 < eps) ++inl;
@@ -191,6 +351,9 @@ static void score_candidate(const float *src, int32_t n, const float *tgt, int32
     rec->inliers = inl;
     rec->boundary = bnd;
     rec->error = err;
+    rec->err_lo = err;
+    rec->err_hi = err;
+    rec->inl_frag = 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -198,9 +361,12 @@ static void score_candidate(const float *src, int32_t n, const float *tgt, int32
 /* the reference bounding box padded by r = max(tau, eps), voxel centres     */
 /*   c_a = lo_a + (idx_a + 1/2) h_a,                                          */
 /* value D = min(min_j ||c - y_j||, r) in double.  The box parameters are     */
-/* single precision so that both sides share them bit for bit:              */
+/* defined in single precision (they are the field's definition, not a       */
+/* result):                                                                  */
 /*   lo_a = min_j y_a - r,  hi_a = max_j y_a + r,  h_a = (hi_a - lo_a)/res,   */
 /*   inv_a = 1/h_a                                         (float arithmetic) */
+/* Outside the padded box every point is farther than r from the reference,  */
+/* so the field's value there is r.                                          */
 /* ------------------------------------------------------------------------ */
 void orc_df_params(const float *tgt, int32_t m, float r, int32_t res, float *lo, float *h,
                    float *inv)
@@ -218,20 +384,6 @@ void orc_df_params(const float *tgt, int32_t m, float r, int32_t res, float *lo,
         h[a] = ext / (float)res;
         inv[a] = 1.0f / h[a];
     }
-}
-
-/* Voxel of a single-precision query: idx_a = floor((q_a - lo_a) * inv_a).  */
-static int df_voxel_of(const float *q, const float *lo, const float *inv, int32_t res,
-                       int32_t *idx)
-{
-    int inside = 1;
-    for (int a = 0; a < 3; ++a) {
-        float u = q[a] - lo[a];
-        u = u * inv[a];
-        idx[a] = (int32_t)floorf(u);
-        if (idx[a] < 0 || idx[a] >= res) inside = 0;
-    }
-    return inside;
 }
 
 typedef struct {
@@ -282,13 +434,146 @@ int orc_df_build(const float *tgt, int32_t m, float r, int32_t res, int32_t nthr
     return 0;
 }
 
-/* Distance-field scoring of one candidate: the query q = R x + t is formed in */
-/* single precision (the same rotate_f32 chain, then + t), its voxel decided  */
-/* by df_voxel_of(); outside the grid the distance exceeds r, so D = r.       */
-static void score_candidate_df(const float *src, int32_t n, const float *R, const float *tf,
-                               int metric, double eps, double tau, double lp, float r,
-                               int32_t res, const float *lo, const float *inv,
-                               const double *field, orc_record *rec)
+typedef struct {
+    const double *field; int32_t res; float r; const float *lo; const float *h;
+    const float *inv; int lookup; double mu;
+} df_view;
+
+/* Field value at voxel idx; r outside the grid. */
+static double df_at(const df_view *f, const int32_t *idx)
+{
+    for (int a = 0; a < 3; ++a)
+        if (idx[a] < 0 || idx[a] >= f->res) return (double)f->r;
+    return f->field[((size_t)idx[0] * f->res + idx[1]) * f->res + idx[2]];
+}
+
+/* Nearest-voxel lookup of a double query: the voxel is floor((q - lo)/h) per
+   axis.  Returns the definition's value in *D and the smallest / largest value
+   over the voxels reachable by moving across faces within mu voxel units. */
+static void df_nearest64(const df_view *f, const double *q, double *D, double *Dmin,
+                         double *Dmax)
+{
+    int32_t idx[3], alt[3];
+    int mask = 0;
+    for (int a = 0; a < 3; ++a) {
+        double u = (q[a] - (double)f->lo[a]) / (double)f->h[a];
+        double w = floor(u);
+        if (!(w >= -1.5 && w <= f->res + 0.5)) {    /* far outside: every neighbour too */
+            idx[a] = alt[a] = -2;
+            continue;
+        }
+        idx[a] = alt[a] = (int32_t)w;
+        double frac = u - w;
+        if (frac < f->mu) { alt[a] = idx[a] - 1; mask |= 1 << a; }
+        else if (frac > 1.0 - f->mu) { alt[a] = idx[a] + 1; mask |= 1 << a; }
+    }
+    *D = *Dmin = *Dmax = df_at(f, idx);
+    for (int c = 1; c < 8; ++c) {
+        if (c & ~mask) continue;
+        int32_t v[3];
+        for (int a = 0; a < 3; ++a) v[a] = ((c >> a) & 1) ? alt[a] : idx[a];
+        double d = df_at(f, v);
+        if (d < *Dmin) *Dmin = d;
+        if (d > *Dmax) *Dmax = d;
+    }
+}
+
+/* Trilinear lookup: the field's values at the voxel centres (r at virtual centres
+   outside the grid) interpolated linearly along each axis.  Continuous in q, so
+   it has no fragile decision. */
+static double df_trilinear64(const df_view *f, const double *q)
+{
+    int32_t i0[3];
+    double fr[3];
+    for (int a = 0; a < 3; ++a) {
+        double u = (q[a] - (double)f->lo[a]) / (double)f->h[a] - 0.5;
+        if (!(u >= -1.0 && u < (double)f->res)) return (double)f->r;   /* all corners out */
+        double w = floor(u);
+        i0[a] = (int32_t)w;
+        fr[a] = u - w;
+    }
+    double acc = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        int32_t v[3];
+        double wgt = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            int hi = (c >> (2 - a)) & 1;
+            v[a] = i0[a] + hi;
+            wgt *= hi ? fr[a] : 1.0 - fr[a];
+        }
+        acc += wgt * df_at(f, v);
+    }
+    return acc;
+}
+
+/* Exported for the pins: per-query field values of double queries q (nq x 3):
+   D by the lookup's definition, Dmin / Dmax over the fragile voxel choices. */
+int orc_df_query(const double *q, int32_t nq, const double *field, int32_t res, float r,
+                 const float *lo, const float *h, int32_t lookup, double mu, double *D,
+                 double *Dmin, double *Dmax)
+{
+    if (res <= 0 || !(r > 0.0f) || !(mu >= 0.0 && mu < 0.5)) return -1;
+    if (lookup != ORC_DF_NEAREST && lookup != ORC_DF_TRILINEAR) return -1;
+    df_view f = {field, res, r, lo, h, NULL, lookup, mu};
+    for (int32_t i = 0; i < nq; ++i) {
+        if (lookup == ORC_DF_TRILINEAR)
+            D[i] = Dmin[i] = Dmax[i] = df_trilinear64(&f, q + 3 * i);
+        else
+            df_nearest64(&f, q + 3 * i, &D[i], &Dmin[i], &Dmax[i]);
+    }
+    return 0;
+}
+
+static void score_candidate_df64(const float *src, int32_t n, const float *R, const double *t,
+                                 int metric, double eps, double tau, double lp, const df_view *f,
+                                 orc_record *rec)
+{
+    double err = 0.0, elo = 0.0, ehi = 0.0;
+    int32_t inl = 0, bnd = 0, ifr = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        double q[3], D, Dmin, Dmax;
+        rotate64(R, src + 3 * i, q);
+        for (int a = 0; a < 3; ++a) q[a] += t[a];
+        if (f->lookup == ORC_DF_TRILINEAR) {
+            D = Dmin = Dmax = df_trilinear64(f, q);
+        } else {
+            df_nearest64(f, q, &D, &Dmin, &Dmax);
+        }
+        if (D < eps) ++inl;
+        if (fabs(D - eps) <= 1e-6) ++bnd;
+        if ((Dmin < eps) != (Dmax < eps)) ++ifr;
+        double e = rho(metric, D, tau, eps, lp);
+        double e1 = rho(metric, Dmin, tau, eps, lp), e2 = rho(metric, Dmax, tau, eps, lp);
+        err += e;
+        elo += e1 < e2 ? e1 : e2;   /* every rho here is non-decreasing in d */
+        ehi += e1 < e2 ? e2 : e1;
+    }
+    rec->inliers = inl;
+    rec->boundary = bnd;
+    rec->error = err;
+    rec->err_lo = elo;
+    rec->err_hi = ehi;
+    rec->inl_frag = ifr;
+}
+
+/* SECONDARY CHECK ONLY: the library's documented single-precision lookup,
+   q = fma-chain(R x) + t in float, idx_a = floor((q_a - lo_a) * inv_a). */
+static int df_voxel_of_f32(const float *q, const float *lo, const float *inv, int32_t res,
+                           int32_t *idx)
+{
+    int inside = 1;
+    for (int a = 0; a < 3; ++a) {
+        float u = q[a] - lo[a];
+        u = u * inv[a];
+        idx[a] = (int32_t)floorf(u);
+        if (idx[a] < 0 || idx[a] >= res) inside = 0;
+    }
+    return inside;
+}
+
+static void score_candidate_df_f32(const float *src, int32_t n, const float *R, const float *tf,
+                                   int metric, double eps, double tau, double lp,
+                                   const df_view *f, orc_record *rec)
 {
     double err = 0.0;
     int32_t inl = 0, bnd = 0;
@@ -297,9 +582,7 @@ static void score_candidate_df(const float *src, int32_t n, const float *R, cons
         int32_t idx[3];
         rotate_f32(R, src + 3 * i, p);
         for (int a = 0; a < 3; ++a) q[a] = p[a] + tf[a];
-        double D = df_voxel_of(q, lo, inv, res, idx)
-                       ? field[((size_t)idx[0] * res + idx[1]) * res + idx[2]]
-                       : (double)r;
+        double D = df_voxel_of_f32(q, f->lo, f->inv, f->res, idx) ? df_at(f, idx) : (double)f->r;
         if (D < eps) ++inl;
         if (fabs(D - eps) <= 1e-6) ++bnd;
         err += rho(metric, D, tau, eps, lp);
@@ -307,6 +590,28 @@ static void score_candidate_df(const float *src, int32_t n, const float *R, cons
     rec->inliers = inl;
     rec->boundary = bnd;
     rec->error = err;
+    rec->err_lo = err;
+    rec->err_hi = err;
+    rec->inl_frag = 0;
+}
+
+/* Score one candidate {R, delta * bin} with the chosen scorer. */
+static void score_bin(const float *src, int32_t n, const float *tgt, int32_t m, const float *R,
+                      const int32_t *bin, float delta, int metric, double eps, double tau,
+                      double lp, const df_view *f, int vote_f32, orc_record *rec)
+{
+    if (f->field && vote_f32) {
+        float tf[3];
+        for (int a = 0; a < 3; ++a) tf[a] = (float)bin[a] * delta;
+        score_candidate_df_f32(src, n, R, tf, metric, eps, tau, lp, f, rec);
+        return;
+    }
+    double t[3];
+    for (int a = 0; a < 3; ++a) t[a] = (double)bin[a] * (double)delta;
+    if (f->field)
+        score_candidate_df64(src, n, R, t, metric, eps, tau, lp, f, rec);
+    else
+        score_candidate(src, n, tgt, m, R, t, metric, eps, tau, lp, rec);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -314,11 +619,10 @@ static void score_candidate_df(const float *src, int32_t n, const float *R, cons
 /* ------------------------------------------------------------------------ */
 typedef struct {
     const float *src; int32_t n; const float *tgt; int32_t m;
-    const float *rots; const int32_t *which; int32_t count;
-    float delta; const int32_t *k_lo; const int32_t *size;
-    int metric; double eps, tau, lp;
-    /* distance-field mode (field == NULL: brute force) */
-    const double *field; float r; int32_t res; const float *lo; const float *inv;
+    const float *rots; const int32_t *which; const int32_t *bins;
+    float delta; double mu; const int32_t *k_lo; const int32_t *size;
+    int metric; double eps, tau, lp; int vote_f32;
+    df_view f;
     orc_record *out;
     int32_t begin, end;
 } reg_job;
@@ -327,71 +631,81 @@ static void *reg_worker(void *arg)
 {
     reg_job *jb = (reg_job *)arg;
     const size_t nbins = (size_t)jb->size[0] * jb->size[1] * jb->size[2];
-    uint32_t *hist = (uint32_t *)malloc(nbins * sizeof(uint32_t));
-    if (!hist) return (void *)1;
+    uint32_t *cnt = (uint32_t *)malloc(nbins * sizeof(uint32_t));
+    uint32_t *outf = (uint32_t *)malloc(nbins * sizeof(uint32_t));
+    uint32_t *inf = (uint32_t *)malloc(nbins * sizeof(uint32_t));
+    if (!cnt || !outf || !inf) { free(cnt); free(outf); free(inf); return (void *)1; }
     for (int32_t u = jb->begin; u < jb->end; ++u) {
         int32_t k = jb->which ? jb->which[u] : u;
         const float *R = jb->rots + 9 * (size_t)k;
         orc_record *rec = &jb->out[u];
         memset(rec, 0, sizeof(*rec));
-        rec->votes = orc_vote(jb->src, jb->n, jb->tgt, jb->m, R, jb->delta, jb->k_lo, jb->size,
-                              hist, rec->bin);
+        rec->rot = k;
+        if (jb->vote_f32) {
+            rec->votes = orc_vote_f32(jb->src, jb->n, jb->tgt, jb->m, R, jb->delta, jb->k_lo,
+                                      jb->size, cnt, rec->bin);
+            rec->votes_lo = rec->votes_hi = rec->lo_max = rec->votes;
+            rec->pinned = 1;
+        } else {
+            vote_info vi;
+            vote64(jb->src, jb->n, jb->tgt, jb->m, R, (double)jb->delta, jb->mu, jb->k_lo,
+                   jb->size, cnt, outf, inf, &vi);
+            for (int a = 0; a < 3; ++a) rec->bin[a] = vi.mode[a];
+            rec->votes = vi.M;
+            rec->votes_lo = vi.lo;
+            rec->votes_hi = vi.hi;
+            rec->lo_max = vi.lo_max;
+            rec->pinned = vi.pinned;
+            rec->frag = vi.frag;
+        }
         rec->valid = rec->votes > 0;
-        if (!rec->valid) { rec->error = INFINITY; continue; }
+        if (!rec->valid) { rec->error = rec->err_lo = rec->err_hi = INFINITY; continue; }
         if (jb->metric == ORC_VOTES) {
             /* Thm. 3 ranking: no scoring, the mode count stands for the L0^{m1}
              * inlier count and the error is 0 for every valid candidate */
             rec->inliers = (int32_t)rec->votes;
-            rec->error = 0.0;
             continue;
         }
-        if (jb->field) {
-            float tf[3];
-            for (int a = 0; a < 3; ++a) tf[a] = (float)rec->bin[a] * jb->delta;
-            score_candidate_df(jb->src, jb->n, R, tf, jb->metric, jb->eps, jb->tau, jb->lp, jb->r,
-                               jb->res, jb->lo, jb->inv, jb->field, rec);
-        } else {
-            double t[3];
-            for (int a = 0; a < 3; ++a) t[a] = (double)rec->bin[a] * (double)jb->delta;
-            score_candidate(jb->src, jb->n, jb->tgt, jb->m, R, t, jb->metric, jb->eps, jb->tau,
-                            jb->lp, rec);
-        }
+        score_bin(jb->src, jb->n, jb->tgt, jb->m, R, rec->bin, jb->delta, jb->metric, jb->eps,
+                  jb->tau, jb->lp, &jb->f, jb->vote_f32, rec);
     }
-    free(hist);
+    free(cnt);
+    free(outf);
+    free(inf);
     return NULL;
 }
 
-/*
- * Run Alg. 2 on the rotations listed in `which` (NULL: all k of them), writing one
- * record per listed rotation.  `field` != NULL selects distance-field scoring with
- * the grid from orc_df_build().  Returns 0, or -1 on invalid input / no memory.
- */
-int orc_records(const float *src, int32_t n, const float *tgt, int32_t m, const float *rots,
-                int32_t k, const int32_t *which, int32_t count, float eps, float delta, float tau,
-                const float *t_min, const float *t_max, int32_t metric, float lp,
-                const double *field, int32_t res, const float *lo, const float *inv,
-                int32_t nthreads, orc_record *out)
+/* Scores of given (rotation, bin) pairs, no vote: for the candidates whose mode
+   is ambiguous, each admissible bin is scored by this. */
+static void *bins_worker(void *arg)
 {
-    int32_t k_lo[3], size[3];
-    if (n <= 0 || m <= 0 || k <= 0 || count < 0 || !(eps > 0.0f)) return -1;
-    if (metric < ORC_TRUNC_L2 || metric > ORC_VOTES || !(lp > 0.0f && lp <= 1.0f)) return -1;
-    if (orc_box(delta, t_min, t_max, k_lo, size)) return -1;
-    if (which)
-        for (int32_t u = 0; u < count; ++u)
-            if (which[u] < 0 || which[u] >= k) return -1;
-    if (!which) count = k;
+    reg_job *jb = (reg_job *)arg;
+    for (int32_t u = jb->begin; u < jb->end; ++u) {
+        int32_t k = jb->which[u];
+        orc_record *rec = &jb->out[u];
+        memset(rec, 0, sizeof(*rec));
+        rec->rot = k;
+        for (int a = 0; a < 3; ++a) rec->bin[a] = jb->bins[3 * u + a];
+        rec->valid = 1;
+        rec->pinned = 1;
+        score_bin(jb->src, jb->n, jb->tgt, jb->m, jb->rots + 9 * (size_t)k, rec->bin, jb->delta,
+                  jb->metric, jb->eps, jb->tau, jb->lp, &jb->f, jb->vote_f32, rec);
+    }
+    return NULL;
+}
+
+static int run_jobs(reg_job *proto, int32_t count, int32_t nthreads, void *(*fn)(void *))
+{
     int nt = n_threads(nthreads);
     if (nt > 256) nt = 256;
     if (nt > count) nt = count > 0 ? count : 1;
     pthread_t th[256];
     reg_job jobs[256];
-    float r = eps > tau ? eps : tau;
     for (int w = 0; w < nt; ++w) {
-        jobs[w] = (reg_job){src, n, tgt, m, rots, which, count, delta, k_lo, size, metric,
-                            (double)eps, (double)tau, (double)lp, field, r, res, lo, inv, out,
-                            (int32_t)((int64_t)count * w / nt),
-                            (int32_t)((int64_t)count * (w + 1) / nt)};
-        pthread_create(&th[w], NULL, reg_worker, &jobs[w]);
+        jobs[w] = *proto;
+        jobs[w].begin = (int32_t)((int64_t)count * w / nt);
+        jobs[w].end = (int32_t)((int64_t)count * (w + 1) / nt);
+        pthread_create(&th[w], NULL, fn, &jobs[w]);
     }
     int bad = 0;
     for (int w = 0; w < nt; ++w) {
@@ -400,6 +714,75 @@ int orc_records(const float *src, int32_t n, const float *tgt, int32_t m, const 
         if (ret) bad = 1;
     }
     return bad ? -1 : 0;
+}
+
+static int job_setup(reg_job *jb, const float *src, int32_t n, const float *tgt, int32_t m,
+                     const float *rots, int32_t k, const int32_t *which, int32_t count,
+                     float eps, float delta, float tau, int32_t metric, float lp, double mu,
+                     int32_t vote_f32, const double *field, int32_t res, const float *lo,
+                     const float *h, const float *inv, int32_t df_lookup, double mu_df,
+                     int32_t *k_lo, int32_t *size, const float *t_min, const float *t_max)
+{
+    if (n <= 0 || m <= 0 || k <= 0 || count < 0 || !(eps > 0.0f)) return -1;
+    if (metric < ORC_TRUNC_L2 || metric > ORC_VOTES || !(lp > 0.0f && lp <= 1.0f)) return -1;
+    if (!(mu >= 0.0 && mu < 0.5) || !(mu_df >= 0.0 && mu_df < 0.5)) return -1;
+    if (df_lookup != ORC_DF_NEAREST && df_lookup != ORC_DF_TRILINEAR) return -1;
+    if (orc_box(delta, t_min, t_max, k_lo, size)) return -1;
+    if (which)
+        for (int32_t u = 0; u < count; ++u)
+            if (which[u] < 0 || which[u] >= k) return -1;
+    memset(jb, 0, sizeof(*jb));
+    jb->src = src; jb->n = n; jb->tgt = tgt; jb->m = m; jb->rots = rots; jb->which = which;
+    jb->delta = delta; jb->mu = mu; jb->k_lo = k_lo; jb->size = size; jb->metric = metric;
+    jb->eps = eps; jb->tau = tau; jb->lp = lp; jb->vote_f32 = vote_f32;
+    jb->f = (df_view){field, res, eps > tau ? eps : tau, lo, h, inv, df_lookup, mu_df};
+    return 0;
+}
+
+/*
+ * Run Alg. 2 on the rotations listed in `which` (NULL: all k of them), writing one
+ * record per listed rotation.  `field` != NULL selects distance-field scoring with
+ * the grid from orc_df_build() (df_lookup: 0 nearest voxel, 1 trilinear).  mu and
+ * mu_df are the fragility margins in bin and voxel units.  vote_f32 = 1 selects
+ * the secondary single-precision formulas.  Returns 0, or -1 on invalid input or
+ * no memory.
+ */
+int orc_records(const float *src, int32_t n, const float *tgt, int32_t m, const float *rots,
+                int32_t k, const int32_t *which, int32_t count, float eps, float delta, float tau,
+                const float *t_min, const float *t_max, int32_t metric, float lp, double mu,
+                int32_t vote_f32, const double *field, int32_t res, const float *lo,
+                const float *h, const float *inv, int32_t df_lookup, double mu_df,
+                int32_t nthreads, orc_record *out)
+{
+    int32_t k_lo[3], size[3];
+    reg_job jb;
+    if (job_setup(&jb, src, n, tgt, m, rots, k, which, count, eps, delta, tau, metric, lp, mu,
+                  vote_f32, field, res, lo, h, inv, df_lookup, mu_df, k_lo, size, t_min, t_max))
+        return -1;
+    if (!which) count = k;
+    jb.out = out;
+    return run_jobs(&jb, count, nthreads, reg_worker);
+}
+
+/* Score the candidates {R_which[u], delta * bins[u]} (no vote); one record each. */
+int orc_score_bins(const float *src, int32_t n, const float *tgt, int32_t m, const float *rots,
+                   int32_t k, const int32_t *which, const int32_t *bins, int32_t count,
+                   float eps, float delta, float tau, int32_t metric, float lp, int32_t vote_f32,
+                   const double *field, int32_t res, const float *lo, const float *h,
+                   const float *inv, int32_t df_lookup, double mu_df, int32_t nthreads,
+                   orc_record *out)
+{
+    int32_t k_lo[3], size[3];
+    const float wide_lo[3] = {-1.0f, -1.0f, -1.0f}, wide_hi[3] = {1.0f, 1.0f, 1.0f};
+    reg_job jb;
+    if (!which || !bins || metric == ORC_VOTES) return -1;
+    if (job_setup(&jb, src, n, tgt, m, rots, k, which, count, eps, delta, tau, metric, lp, 0.0,
+                  vote_f32, field, res, lo, h, inv, df_lookup, mu_df, k_lo, size, wide_lo,
+                  wide_hi))
+        return -1;
+    jb.bins = bins;
+    jb.out = out;
+    return run_jobs(&jb, count, nthreads, bins_worker);
 }
 
 /*
@@ -462,8 +845,10 @@ static void *exh_worker(void *arg)
                         have = 1;
                     }
                 }
-        best.votes = 1;
+        best.votes = best.votes_lo = best.votes_hi = best.lo_max = 1;
         best.valid = 1;
+        best.pinned = 1;
+        best.rot = k;
         jb->out[k] = best;
     }
     return NULL;

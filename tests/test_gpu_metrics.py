@@ -1,14 +1,19 @@
 """Metric variants: truncated Lp (p < 1) and the votes-only ranking of Thm. 3.
 
-Lp tolerance: the float32 query carries <= 6e-7 of distance error (see parity.py);
-rho = min(d, tau)^p amplifies it by p d^(p-1), <= 16 for d >= 1e-6 at p = 0.5, so a
-record's error may differ by 1e-5 |err| + 1e-5 N.  The votes ranking is integer:
-bit-exact."""
+Lp tolerance, derived per point from the oracle's distance d at the GPU's bin: a
+float32 query q = R x + t (|q| <= 3) and its distance carry at most
+DIST_ERR = 1e-6 of absolute error (a few ulp of each coordinate, sqrt(3) of them
+in a distance).  rho = min(d, tau)^p then moves by at most
+min(DIST_ERR^p, p a^(p-1) DIST_ERR), a = min(d, tau) - DIST_ERR (mean value theorem
+and the p-Hoelder bound of x^p), and not at all when d >= tau + DIST_ERR; a record's
+tolerance is the sum over its points plus 1e-5 |err| for the float32 sum and power.
+The votes ranking is integer: checked against the oracle's vote intervals."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2502_00115_amd import synth
+from parity import check_selection, compare_records
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -18,9 +23,28 @@ if not torch.cuda.is_available():
 
 from paper_2502_00115_amd import dses  # noqa: E402
 
+DIST_ERR = 1e-6
 
-def _lp_tol(err, n):
-    return 1e-5 * np.abs(err) + 1e-5 * n
+
+def _lp_tol(gpu, ref, lp, tau, df_values=None):
+    """Per-record tolerance of the truncated Lp error (module docstring)."""
+    ctx = ref.ctx
+    delta = float(np.float32(ctx["delta"]))
+    tau = float(np.float32(tau))
+    lp = float(np.float32(lp))
+    src = ctx["src"].astype(np.float64)
+    out = np.zeros(len(gpu))
+    for u in np.nonzero(gpu["votes"] > 0)[0]:
+        R = ctx["rots"][ref["rot"][u]].astype(np.float64).reshape(3, 3)
+        q = src @ R.T + gpu["bin"][u].astype(np.float64) * delta
+        d = df_values(q) if df_values else oracle.nn(q, ctx["tgt"])
+        a = np.minimum(d, tau) - DIST_ERR
+        with np.errstate(divide="ignore", invalid="ignore"):
+            slope = np.where(a > 0, lp * np.maximum(a, 1e-300) ** (lp - 1) * DIST_ERR, np.inf)
+        per = np.minimum(DIST_ERR ** lp, slope)
+        per[d >= tau + DIST_ERR] = 0.0
+        out[u] = per.sum() + 1e-5 * abs(float(gpu["error"][u]))
+    return out
 
 
 @pytest.mark.parametrize("lp", [0.5, 0.75])
@@ -32,18 +56,28 @@ def test_truncated_lp_matches_oracle(lp, scorer, seed):
     g = dses.register(p.src, p.tgt, p.rotations, p.eps, metric="trunc_lp", lp=lp, scorer=scorer,
                       records=True)
     orc = oracle.records(p.src, p.tgt, p.rotations, p.eps, metric="trunc_lp", p=lp)
-    v = orc["valid"].astype(bool)
-    np.testing.assert_array_equal(g.records["votes"], orc["votes"])
-    np.testing.assert_array_equal(g.records["bin"][v], orc["bin"][v])
-    dinl = np.abs(g.records["inliers"][v].astype(np.int64) - orc["inliers"][v])
-    assert np.all(dinl <= orc["boundary"][v])
-    eg, eo = g.records["error"][v].astype(np.float64), orc["error"][v]
-    bad = np.abs(eg - eo) > _lp_tol(eo, n)
-    assert not bad.any(), (eg[bad][:4], eo[bad][:4])
-    err = np.where(v, orc["error"], np.inf)
-    best = int(np.argmin(err))
-    admissible = np.nonzero(err <= err[best] + 2 * _lp_tol(err[best], n))[0]
-    assert g.rot_index in admissible
+    tol = _lp_tol(g.records, orc, lp, p.eps)
+    rep = compare_records(g.records, orc, n, metric="trunc_lp", tol=tol, label=f"lp {lp}")
+    check_selection(g, rep, p.eps, label=f"lp {lp}")
+    print(f"lp {lp} {scorer}: worst deviation / tolerance {rep['worst_err_over_tol']:.3f}")
+
+
+def test_truncated_lp_object_scale_sampled():
+    """Truncated Lp (p = 0.5) on the 717 x 1,024 x 36,864 registration: sampled
+    records and the GPU's best candidates against the oracle."""
+    p = synth.make_c2(1)
+    n = len(p.src)
+    g = dses.register(p.src, p.tgt, p.rotations, p.eps, metric="trunc_lp", lp=0.5, records=True)
+    recs = g.records
+    rng = np.random.default_rng(4)
+    top = np.argsort(np.where(recs["votes"] > 0, recs["error"], np.inf))[:16]
+    which = np.unique(np.concatenate([rng.choice(len(p.rotations), 160, replace=False), top]))
+    orc = oracle.records(p.src, p.tgt, p.rotations, p.eps, metric="trunc_lp", p=0.5,
+                         which=which)
+    tol = _lp_tol(recs[which], orc, 0.5, p.eps)
+    rep = compare_records(recs[which], orc, n, metric="trunc_lp", tol=tol, label="c2 lp")
+    check_selection(g, rep, p.eps, label="c2 lp")
+    print(f"c2 lp: worst deviation / tolerance {rep['worst_err_over_tol']:.3f}")
 
 
 def test_truncated_lp_distance_field_matches_oracle_field():
@@ -54,25 +88,35 @@ def test_truncated_lp_distance_field_matches_oracle_field():
                                records=True)
     df = oracle.df_build(p.tgt, p.eps, 64)
     orc = oracle.records(p.src, p.tgt, p.rotations, p.eps, metric="trunc_lp", p=0.5, df=df)
-    v = orc["valid"].astype(bool)
-    np.testing.assert_array_equal(g.records["votes"], orc["votes"])
-    eg, eo = g.records["error"][v].astype(np.float64), orc["error"][v]
-    assert np.all(np.abs(eg - eo) <= _lp_tol(eo, len(p.src)))
+    # the field's float32 values differ from the oracle's by <= 1e-6 as well; the
+    # voxel choice of a fragile point is covered by [err_lo, err_hi]
+    tol = _lp_tol(g.records, orc, 0.5, p.eps,
+                  df_values=lambda q: oracle.df_query(df, q, mu=orc.ctx["mu_df"])[0])
+    rep = compare_records(g.records, orc, len(p.src), metric="trunc_lp", tol=tol, label="df lp")
+    check_selection(g, rep, p.eps, label="df lp")
+
+
+def _own_order(rec, k):
+    valid = np.nonzero(rec["votes"] > 0)[0]
+    order = sorted(valid, key=lambda q: (-int(rec["votes"][q]), int(q)))
+    out = np.full(k, -1, np.int64)
+    out[:min(k, len(order))] = order[:k]
+    return out
 
 
 @pytest.mark.parametrize("seed", range(4))
-def test_votes_ranking_bit_exact(seed):
+def test_votes_ranking_matches_oracle(seed):
     p = synth.make_c1(seed)
     g = dses.register(p.src, p.tgt, p.rotations, p.eps, metric="votes", records=True, top_k=8)
     orc = oracle.records(p.src, p.tgt, p.rotations, p.eps, metric="votes")
-    np.testing.assert_array_equal(g.records["votes"], orc["votes"])
-    v = orc["valid"].astype(bool)
-    np.testing.assert_array_equal(g.records["bin"][v], orc["bin"][v])
-    np.testing.assert_array_equal(g.records["inliers"][v], orc["inliers"][v])
-    assert np.all(g.records["error"][v] == 0.0)
-    assert g.rot_index == oracle.select(orc)
-    assert g.votes == int(orc["votes"].max()) and g.inliers == g.votes and g.error == 0.0
-    np.testing.assert_array_equal(g.top["rot_index"], oracle.topk(orc, 8))
+    rep = compare_records(g.records, orc, len(p.src), metric="votes", label=f"votes {seed}")
+    check_selection(g, rep, p.eps, label=f"votes {seed}")
+    # the ranking is the largest count, lowest index first, over the GPU's own counts
+    assert g.rot_index == int(np.argmax(g.records["votes"]))
+    assert g.votes == int(g.records["votes"].max()) and g.inliers == g.votes and g.error == 0.0
+    np.testing.assert_array_equal(g.top["rot_index"], _own_order(g.records, 8))
+    if np.array_equal(g.records["votes"], orc["votes"]):
+        np.testing.assert_array_equal(g.top["rot_index"], oracle.topk(orc, 8))
 
 
 def test_votes_resident_and_rejections():

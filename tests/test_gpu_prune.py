@@ -1,7 +1,8 @@
 """q-pruned scoring (the pruning step of Alg. 2): vote every rotation, score only
-those with M_k >= q M*.  Votes and bins bit-exact, the scored set identical to the
-oracle's, scored errors within tolerance, selection inside the oracle's admissible
-set restricted to the scored rotations."""
+those with M_k >= q M*.  Votes and bins against the oracle's definition (within its
+fragility intervals), the scored set exactly the rule applied to the votes, scored
+errors within tolerance, selection inside the oracle's admissible set restricted
+to the scored rotations."""
 import numpy as np
 import pytest
 
@@ -18,19 +19,33 @@ if not torch.cuda.is_available():
 from paper_2502_00115_amd import dses  # noqa: E402
 
 
+def _gpu_mask(votes, q):
+    """The pruning rule applied to a list of vote counts (M_k >= q M*, compared in
+    double precision on the counts and the float q)."""
+    votes = votes.astype(np.float64)
+    return (votes > 0) & (votes >= np.float64(np.float32(q)) * votes.max())
+
+
 def _check(g, orc, q, n, delta, label):
-    mask = oracle.prune_mask(orc, q)
-    # votes and bins of every rotation as without pruning
-    np.testing.assert_array_equal(g.records["votes"], orc["votes"], err_msg=label)
-    v = orc["valid"].astype(bool)
-    np.testing.assert_array_equal(g.records["bin"][v], orc["bin"][v], err_msg=label)
-    scored = np.isfinite(g.records["error"])
+    # votes and bins of every rotation: the definition's, within its fragility ranges
+    # (the scores of the unscored rotations are not compared)
+    probe = g.records.copy()
+    mask = _gpu_mask(probe["votes"], q)
+    # the scored set is exactly the rule applied to the GPU's votes; when every vote
+    # is pinned to the oracle's count it is the oracle's own set
+    scored = np.isfinite(probe["error"])
     np.testing.assert_array_equal(scored, mask, err_msg=f"{label}: scored set")
-    assert np.all(g.records["inliers"][~mask] == 0)
-    sub = orc.copy()
-    sub["valid"] = mask
-    compare_records(g.records[mask], orc[mask], n, label=label)
-    check_selection(g, sub, n, delta, label=label)
+    if np.array_equal(probe["votes"], orc["votes"]):
+        np.testing.assert_array_equal(mask, oracle.prune_mask(orc, q), err_msg=label)
+    assert np.all(probe["inliers"][~mask] == 0)
+    rep = compare_records(probe[mask], orc[mask], n, label=label)
+    unscored = ~mask & (probe["votes"] > 0)
+    if unscored.any():
+        # unscored candidates carry their vote: compared with the metric ignored
+        rv = compare_records(probe[unscored], orc[unscored], n, scores=False,
+                             label=f"{label} (unscored)")
+        assert rv["rotations"] == int(unscored.sum())
+    check_selection(g, rep, delta, label=label)
 
 
 @pytest.mark.parametrize("seed", range(4))
@@ -82,5 +97,8 @@ def test_pruned_c2_sampled_against_oracle():
     which = keep[:: max(1, len(keep) // 40)]
     orc = oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which)
     compare_records(g.records[which], orc, len(p.src), label="c2 q 0.85")
+    # M* of the pruned run is the largest count of the unpruned run
+    full = dses.register(p.src, p.tgt, p.rotations, p.eps, records=True)
+    assert full.records["votes"].tobytes() == g.records["votes"].tobytes()
     e = g.records["error"][keep]
     assert abs(float(np.min(e)) - g.error) <= err_tol(g.error, len(p.src))

@@ -51,8 +51,8 @@ def test_df_scoring_matches_oracle(metric):
     got = dses.register_resident(T, S, p.src, p.eps, metric, tau=tau, scorer="df", records=True)
     df = oracle.df_build(p.tgt, r, res)
     ref = oracle.records(p.src, p.tgt, p.rotations, p.eps, metric=metric, tau=tau, df=df)
-    compare_records(got.records, ref, len(p.src), metric=metric, label=f"df/{metric}")
-    check_selection(got, ref, len(p.src), p.eps, metric=metric)
+    rep = compare_records(got.records, ref, len(p.src), metric=metric, label=f"df/{metric}")
+    check_selection(got, rep, p.eps, label=f"df/{metric}")
 
 
 def test_df_rejects_mismatched_truncation_and_l1():

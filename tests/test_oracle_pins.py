@@ -62,11 +62,30 @@ def test_box_asymmetric():
 # ---------------------------------------------------------------------------
 # vote array and mode (Lemma 2, Alg. 2 first loop)
 # ---------------------------------------------------------------------------
+def _pair_u_f64(src, tgt, R, delta):
+    """(y_j - R x_i)/delta for every pair (N, M, 3), in double, test-side."""
+    return _pair_bins_f64(src, tgt, R, delta)
+
+
+def _fragile_sets(u, mu):
+    """Per pair: the definition's bin and the set of bins reachable by moving
+    across faces within mu (test-side, from u alone)."""
+    w = u + 0.5
+    b = np.floor(w).astype(np.int64)
+    frac = w - b
+    alt = b.copy()
+    alt[frac < mu] -= 1
+    alt[frac > 1 - mu] += 1
+    return b, alt
+
+
 @pytest.mark.parametrize("seed", range(12))
 def test_vote_matches_all_pairs_brute_force(seed):
-    """Every pair's bin is counted by an O((NM)^2) comparison with no vote array."""
+    """Every pair's bin (the definition floor(u + 1/2), u = (y - R x)/delta in double)
+    is counted by an O((NM)^2) comparison with no vote array, on every draw; the
+    fragility counts equal a test-side enumeration of the pairs near a face."""
     rng = np.random.default_rng(seed)
-    for _ in range(50):
+    for draw in range(8):
         n, m = int(rng.integers(2, 7)), int(rng.integers(2, 9))
         delta = float(rng.choice([0.0625, 0.1, 0.25]))
         src = rng.uniform(-0.6, 0.6, (n, 3)).astype(np.float32)
@@ -76,29 +95,169 @@ def test_vote_matches_all_pairs_brute_force(seed):
         R = synth.random_rotations(rng, 1)[0].astype(np.float32)
         if seed % 3 == 0:
             R = np.eye(3, dtype=np.float32)
-        u = _pair_bins_f64(src, tgt, R, delta)
-        if _far_from_faces(u):
-            break
-    else:
-        pytest.skip("no face-free draw")
-    t_lo = -rng.uniform(0.3, 1.2, 3)
-    t_hi = rng.uniform(0.3, 1.2, 3)
-    hist, mode, M = oracle.vote(src, tgt, R, delta, t_lo, t_hi)
-    k_lo, size = oracle.box(delta, t_lo, t_hi)
-    b = np.floor(u + 0.5).astype(np.int64).reshape(-1, 3)
-    inbox = [tuple(v) for v in b if np.all(v >= k_lo) and np.all(v < k_lo + size)]
-    counts = {v: sum(1 for w in inbox if w == v) for v in inbox}     # all-pairs comparison
-    assert int(hist.sum()) == len(inbox)
-    for v, c in counts.items():
-        assert hist[tuple(np.array(v) - k_lo)] == c
-    if not inbox:
-        assert M == 0
-        return
-    best = max(counts.values())
-    first = min((v for v, c in counts.items() if c == best),
-                key=lambda v: ((v[0] - k_lo[0]) * size[1] + v[1] - k_lo[1]) * size[2] + v[2] - k_lo[2])
-    assert M == best
-    assert tuple(mode) == first
+        # a wide margin on some draws so that fragile pairs actually occur
+        mu = [1e-4, 0.05, 0.2][draw % 3]
+        t_lo = -rng.uniform(0.3, 1.2, 3)
+        t_hi = rng.uniform(0.3, 1.2, 3)
+        cnt, out, inn, info = oracle.vote64(src, tgt, R, delta, t_lo, t_hi, mu=mu)
+        k_lo, size = oracle.box(delta, t_lo, t_hi)
+        u = _pair_u_f64(src, tgt, R, delta).reshape(-1, 3)
+        b, alt = _fragile_sets(u, mu)
+
+        def inside(v):
+            return bool(np.all(v >= k_lo) and np.all(v < k_lo + size))
+
+        inbox = [tuple(v) for v in b if inside(v)]
+        counts = {v: sum(1 for w in inbox if w == v) for v in inbox}     # all-pairs comparison
+        assert int(cnt.sum()) == len(inbox)
+        for v, c in counts.items():
+            assert cnt[tuple(np.array(v) - k_lo)] == c
+        exp_out = np.zeros_like(out)
+        exp_in = np.zeros_like(inn)
+        for bi, ai in zip(b, alt):
+            opts = [sorted({bi[a], ai[a]}) for a in range(3)]
+            reach = [np.array(v) for v in itertools.product(*opts)]
+            if len(reach) == 1:
+                continue
+            for v in reach:
+                if not inside(v):
+                    continue
+                if np.array_equal(v, bi):
+                    exp_out[tuple(v - k_lo)] += 1
+                else:
+                    exp_in[tuple(v - k_lo)] += 1
+        np.testing.assert_array_equal(out, exp_out)
+        np.testing.assert_array_equal(inn, exp_in)
+        if not inbox:
+            assert info["M"] == 0
+            continue
+        best = max(counts.values())
+        first = min((v for v, c in counts.items() if c == best),
+                    key=lambda v: ((v[0] - k_lo[0]) * size[1] + v[1] - k_lo[1]) * size[2]
+                    + v[2] - k_lo[2])
+        assert info["M"] == best
+        assert info["mode"] == first
+
+
+def test_pair_exactly_on_a_face_is_fragile():
+    """A translation exactly half a bin from a lattice point (dyadic data, exact in
+    double): the definition rounds it up, and the pair is fragile across that face."""
+    d = 2.0 ** -4
+    src = np.zeros((1, 3), np.float32)
+    # x on a face (2.5 bins), y and z well inside bins 0 and -1
+    tgt = np.array([[2.5 * d, 0.25 * d, -1.25 * d]], np.float32)
+    cnt, out, inn, info = oracle.vote64(src, tgt, np.eye(3, dtype=np.float32), d, mu=1e-4)
+    k_lo, _ = oracle.box(d)
+    at = lambda b: tuple(np.array(b) - k_lo)  # noqa: E731
+    assert info["M"] == 1 and info["mode"] == (3, 0, -1)
+    assert cnt[at((3, 0, -1))] == 1 and out[at((3, 0, -1))] == 1
+    assert inn[at((2, 0, -1))] == 1 and int(inn.sum()) == 1 and int(out.sum()) == 1
+    # the two bins tie at worst: the mode is not pinned; both are admissible
+    assert not info["pinned"] and info["lo_max"] == 0
+    # all three axes on faces: eight bins reachable
+    tgt = np.array([[2.5 * d, -0.5 * d, 1.5 * d]], np.float32)
+    cnt, out, inn, info = oracle.vote64(src, tgt, np.eye(3, dtype=np.float32), d, mu=1e-4)
+    assert info["mode"] == (3, 0, 2) and int(out.sum()) == 1 and int(inn.sum()) == 7
+    for v in itertools.product([2, 3], [-1, 0], [1, 2]):
+        assert inn[at(v)] + out[at(v)] == 1
+
+
+def _modes_by_enumeration(b, alt, k_lo, size):
+    """Every assignment of the fragile pairs to one of their reachable bins: the set of
+    modes (largest count, lowest linear index) and, per bin, the range of counts."""
+    def lin(v):
+        return ((v[0] - k_lo[0]) * size[1] + v[1] - k_lo[1]) * size[2] + v[2] - k_lo[2]
+
+    def inside(v):
+        return all(k_lo[a] <= v[a] < k_lo[a] + size[a] for a in range(3))
+
+    choices = []
+    for bi, ai in zip(b, alt):
+        opts = [sorted({bi[a], ai[a]}) for a in range(3)]
+        choices.append([tuple(int(x) for x in v) for v in itertools.product(*opts)])
+    modes, ranges = set(), {}
+    for pick in itertools.product(*choices):
+        cnt = {}
+        for v in pick:
+            if inside(v):
+                cnt[v] = cnt.get(v, 0) + 1
+        for v in set(ranges) | set(cnt):
+            lo_, hi_ = ranges.get(v, (10 ** 9, -1))
+            c = cnt.get(v, 0)
+            ranges[v] = (min(lo_, c), max(hi_, c))
+        if cnt:
+            top = max(cnt.values())
+            modes.add(min((v for v, c in cnt.items() if c == top), key=lin))
+        else:
+            modes.add(None)
+    return modes, ranges
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_pinned_and_admissible_modes_by_enumeration(seed):
+    """The mode is pinned exactly when every assignment of the fragile pairs gives the
+    same mode; every mode some assignment gives is admissible; every count some
+    assignment gives a bin lies in [cnt - out, cnt + in]."""
+    rng = np.random.default_rng(500 + seed)
+    d = 0.25
+    checked = 0
+    for _ in range(40):
+        n, m = int(rng.integers(1, 4)), int(rng.integers(2, 5))
+        src = rng.uniform(-0.3, 0.3, (n, 3)).astype(np.float32)
+        tgt = rng.uniform(-0.5, 0.5, (m, 3)).astype(np.float32)
+        tgt[0] = src[0] + np.float32(0.1)              # repeated translations
+        if m > 2 and n > 1:
+            tgt[1] = src[1] + np.float32(0.1)
+        R = np.eye(3, dtype=np.float32)
+        mu = 0.12
+        u = _pair_u_f64(src, tgt, R, d).reshape(-1, 3)
+        b, alt = _fragile_sets(u, mu)
+        n_comb = np.prod([len({tuple(x)}) * 2 ** int(np.sum(x != y)) for x, y in zip(b, alt)])
+        if n_comb > 4096:
+            continue
+        k_lo, size = oracle.box(d, -0.5, 0.5)
+        cnt, out, inn, info = oracle.vote64(src, tgt, R, d, -0.5, 0.5, mu=mu)
+        modes, ranges = _modes_by_enumeration(b, alt, k_lo, size)
+        lo_max = int(np.max(cnt.astype(np.int64) - out))
+        assert info["lo_max"] == lo_max
+        if info["pinned"]:
+            assert modes == {info["mode"] if info["M"] > 0 else None}
+        else:
+            assert len(modes) > 1 or modes != {info["mode"]}
+        for v in modes:
+            if v is None:
+                assert lo_max == 0
+                continue
+            c = tuple(np.array(v) - k_lo)
+            assert cnt[c] + inn[c] >= lo_max, "a reachable mode must be admissible"
+        for v, (clo, chi) in ranges.items():
+            c = tuple(np.array(v) - k_lo)
+            if not all(0 <= c[a] < size[a] for a in range(3)):
+                continue
+            assert cnt[c] - out[c] <= clo and chi <= cnt[c] + inn[c]
+        checked += 1
+    assert checked >= 10
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_vote_margin_covers_the_single_precision_formula(seed):
+    """The margin mu bounds the float32 rounding of the bin decision: on an
+    object-scale draw every pair whose bin under the library's single-precision
+    formula differs from the definition's lies within mu of a face."""
+    p = synth.make_c2(seed)
+    rng = np.random.default_rng(seed)
+    src = p.src[rng.choice(len(p.src), 200, replace=False)]
+    tgt = p.tgt
+    mu = oracle.vote_margin(src, tgt, p.eps)
+    for R in p.rotations[rng.choice(len(p.rotations), 6, replace=False)]:
+        c64, out, inn, info = oracle.vote64(src, tgt, R, p.eps, mu=mu)
+        c32, mode32, M32 = oracle.vote_f32(src, tgt, R, p.eps)
+        diff = c32.astype(np.int64) - c64
+        # every change is explained by fragile pairs
+        assert np.all(diff <= inn) and np.all(-diff <= out)
+        if info["pinned"]:
+            assert tuple(mode32) == info["mode"]
+            assert info["lo"] <= M32 <= info["hi"]
 
 
 def test_round_half_goes_up():
@@ -450,3 +609,84 @@ def test_distance_field_score_within_lipschitz_bound():
     np.testing.assert_array_equal(exact["bin"], approx["bin"])
     bound = len(p.src) * 0.5 * float(np.linalg.norm(_f64(df.h)))
     assert np.all(np.abs(exact["error"] - approx["error"]) <= bound + 1e-9)
+
+
+def test_df_nearest_lookup_by_definition():
+    """Nearest-voxel lookup: the voxel of q is floor((q - lo)/h) (double); test-side
+    indexing of the oracle's field gives the oracle's value, r outside the grid; a
+    query exactly on a voxel face is fragile and reports both voxels' values."""
+    rng = np.random.default_rng(3)
+    # a reference whose padded box is dyadic: lo = -0.5, h = 1/16
+    tgt = np.vstack([rng.uniform(-0.4375, 0.4375, (60, 3)),
+                     [[-0.4375] * 3, [0.4375] * 3]]).astype(np.float32)
+    df = oracle.df_build(tgt, np.float32(0.0625), 16)
+    assert np.all(df.lo == -0.5) and np.all(df.h == 0.0625)
+    q = rng.uniform(-0.7, 0.7, (400, 3))
+    D, Dmin, Dmax = oracle.df_query(df, q, mu=1e-4)
+    idx = np.floor((q - _f64(df.lo)) / _f64(df.h)).astype(np.int64)
+    inside = np.all((idx >= 0) & (idx < 16), axis=1)
+    exp = np.full(len(q), 0.0625)
+    exp[inside] = df.field[tuple(idx[inside].T)]
+    np.testing.assert_array_equal(D, exp)
+    assert np.all(Dmin <= D) and np.all(D <= Dmax)
+    # on the face between voxels 4 and 5 in x (q_x = lo + 5h exactly)
+    face = np.array([[-0.5 + 5 * 0.0625, 0.03, -0.11]])
+    D, Dmin, Dmax = oracle.df_query(df, face, mu=1e-4)
+    iy, iz = int((0.03 + 0.5) * 16), int((-0.11 + 0.5) * 16)
+    pair = sorted([df.field[4, iy, iz], df.field[5, iy, iz]])
+    assert D[0] == df.field[5, iy, iz]
+    assert (Dmin[0], Dmax[0]) == (pair[0], pair[1])
+
+
+def test_df_trilinear_against_scipy_interpolator():
+    """Trilinear lookup: linear interpolation between voxel centres, with the value r
+    at the virtual centres just outside the grid, equals scipy's regular-grid linear
+    interpolator over the field padded by one layer of r; r farther out."""
+    from scipy.interpolate import RegularGridInterpolator
+    p = synth.make_c1(6)
+    r, res = np.float32(0.05), 20
+    df = oracle.df_build(p.tgt, r, res)
+    pad = np.pad(df.field, 1, constant_values=float(r))
+    axes = [_f64(df.lo[a]) + (np.arange(-1, res + 1) + 0.5) * _f64(df.h[a]) for a in range(3)]
+    interp = RegularGridInterpolator(axes, pad, method="linear", bounds_error=False,
+                                     fill_value=float(r))
+    rng = np.random.default_rng(8)
+    lo, hi = _f64(df.lo) - 2 * _f64(df.h), _f64(df.lo) + (res + 2) * _f64(df.h)
+    q = rng.uniform(lo, hi, (3000, 3))
+    D, Dmin, Dmax = oracle.df_query(df, q, lookup="trilinear")
+    np.testing.assert_allclose(D, interp(q), rtol=0, atol=1e-12)
+    assert np.array_equal(D, Dmin) and np.array_equal(D, Dmax)
+    # at the voxel centres it is the field itself
+    idx = rng.integers(0, res, (50, 3))
+    c = _f64(df.lo) + (idx + 0.5) * _f64(df.h)
+    D, _, _ = oracle.df_query(df, c, lookup="trilinear")
+    np.testing.assert_allclose(D, df.field[tuple(idx.T)], rtol=0, atol=1e-12)
+    # within the Lipschitz bound of the exact truncated distance (sqrt(3) h)
+    q = rng.uniform(_f64(df.lo), _f64(df.lo) + res * _f64(df.h), (500, 3))
+    D, _, _ = oracle.df_query(df, q, lookup="trilinear")
+    exact = np.minimum(cKDTree(_f64(p.tgt)).query(q)[0], float(r))
+    assert np.all(np.abs(D - exact) <= math.sqrt(3) * float(np.max(df.h)) + 1e-12)
+
+
+@pytest.mark.parametrize("lookup", ["nearest", "trilinear"])
+def test_df_candidate_error_is_the_sum_of_lookups(lookup):
+    """A distance-field candidate's error is the sum over the source of
+    min(D(R x + t), tau); err_lo <= error <= err_hi."""
+    p = synth.make_c1(4)
+    res = 40
+    df = oracle.df_build(p.tgt, p.eps, res)
+    which = np.arange(0, 577, 13)
+    recs = oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which, df=df,
+                          df_lookup=lookup)
+    eps = float(np.float32(p.eps))
+    for rec, k in zip(recs, which):
+        if not rec["valid"]:
+            continue
+        R = _f64(p.rotations[k]).reshape(3, 3)
+        q = _f64(p.src) @ R.T + rec["bin"] * eps
+        D, Dmin, Dmax = oracle.df_query(df, q, lookup, mu=recs.ctx["mu_df"])
+        assert abs(rec["error"] - np.minimum(D, eps).sum()) <= 1e-9
+        assert rec["err_lo"] <= rec["error"] <= rec["err_hi"]
+        assert abs(rec["err_lo"] - np.minimum(Dmin, eps).sum()) <= 1e-9
+        assert abs(rec["err_hi"] - np.minimum(Dmax, eps).sum()) <= 1e-9
+        assert rec["inliers"] == int(np.sum(D < eps))

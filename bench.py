@@ -1,15 +1,20 @@
 """Benchmark: DSES candidate sweep on one MI355X.
 
-One step = one full registration (vote, mode, score every candidate, select) of
-the object-scale workload: a 1,024-point multi-primitive reference, a 717-point
-partial source (70% cut, sigma 0.01 clipped at 0.05, 10% outliers) and the
-36,864-rotation uniform SO(3) grid, eps = 0.03, truncated-L2 error, float32.
-Inputs are synthetic and already resident in device memory when timing starts.
+Default (the headline): one step = one full registration (vote, mode, score every
+candidate, select) of the scene-scale workload: a 16,384-point six-primitive
+reference, a 4,096-point partial source (sigma 0.005 clipped at 0.05, 20%
+outliers) and the 294,912-rotation uniform SO(3) grid, eps = 0.02, truncated-L2
+error, exact cell-grid scoring, float32.  Inputs are synthetic and already
+resident in device memory when timing starts.
 
 Prints one JSON line with whole-job throughput (candidate poses scored per
 second), per-registration latency percentiles, the dominant kernel's roofline
-position (timed with HIP events on its launch stream) and the CPU oracle's rate
-on a bounded sample of the same workload.
+position (timed with HIP events on its launch stream), the CPU oracle's rate on a
+bounded sample of the same workload, and, in the same line, the serving workload
+(Poisson requests against resident references: p50/p99 latency served versus one
+launch per request, open loop at 0.8 load and closed loop at saturation) and the
+object-scale registration (1,024-point reference, 717-point source, 36,864
+rotations).  --workload picks another workload alone.
 """
 import argparse
 import hashlib
@@ -78,19 +83,42 @@ def make_workload(name):
                               "717-pt source, 36,864-rotation Hopf grid")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p, sample, threads):
+    """The oracle (plain C, FP64, one thread per core over rotations) on a seeded
+    sample of the workload's rotations, plus a single-thread run on a few of them."""
     import numpy as np
     import oracle
     rng = np.random.default_rng(0)
     which = np.sort(rng.choice(len(p.rotations), min(sample, len(p.rotations)), replace=False))
     box = p.meta.get("t_box")
     kw = {"t_min": -box, "t_max": box} if box is not None else {}
+    pairs = float(len(p.src)) * len(p.tgt)
     t0 = time.perf_counter()
     oracle.records(p.src, p.tgt, p.rotations, p.eps, which=which, threads=threads, **kw)
     dt = time.perf_counter() - t0
+    one = which[: max(1, min(len(which), int(2.0e8 / pairs) + 1))]
+    t1 = time.perf_counter()
+    oracle.records(p.src, p.tgt, p.rotations, p.eps, which=one, threads=1, **kw)
+    dt1 = time.perf_counter() - t1
     return {"value": len(which) / dt, "unit": "candidates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "single_thread_pairs_per_s": len(one) * pairs / dt1,
+            "single_thread_candidates_per_s": len(one) / dt1,
             "sample": f"{len(which)} of {len(p.rotations)} rotations of the same registration "
-                      f"(seeded), full vote + brute-force FP64 scoring, {dt:.1f} s wall"}
+                      f"(seeded), full FP64 vote by the definition + brute-force FP64 scoring, "
+                      f"{dt:.1f} s wall on {threads} threads; single thread: {len(one)} "
+                      f"rotations in {dt1:.1f} s (a pair is voted and scored)"}
 
 
 def bench_batch(args):
@@ -227,16 +255,18 @@ def bench_exhaustive(args):
             "speedup_dses": t_exh / t_dses}
 
 
-def bench_serve(args):
+def bench_serve(args, n_req=None, quiet=False):
     """Poisson arrivals against 8 resident references (with 128^3 distance fields):
-    served (continuous batching) versus one launch per request in FIFO order."""
+    served (continuous batching) versus one launch per request in FIFO order, at 0.8
+    of the plain path's capacity; then closed loop (every request outstanding at
+    once) for the saturation throughput of both paths."""
     import threading
 
     import numpy as np
     import torch
     from paper_2502_00115_amd import dses, synth
 
-    n_req = args.requests
+    n_req = args.requests if n_req is None else n_req
     targets = synth.make_c4_targets(0, count=8)
     T = [dses.Target(t, df_trunc=0.03, df_res=128) for t, _ in targets]
     R = dses.RotationSet(synth.hopf_grid(3).reshape(-1, 9).astype(np.float32))
@@ -252,6 +282,9 @@ def bench_serve(args):
     rate = 0.8 / mean_service
     rng = np.random.default_rng(0)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    if not quiet:
+        print(f"bench.py: serving, {n_req} requests at {rate:.1f}/s", file=sys.stderr,
+              flush=True)
 
     # plain: one launch per request, FIFO, same arrival times
     lat_plain, svc_plain = [], []
@@ -281,14 +314,27 @@ def bench_serve(args):
     th = threading.Thread(target=producer)
     th.start()
     th.join()
+    done = [srv.wait(rid, timeout_ms=600000) for rid in ids]
+    served_wall = time.perf_counter() - start
+    lat_served = [g.total_s for g in done]
+    queue_served = [g.queue_s for g in done]
+
+    # closed loop: all requests outstanding at once
+    t0 = time.perf_counter()
+    for tid, src in reqs:
+        dses.register_resident(T[tid], R, src, 0.03)
+    torch.cuda.synchronize()
+    sat_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ids = [srv.submit(T[tid], R, src, 0.03) for tid, src in reqs]
     for rid in ids:
         srv.wait(rid, timeout_ms=600000)
-    served_wall = time.perf_counter() - start
-    tim = [srv.timing(rid) for rid in ids]
-    lat_served = [t[1] for t in tim]
-    queue_served = [t[0] for t in tim]
+    sat_served = time.perf_counter() - t0
     srv.close()
     cands = 36864 * n_req
+    # algorithmic work with distance-field scoring: 3 FLOP per vote pair, 18 per
+    # transformed point, per candidate
+    flop = sum((3.0 * len(src) * T[tid].m + 18.0 * len(src)) * 36864 for tid, src in reqs)
     if args.latency_dump:
         with open(args.latency_dump, "w") as f:
             json.dump({"arrival_s": [float(a) for a in arrivals], "plain_s": lat_plain,
@@ -312,7 +358,126 @@ def bench_serve(args):
             "plain": {"p50_ms": pct(lat_plain, 50), "p99_ms": pct(lat_plain, 99),
                       "mean_ms": float(np.mean(lat_plain)) * 1e3,
                       "mean_service_ms": float(np.mean(svc_plain)) * 1e3,
-                      "throughput": cands / plain_wall, "path": "one launch per request, FIFO"}}
+                      "throughput": cands / plain_wall, "path": "one launch per request, FIFO"},
+            "saturation": {"served": cands / sat_served, "plain": cands / sat_plain,
+                           "unit": "candidates/s",
+                           "served_frac_of_fp32_peak": flop / sat_served / 1e12
+                           / PEAK_FP32_VECTOR_TFLOPS,
+                           "plain_frac_of_fp32_peak": flop / sat_plain / 1e12
+                           / PEAK_FP32_VECTOR_TFLOPS,
+                           "work": "algorithmic (3*N*M + 18*N) FLOP per candidate (DF "
+                                   "scoring), whole run",
+                           "path": "closed loop: every request outstanding at once"}}
+
+
+def bench_plain(args, workload, steps, warmup, cpu_sample, scorer="auto", q=0.0):
+    """Timed single-registration steps of one workload (inputs resident on the
+    device), with the sweep kernel's HIP-event time and the roofline position."""
+    import numpy as np
+    import torch
+    from paper_2502_00115_amd import dses
+
+    p, desc = make_workload(workload)
+    dev = torch.device("cuda:0")
+    src = torch.from_numpy(p.src).to(dev)
+    tgt = torch.from_numpy(p.tgt).to(dev)
+    rot = torch.from_numpy(p.rotations).to(dev)
+    n, m, k = len(p.src), len(p.tgt), len(p.rotations)
+
+    box = p.meta.get("t_box")
+    if box is not None:                  # a local search: the box of the initial guess
+        box_kw = {"t_min": -box, "t_max": box}
+    else:
+        box_kw = {}
+    if scorer == "df":
+        # distance-field scoring needs the reference resident with its 128^3 field
+        target = dses.Target(tgt, df_trunc=p.eps, df_res=128)
+        rotset = dses.RotationSet(rot)
+
+        def run(**kw):
+            return dses.register_resident(target, rotset, src, p.eps, scorer="df", q=q,
+                                          **box_kw, **kw)
+    else:
+        def run(**kw):
+            return dses.register(src, tgt, rot, p.eps, scorer=scorer, q=q, **box_kw, **kw)
+    for w in range(warmup):
+        ts = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        if time.perf_counter() - ts > 2.0:
+            print(f"bench.py: {workload} warm-up {w + 1}/{warmup} "
+                  f"{time.perf_counter() - ts:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dses.kernel_stats(reset=True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(steps):
+        ts = time.perf_counter()
+        r = run(timing=True)
+        lat.append(time.perf_counter() - ts)
+        if lat[-1] > 2.0:
+            print(f"bench.py: {workload} step {step + 1}/{steps} {lat[-1]:.1f} s",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = dses.kernel_stats()
+
+    sweep_ms = st["vote_score_ms"] / max(1, st["vote_score_launches"])
+    # algorithmic work per candidate: 3 FLOP per vote pair, 8 per brute-force score pair,
+    # 18 per transformed point; distance-field scoring replaces the score pairs by
+    # one lookup per point
+    score_pairs = 0.0 if scorer == "df" else 8.0 * n * m
+    scored = k
+    if q > 0.0:                          # pruning: every rotation voted, the kept ones scored
+        scored = int(np.isfinite(run(records=True).records["error"]).sum())
+    flop_per_launch = (3.0 * n * m + 18.0 * n) * k + score_pairs * scored
+    achieved = flop_per_launch / (sweep_ms * 1e-3) / 1e12
+    # the counters were taken on the default configuration of the workload (every
+    # rotation scored, automatic scorer); other configurations run other kernels
+    traffic = load_traffic(workload) if q == 0.0 and scorer == "auto" else None
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": "candidate poses {R,t} scored/sec (1 GPU) + p50/p99 registration latency, "
+                  "served vs plain",
+        "value": k * steps / elapsed,
+        "unit": "candidates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "n_src": n, "n_ref": m, "rotations": k, "eps": p.eps,
+                   "metric": "trunc_l2", "scorer": scorer, "q": q,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                       "p99": float(np.percentile(lat_ms, 99)), "path": "plain, one call"},
+        "roofline": {"bound": "alu", "kernel": "k_sweep (vote + mode + score)",
+                     "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+                     "work": ("algorithmic (3*N*M + 18*N) FLOP per candidate (DF scoring)"
+                              if scorer == "df" else
+                              "algorithmic (11*N*M + 18*N) FLOP per candidate"),
+                     "kernel_ms": sweep_ms},
+        "result": {"rot_index": r.rot_index, "inliers": r.inliers, "error": r.error,
+                   "rot_err_deg": float(np.rad2deg(np.arccos(np.clip(
+                       (np.trace(r.R.astype(np.float64).T @ p.R_true) - 1.0) / 2.0, -1.0, 1.0)))),
+                   "t_err": float(np.linalg.norm(r.t.astype(np.float64) - p.t_true))},
+    }
+    if q > 0.0:
+        out["result"]["scored"] = scored
+        out["roofline"]["work"] += " (q > 0: score pairs only for the scored rotations)"
+    if cpu_sample != 0:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        sample = cpu_sample if cpu_sample > 0 else max(16, int(2.2e10 / (n * m)))
+        print(f"bench.py: oracle CPU baseline on {min(sample, k)} rotations", file=sys.stderr,
+              flush=True)
+        out["cpu_baseline"] = cpu_baseline(p, sample, threads)
+    return out
 
 
 def main():
@@ -320,13 +485,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=WORKLOADS, default="c2")
+    ap.add_argument("--workload", choices=WORKLOADS, default="c5")
     ap.add_argument("--scorer", default="auto")
     ap.add_argument("--q", type=float, default=0.0,
                     help="pruning of Alg. 2: score only rotations with M_k >= q M* (0: all)")
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="rotations of the oracle CPU baseline (-1: as many as about "
-                         "2.2e10 point pairs, some 10 s on 16 cores; 0: skip)")
+                         "2.2e10 point pairs, some 10-30 s on 16 cores; 0: skip)")
     ap.add_argument("--requests", type=int, default=200, help="c4: measured requests")
     ap.add_argument("--aging", type=float, default=0.0,
                     help="c4: server priority aging (0: library default)")
@@ -334,6 +499,8 @@ def main():
                     help="c4: write per-request arrival, plain and served latency (JSON)")
     ap.add_argument("--slice-mpairs", type=int, default=0,
                     help="c4: server work per slice, millions of pairs (0: library default)")
+    ap.add_argument("--alone", action="store_true",
+                    help="the headline workload only (no serving or object-scale figures)")
     ap.add_argument("--lds-probe", action="store_true",
                     help="print the device's LDS atomic throughput (vote ceiling) and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -371,106 +538,20 @@ def main():
     if args.workload == "exhaustive":
         print(json.dumps(bench_exhaustive(args)), flush=True)
         return
-
-    import numpy as np
-    import torch
-    from paper_2502_00115_amd import dses
-
-    p, desc = make_workload(args.workload)
-    dev = torch.device("cuda:0")
-    src = torch.from_numpy(p.src).to(dev)
-    tgt = torch.from_numpy(p.tgt).to(dev)
-    rot = torch.from_numpy(p.rotations).to(dev)
-    n, m, k = len(p.src), len(p.tgt), len(p.rotations)
-
-    box = p.meta.get("t_box")
-    if box is not None:                  # a local search: the box of the initial guess
-        box_kw = {"t_min": -box, "t_max": box}
-    else:
-        box_kw = {}
-    if args.scorer == "df":
-        # distance-field scoring needs the reference resident with its 128^3 field
-        target = dses.Target(tgt, df_trunc=p.eps, df_res=128)
-        rotset = dses.RotationSet(rot)
-
-        def run(**kw):
-            return dses.register_resident(target, rotset, src, p.eps, scorer="df", q=args.q,
-                                          **box_kw, **kw)
-    else:
-        def run(**kw):
-            return dses.register(src, tgt, rot, p.eps, scorer=args.scorer, q=args.q, **box_kw,
-                                 **kw)
-    for _ in range(args.warmup):
-        run()
-    torch.cuda.synchronize()
-    dses.kernel_stats(reset=True)
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for step in range(args.steps):
-        ts = time.perf_counter()
-        r = run(timing=True)
-        lat.append(time.perf_counter() - ts)
-        if lat[-1] > 5.0:
-            print(f"bench.py: step {step + 1}/{args.steps} {lat[-1]:.1f} s", file=sys.stderr,
-                  flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    st = dses.kernel_stats()
-
-    sweep_ms = st["vote_score_ms"] / max(1, st["vote_score_launches"])
-    # algorithmic work per candidate: 3 FLOP per vote pair, 8 per brute-force score pair,
-    # 18 per transformed point; distance-field scoring replaces the score pairs by
-    # one lookup per point
-    score_pairs = 0.0 if args.scorer == "df" else 8.0 * n * m
-    scored = k
-    if args.q > 0.0:                     # pruning: every rotation voted, the kept ones scored
-        scored = int(np.isfinite(run(records=True).records["error"]).sum())
-    flop_per_launch = (3.0 * n * m + 18.0 * n) * k + score_pairs * scored
-    achieved = flop_per_launch / (sweep_ms * 1e-3) / 1e12
-    # the counters were taken on the default configuration of the workload (every
-    # rotation scored, automatic scorer); other configurations run other kernels
-    traffic = load_traffic(args.workload) if args.q == 0.0 and args.scorer == "auto" else None
-    lat_ms = np.array(lat) * 1e3
-    out = {
-        "metric": "candidate poses {R,t} scored/sec (1 GPU) + p50/p99 registration latency",
-        "value": k * args.steps / elapsed,
-        "unit": "candidates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": desc, "n_src": n, "n_ref": m, "rotations": k, "eps": p.eps,
-                   "metric": "trunc_l2", "scorer": args.scorer, "q": args.q,
-                   "parallelism": "single GPU"},
-        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
-                       "p99": float(np.percentile(lat_ms, 99)), "path": "plain, one call"},
-        "roofline": {"bound": "alu", "kernel": "k_sweep (vote + mode + score)",
-                     "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
-                     "work": ("algorithmic (3*N*M + 18*N) FLOP per candidate (DF scoring)"
-                              if args.scorer == "df" else
-                              "algorithmic (11*N*M + 18*N) FLOP per candidate"),
-                     "kernel_ms": sweep_ms},
-        "result": {"rot_index": r.rot_index, "inliers": r.inliers, "error": r.error,
-                   "rot_err_deg": float(np.rad2deg(np.arccos(np.clip(
-                       (np.trace(r.R.astype(np.float64).T @ p.R_true) - 1.0) / 2.0, -1.0, 1.0)))),
-                   "t_err": float(np.linalg.norm(r.t.astype(np.float64) - p.t_true))},
-    }
-    if args.q > 0.0:
-        out["result"]["scored"] = scored
-        out["roofline"]["work"] += " (q > 0: score pairs only for the scored rotations)"
-    if args.cpu_sample != 0:
-        threads = min(16, len(os.sched_getaffinity(0)))
-        sample = args.cpu_sample if args.cpu_sample > 0 else max(16, int(2.2e10 / (n * m)))
-        print(f"bench.py: oracle CPU baseline on {min(sample, k)} rotations", file=sys.stderr,
-              flush=True)
-        out["cpu_baseline"] = cpu_baseline(p, sample, threads)
+    out = bench_plain(args, args.workload, args.steps, args.warmup, args.cpu_sample,
+                      args.scorer, args.q)
+    if args.workload == "c5" and not args.alone and args.scorer == "auto" and args.q == 0.0:
+        # the metric's second half: served vs plain latency on the serving workload
+        sv = bench_serve(args, n_req=min(args.requests, 100))
+        out["served_vs_plain"] = {"workload": sv["config"]["workload"],
+                                  "served": sv["served"], "plain": sv["plain"],
+                                  "saturation": sv["saturation"]}
+        # the object-scale registration (its own line with --workload c2)
+        c2 = bench_plain(args, "c2", 10, 2, 0)
+        out["object_scale"] = {"workload": c2["config"]["workload"], "value": c2["value"],
+                               "unit": c2["unit"], "ms_per_step": c2["ms_per_step"],
+                               "latency_ms": c2["latency_ms"], "roofline": c2["roofline"],
+                               "result": c2["result"]}
     print(json.dumps(out), flush=True)
 
 

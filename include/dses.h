@@ -28,32 +28,36 @@
  *  - Every call returns a dses_status; on failure a message is available from
  *    dses_last_error() (thread-local) and `out` is left untouched.
  *
- * Translation lattice and ROUND (Alg. 2, "ROUND(y_j - R x_i, delta_t)")
- * ----------------------------------------------------------------------
+ * Translation lattice and ROUND (Alg. 2: the rounded pair translation y_j - R x_i)
+ * ----------------------------------------------------------------------------
  * The vote array spans the translation box [t_min, t_max] (default [-1, 1]^3;
  * the paper bounds it by the search range of its experiments, Sec. V).  Its bins
  * are the lattice points b*delta with, per axis a,
  *     k_lo_a = ceil(t_min_a/delta - 1e-4),  k_hi_a = floor(t_max_a/delta + 1e-4)
- * (double precision), size_a = k_hi_a - k_lo_a + 1.  The bin of a pair is decided
- * in IEEE single precision, exactly as follows (the paper fixes no precision):
+ * (double precision), size_a = k_hi_a - k_lo_a + 1.  A pair votes for the nearest
+ * lattice point, halves rounded up: b_a = floor((y_a - p_a)/delta + 1/2) with
+ * p = R x (Lemma 2, Eq. (5)), and only if b lies in the box.  The kernels evaluate
+ * this in IEEE single precision (the paper fixes no precision), as
  *     s    = 1.0f / delta
  *     p_a  = fmaf(R[a][2], x_z, fmaf(R[a][1], x_y, R[a][0] * x_x))
  *     Y_a  = (y_a * s) + (0.5f - (float)k_lo_a)          (two roundings, no fma)
  *     c_a  = floorf(Y_a - p_a * s)                        (box-relative bin)
- * i.e. c_a = round-half-up((y_a - p_a)/delta) - k_lo_a.  A pair votes iff
- * 0 <= c_a < size_a on every axis.  The mode is the bin with the largest count;
- * ties go to the lowest linear index ((c_x * size_y + c_y) * size_z + c_z).
- * The returned translation is t_a = (float)(c_a + k_lo_a) * delta (no refinement:
- * the paper's answer is exact only up to the discretisation delta).
+ * voting iff 0 <= c_a < size_a on every axis; so a pair whose exact u + 1/2 lies
+ * within float rounding (about 1e-5 bin units at the workloads' magnitudes) of an
+ * integer may be counted in the neighbouring bin.  The mode is the bin with the
+ * largest count; ties go to the lowest linear index
+ * ((c_x * size_y + c_y) * size_z + c_z).  The returned translation is
+ * t_a = (float)(c_a + k_lo_a) * delta (no refinement: the paper's answer is exact
+ * only up to the discretisation delta).
  *
- * Metrics (Eq. (1): "any desired norm"; Sec. IV-B uses a truncated norm)
- * ----------------------------------------------------------------------
+ * Metrics (Eq. (1) leaves the norm free; Sec. IV-B uses a truncated norm)
+ * ------------------------------------------------------------------------
  *   DSES_TRUNC_L2  error = sum_i min(d_i, tau), d_i the Euclidean NN distance
  *   DSES_INLIERS   error = N - inliers  (the L0^{m1} objective of Eq. (3), Thm. 3)
  *   DSES_TLS       error = sum_i min(d_i^2, tau^2)
  *   DSES_TRUNC_L1  error = sum_i min(min_j ||q_i - y_j||_1, tau)
  *   DSES_TRUNC_LP  error = sum_i min(d_i, tau)^p, p in (0, 1] (dses_options.p; the
- *                  Lp, p < 1, sparsity objectives the paper's "any norm" allows)
+ *                  Lp, p < 1, sparsity objectives that Sec. III admits)
  *   DSES_VOTES     no scoring: candidates are ranked by their mode count M_k alone
  *                  (Thm. 3: under its separation condition M_k is the L0^{m1}
  *                  inlier count of {R_k, t_k}); records and results carry
@@ -98,14 +102,21 @@ typedef enum {
 /* How the per-candidate nearest-neighbour term of Eq. (2) is evaluated. */
 typedef enum {
     DSES_SCORER_AUTO = 0,   /* GRID, or DF when the target handle carries a field    */
-    DSES_SCORER_BRUTE = 1,  /* every reference point per source point (Alg. 2 as
-                               printed: "brute-force checking every nearest neighbor") */
+    DSES_SCORER_BRUTE = 1,  /* every reference point per source point (the error
+                               loop of Alg. 2 as printed, a brute-force search)       */
     DSES_SCORER_GRID = 2,   /* exact: only reference points within r = max(eps, tau)
                                can change rho or the inlier test, found through a
                                uniform cell grid of pitch >= r; same result as BRUTE  */
     DSES_SCORER_DF = 3      /* voxel distance field of the reference (approximate,
                                see dses_target_create); TRUNC_L1 is not supported     */
 } dses_scorer;
+
+/* How a distance-field scorer reads the field at a query q (dses_target_create). */
+typedef enum {
+    DSES_DF_NEAREST = 0,    /* the value of the voxel containing q                    */
+    DSES_DF_TRILINEAR = 1   /* linear interpolation between the 8 voxel centres around
+                               q along each axis (r at centres outside the grid)       */
+} dses_df_lookup;
 
 #define DSES_DEVICE_PTRS 0x1u   /* inputs (and records) are device pointers            */
 #define DSES_TIMING 0x2u        /* time each kernel with HIP events (dses_kernel_stats) */
@@ -143,6 +154,7 @@ typedef struct {
                                  chosen per call from the sizes and the reference's
                                  extent.  Results do not depend on it; other values
                                  are DSES_E_INVAL                                     */
+    int32_t df_lookup;        /* dses_df_lookup of the DF scorer; 0 -> NEAREST         */
 } dses_options;
 
 #define DSES_TOPK_MAX 64
@@ -246,9 +258,14 @@ typedef struct {
  * distance field: a df_res^3 float32 grid over the reference AABB padded by r,
  * voxel centres c = lo + (idx + 1/2) h, value min(min_j ||c - y_j||, r), where in
  * float32  lo_a = min_j y_a - r,  h_a = ((max_j y_a + r) - lo_a) / df_res.
- * A DF query q (formed in float32 as R x + t) reads the voxel
- * idx_a = floorf((q_a - lo_a) * (1.0f / h_a)); outside the grid its value is r.
- * DF scoring then requires r == max(eps, tau) of the registration. */
+ * A DF query q (formed in float32 as R x + t) reads, with DSES_DF_NEAREST, the
+ * voxel idx_a = floor((q_a - lo_a)/h_a) (evaluated as floorf((q_a - lo_a) *
+ * (1.0f / h_a))); outside the grid its value is r.  With DSES_DF_TRILINEAR it
+ * interpolates linearly along each axis between the values at the 8 voxel
+ * centres around q, u_a = (q_a - lo_a)/h_a - 1/2, a centre outside the grid
+ * counting as r (outside the padded box every point is farther than r from the
+ * reference); the interpolant is continuous in q.  DF scoring requires
+ * r == max(eps, tau) of the registration. */
 dses_status dses_target_create(const float *tgt, int64_t m, const dses_target_opts *opt,
                                dses_target **out);
 dses_status dses_target_destroy(dses_target *t);
@@ -304,6 +321,7 @@ typedef struct {
                                  stream window, 1..16); 0 -> tuned or automatic
                                  (64 / groups, 1..8, per problem)                   */
     void *stream;
+    int32_t df_lookup;        /* dses_df_lookup for DF-scored problems; 0 -> NEAREST  */
 } dses_batch_opts;
 
 /* Register every problem; results (and records) are identical to running each
@@ -376,20 +394,38 @@ typedef struct {
 } dses_server_opts;
 
 dses_status dses_server_create(const dses_server_opts *opt, dses_server **out);
-/* Queue a registration of host src (n x 3) against resident data; the source is
- * copied at submit time.  Returns a request id. */
+/* Queue a registration of host src (n x 3, n <= 16,384) against resident data;
+ * the source is copied at submit time.  Returns a request id.
+ * opt (NULL: defaults) sets this request's delta_t, tau, translation box,
+ * scorer (0: the server's), df_lookup, and optionally asks for its records
+ * (opt->records: k dses_record) and its top_k best candidates (opt->topk);
+ * both are host buffers the caller keeps valid until dses_server_wait returns
+ * for the request, filled before the request is reported finished.  flags
+ * (other than 0), stream, q, p and lane_group are plain-path options and must be
+ * 0; DSES_TRUNC_LP and DSES_VOTES are plain-path metrics.  The result equals that
+ * of dses_register_resident with the same options, whatever else is served. */
 dses_status dses_server_submit(dses_server *srv, const dses_target *tgt,
                                const dses_rotset *rots, const float *src, int64_t n, float eps,
-                               dses_metric metric, uint64_t *req_id);
-/* Wait up to timeout_ms (< 0: forever) for a request; consumes it on success. */
+                               dses_metric metric, const dses_options *opt, uint64_t *req_id);
+/* Wait up to timeout_ms (< 0: forever) for a request.  On DSES_OK the request is
+ * consumed: *out (if *req_status is DSES_OK), *req_status, and if not NULL its
+ * time from submission to admission to the device (*queue_s) and to completion
+ * (*total_s), in seconds, are written, and the id is forgotten (a later wait,
+ * poll, timing or cancel of it returns DSES_E_STATE). */
 dses_status dses_server_wait(dses_server *srv, uint64_t req_id, int32_t timeout_ms,
-                             dses_result *out, dses_status *req_status);
-/* Non-blocking: 1 if finished, 0 if pending, < 0 on error. */
+                             dses_result *out, dses_status *req_status, double *queue_s,
+                             double *total_s);
+/* Non-blocking: 1 if finished, 0 if pending, < 0 on error (DSES_E_STATE for an
+ * unknown or consumed id). */
 int32_t dses_server_poll(dses_server *srv, uint64_t req_id);
-/* Submit-to-finish latency (seconds) of a finished request, and the moment (on the
- * server's steady clock) it was admitted to the device. */
+/* Queue and total latency (seconds) of a finished request not yet consumed by
+ * dses_server_wait. */
 dses_status dses_server_timing(dses_server *srv, uint64_t req_id, double *queue_s,
                                double *total_s);
+/* Withdraw a request that is still queued (not yet admitted to the device): it is
+ * consumed and never runs.  DSES_E_STATE if it is unknown, consumed, already on
+ * the device or finished (wait for it instead). */
+dses_status dses_server_cancel(dses_server *srv, uint64_t req_id);
 dses_status dses_server_destroy(dses_server *srv);
 
 #ifdef __cplusplus

@@ -1,6 +1,7 @@
 // DSES C ABI: context, argument checking and the plain registration driver.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -449,6 +450,25 @@ dses_status apply_metric_options(const dses_options &o, Params *p)
         set_error("lane_group must be 0 (automatic), 16, 32 or 64");
         return DSES_E_INVAL;
     }
+    if (o.df_lookup != DSES_DF_NEAREST && o.df_lookup != DSES_DF_TRILINEAR) {
+        set_error("df_lookup must be DSES_DF_NEAREST or DSES_DF_TRILINEAR");
+        return DSES_E_INVAL;
+    }
+    p->df_lookup = o.df_lookup;
+    return DSES_OK;
+}
+
+dses_status copy_options(const dses_options *opt, dses_options *o)
+{
+    *o = dses_options{};
+    if (!opt) return DSES_OK;
+    const size_t given = opt->struct_size ? opt->struct_size : sizeof(dses_options);
+    // the first field that existed in every version ends at lane_group
+    if (given < offsetof(dses_options, df_lookup) || given > sizeof(dses_options)) {
+        set_error("dses_options.struct_size is not a size of this structure");
+        return DSES_E_INVAL;
+    }
+    std::memcpy(o, opt, given);
     return DSES_OK;
 }
 
@@ -591,6 +611,7 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
         a.field.val = t->df;
         a.field.res = t->df_res;
         a.field.r = t->df_r;
+        a.field.lookup = job.p.df_lookup;
         for (int q = 0; q < 3; ++q) { a.field.lo[q] = t->df_lo[q]; a.field.inv[q] = t->df_inv[q]; }
     }
 
@@ -711,14 +732,8 @@ dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t
         set_error("n, m, k must be positive with n*m < 2^31 and k < 2^31");
         return DSES_E_INVAL;
     }
-    dses_options o{};
-    if (opt) {
-        if (opt->struct_size != 0 && opt->struct_size < sizeof(dses_options)) {
-            set_error("dses_options.struct_size too small");
-            return DSES_E_INVAL;
-        }
-        o = *opt;
-    }
+    dses_options o;
+    if (copy_options(opt, &o) != DSES_OK) return DSES_E_INVAL;
     if (o.top_k < 0 || o.top_k > DSES_TOPK_MAX || (o.top_k > 0 && !o.topk) ||
         !(o.q >= 0.0f && o.q <= 1.0f)) {
         set_error("top_k must be in 0..DSES_TOPK_MAX with a topk buffer, q in [0, 1]");
@@ -784,14 +799,8 @@ dses_status dses_register_exhaustive(const float *src, int64_t n, const float *t
         set_error("n, m, k must be positive with n*m < 2^31 and n <= 12288");
         return DSES_E_INVAL;
     }
-    dses_options o{};
-    if (opt) {
-        if (opt->struct_size != 0 && opt->struct_size < sizeof(dses_options)) {
-            set_error("dses_options.struct_size too small");
-            return DSES_E_INVAL;
-        }
-        o = *opt;
-    }
+    dses_options o;
+    if (copy_options(opt, &o) != DSES_OK) return DSES_E_INVAL;
     if (o.top_k != 0 || o.q != 0.0f) {
         set_error("top_k and q are not options of the exhaustive search");
         return DSES_E_INVAL;

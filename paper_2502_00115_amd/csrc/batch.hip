@@ -11,6 +11,7 @@
 // fits the buffers' capacity.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -208,9 +209,17 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         return DSES_E_INVAL;
     }
     dses_batch_opts o{};
-    if (opt) o = *opt;
+    if (opt) {
+        const size_t given = opt->struct_size ? opt->struct_size : sizeof(dses_batch_opts);
+        if (given < offsetof(dses_batch_opts, df_lookup) || given > sizeof(dses_batch_opts)) {
+            set_error("dses_batch_opts.struct_size is not a size of this structure");
+            return DSES_E_INVAL;
+        }
+        std::memcpy(&o, opt, given);
+    }
     if (o.scorer < DSES_SCORER_AUTO || o.scorer > DSES_SCORER_DF || o.tile_rot < 0 ||
-        o.vote_parts < 0 || o.vote_parts > 16) {
+        o.vote_parts < 0 || o.vote_parts > 16 ||
+        (o.df_lookup != DSES_DF_NEAREST && o.df_lookup != DSES_DF_TRILINEAR)) {
         set_error("invalid batch options");
         return DSES_E_INVAL;
     }
@@ -513,6 +522,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
             a.field.val = x.target->df;
             a.field.res = x.target->df_res;
             a.field.r = x.target->df_r;
+            a.field.lookup = o.df_lookup;
             for (int q = 0; q < 3; ++q) {
                 a.field.lo[q] = x.target->df_lo[q];
                 a.field.inv[q] = x.target->df_inv[q];

@@ -76,10 +76,12 @@ struct Params {
     int metric;
     int scorer;
     float lp = 0.5f;         // exponent of DSES_TRUNC_LP
+    int32_t df_lookup = DSES_DF_NEAREST;   // how the DF scorer reads the field
 };
 
 // Applies the plain-path options that resolve_params does not see (the Lp
-// exponent; q has no meaning with DSES_VOTES; lane_group is 0, 16, 32 or 64).
+// exponent; q has no meaning with DSES_VOTES; lane_group is 0, 16, 32 or 64;
+// the distance-field lookup).
 // Host-side check, no device use.
 dses_status apply_metric_options(const dses_options &o, Params *p);
 
@@ -174,6 +176,10 @@ struct Job {
     const float *host_tgt = nullptr;     // host AoS copy of the reference, if known
     bool exhaustive = false;             // Alg. 1: every lattice translation per rotation
 };
+
+// The option struct a caller passed, checked against its declared size (0: the
+// full current size) and copied; missing trailing fields stay 0 (defaults).
+dses_status copy_options(const dses_options *opt, dses_options *o);
 
 // Run one registration on `stream` using the context workspace (caller holds c->mu).
 dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check_inputs,

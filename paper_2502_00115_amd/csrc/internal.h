@@ -48,6 +48,7 @@ struct Field {
     float inv[3];          // 1 / voxel pitch per axis
     int32_t res;
     float r;               // value outside the grid
+    int32_t lookup;        // dses_df_lookup: nearest voxel or trilinear
 };
 
 // Per-rotation source sort: sb_n buckets (a multiple of the block size, at most

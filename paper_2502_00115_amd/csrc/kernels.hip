@@ -872,16 +872,48 @@ __device__ __forceinline__ void nn_grid(const CellGrid &cg, float qx, float qy, 
     nn.l1 = bl1;
 }
 
-// Distance-field lookup: idx_a = floor((q_a - lo_a) * inv_a); r outside the grid.
-__device__ __forceinline__ float df_lookup(const Field &f, float qx, float qy, float qz)
+// Distance-field value of voxel (ix, iy, iz); r outside the grid.
+__device__ __forceinline__ float df_at(const Field &f, int ix, int iy, int iz)
 {
-    const int ix = cvt_flr(__fmul_rn(qx - f.lo[0], f.inv[0]));
-    const int iy = cvt_flr(__fmul_rn(qy - f.lo[1], f.inv[1]));
-    const int iz = cvt_flr(__fmul_rn(qz - f.lo[2], f.inv[2]));
     const uint32_t R = (uint32_t)f.res;
     if ((uint32_t)ix < R && (uint32_t)iy < R && (uint32_t)iz < R)
         return f.val[((size_t)ix * R + iy) * R + iz];
     return f.r;
+}
+
+// Nearest-voxel lookup: idx_a = floor((q_a - lo_a) * inv_a); r outside the grid.
+__device__ __forceinline__ float df_nearest(const Field &f, float qx, float qy, float qz)
+{
+    return df_at(f, cvt_flr(__fmul_rn(qx - f.lo[0], f.inv[0])),
+                 cvt_flr(__fmul_rn(qy - f.lo[1], f.inv[1])),
+                 cvt_flr(__fmul_rn(qz - f.lo[2], f.inv[2])));
+}
+
+// Trilinear lookup: u_a = (q_a - lo_a) * inv_a - 1/2 in voxel-centre units, the
+// eight centres floor(u) + {0, 1} weighted by the fractional parts (a centre
+// outside the grid counts as r); r when every centre is outside along an axis
+// (u_a < -1 or u_a >= res, NaN included).
+__device__ __forceinline__ float df_trilinear(const Field &f, float qx, float qy, float qz)
+{
+    const float ux = __fmul_rn(qx - f.lo[0], f.inv[0]) - 0.5f;
+    const float uy = __fmul_rn(qy - f.lo[1], f.inv[1]) - 0.5f;
+    const float uz = __fmul_rn(qz - f.lo[2], f.inv[2]) - 0.5f;
+    const float R = (float)f.res;
+    if (!(ux >= -1.0f && ux < R && uy >= -1.0f && uy < R && uz >= -1.0f && uz < R)) return f.r;
+    const float fx = floorf(ux), fy = floorf(uy), fz = floorf(uz);
+    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    const float wx = ux - fx, wy = uy - fy, wz = uz - fz;
+    float c[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const float v0 = df_at(f, ix + a, iy + b, iz), v1 = df_at(f, ix + a, iy + b, iz + 1);
+            c[a][b] = fmaf(wz, v1 - v0, v0);
+        }
+    const float e0 = fmaf(wy, c[0][1] - c[0][0], c[0][0]);
+    const float e1 = fmaf(wy, c[1][1] - c[1][0], c[1][0]);
+    return fmaf(wx, e1 - e0, e0);
 }
 
 // Score candidate {R_k, t_k = b delta} (Eq. (1)/(2): sum over the source of the
@@ -946,7 +978,8 @@ __device__ void score_candidate(const SweepArgs &a, int k, const float *R, int b
             if (SCORER == DSES_SCORER_GRID)
                 nn_grid(a.grid, qx, qy, qz, want_l1, nn);
             else
-                D = df_lookup(a.field, qx, qy, qz);
+                D = a.field.lookup == DSES_DF_TRILINEAR ? df_trilinear(a.field, qx, qy, qz)
+                                                        : df_nearest(a.field, qx, qy, qz);
         }
         if (SCORER == DSES_SCORER_BRUTE && L.G > 1) {
             // combine the reference partitions of each source point

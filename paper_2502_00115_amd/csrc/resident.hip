@@ -301,8 +301,8 @@ dses_status dses_register_resident(const dses_target *tgt, const dses_rotset *ro
         set_error("invalid arguments");
         return DSES_E_INVAL;
     }
-    dses_options o{};
-    if (opt) o = *opt;
+    dses_options o;
+    if (copy_options(opt, &o) != DSES_OK) return DSES_E_INVAL;
     Params p;
     dses_status st = resolve_params(eps, metric, o.delta_t, o.tau, o.t_min, o.t_max, o.scorer, &p);
     if (st != DSES_OK) return st;

@@ -102,6 +102,12 @@ struct Request {
     int32_t next_k = 0;                      // rotations handed to slices so far
     double pair_cost = 0.0;                  // n * m per rotation
     dses_record *d_rec = nullptr;            // records inside the request's pool range
+    // optional outputs (caller-owned host buffers, filled before DONE)
+    dses_record *host_rec = nullptr;
+    dses_candidate *host_topk = nullptr;
+    int32_t top_k = 0;
+    void *d_topk_a = nullptr, *d_topk_b = nullptr;   // top-k passes, in the pool range
+    dses_candidate *d_topk = nullptr;
 };
 
 struct SliceSet {
@@ -125,6 +131,7 @@ struct ServerImpl {
     Context *c = nullptr;
     dses_server_opts opt{};
     hipStream_t up = nullptr;                // admission uploads and staging
+    hipStream_t down = nullptr;              // result copies of finished requests
     hipEvent_t up_done = nullptr;            // recorded after every admission's uploads
     hipStream_t stream = nullptr;            // even slices
     hipStream_t stream2 = nullptr;           // odd slices
@@ -172,7 +179,10 @@ struct ServerImpl {
 size_t ServerImpl::need_bytes(const Request &r) const
 {
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return al(12 * (size_t)r.n) + al(24 * (size_t)r.k);
+    size_t b = al(12 * (size_t)r.n) + al(24 * (size_t)r.k);
+    if (r.top_k > 0)
+        b += 2 * al(topk_scratch_bytes(r.k, r.top_k)) + al(sizeof(dses_candidate) * r.top_k);
+    return b;
 }
 
 dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
@@ -187,6 +197,7 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     grid = std::max(1, c->n_cu);
     slice_pairs = 1.0e6 * (opt.slice_mpairs > 0 ? opt.slice_mpairs : 12000);
     DSES_HIP(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
+    DSES_HIP(hipStreamCreateWithFlags(&down, hipStreamNonBlocking));
     // The slice streams must sit on two different hardware queues: kernels of one
     // queue never overlap, and streams created the ordinary way share a small
     // pool of queues (two of them can land on the same one).  A stream created
@@ -242,6 +253,7 @@ ServerImpl::~ServerImpl()
     cv_work.notify_all();
     if (worker.joinable()) worker.join();
     if (up) (void)hipStreamSynchronize(up);
+    if (down) (void)hipStreamSynchronize(down);
     if (stream) (void)hipStreamSynchronize(stream);
     if (stream2) (void)hipStreamSynchronize(stream2);
     if (up_done) (void)hipEventDestroy(up_done);
@@ -263,6 +275,7 @@ ServerImpl::~ServerImpl()
     if (d_status) (void)hipFree(d_status);
     if (pool_mem) (void)hipFree(pool_mem);
     if (up) (void)hipStreamDestroy(up);
+    if (down) (void)hipStreamDestroy(down);
     if (stream) (void)hipStreamDestroy(stream);
     if (stream2) (void)hipStreamDestroy(stream2);
     for (auto &kv : all) delete kv.second;
@@ -290,6 +303,13 @@ dses_status ServerImpl::prepare(Request *r)
     char *base = static_cast<char *>(pool_mem) + r->off;
     float *d_src = reinterpret_cast<float *>(base);
     r->d_rec = reinterpret_cast<dses_record *>(base + al(12 * (size_t)r->n));
+    if (r->top_k > 0) {
+        char *tk = base + al(12 * (size_t)r->n) + al(24 * (size_t)r->k);
+        const size_t sb = al(topk_scratch_bytes(r->k, r->top_k));
+        r->d_topk_a = tk;
+        r->d_topk_b = tk + sb;
+        r->d_topk = reinterpret_cast<dses_candidate *>(tk + 2 * sb);
+    }
     char *stage = reinterpret_cast<char *>(h_stage) + (size_t)r->slot * kSlotStageBytes;
     std::memcpy(stage, r->src.data(), 12 * (size_t)r->n);
     SweepArgs &a = *reinterpret_cast<SweepArgs *>(stage + 12 * (size_t)kServeMaxSrc);
@@ -309,6 +329,7 @@ dses_status ServerImpl::prepare(Request *r)
         a.field.val = tm->df;
         a.field.res = tm->df_res;
         a.field.r = tm->df_r;
+        a.field.lookup = r->p.df_lookup;
         for (int q = 0; q < 3; ++q) { a.field.lo[q] = tm->df_lo[q]; a.field.inv[q] = tm->df_inv[q]; }
     }
     a.rec = r->d_rec;
@@ -422,9 +443,13 @@ bool ServerImpl::launch_slice()
         if (have_last) chk(hipStreamWaitEvent(st, last_slice, 0));
         chk(launch_batch_aux(nullptr, static_cast<SelectDesc *>(s->d_sel),
                              static_cast<int32_t *>(s->d_header), n_sel, 1, st));
-        for (Request *r : s->finishing)
+        for (Request *r : s->finishing) {
+            if (r->top_k > 0)
+                chk(launch_topk(r->d_rec, r->k, r->top_k, r->p.delta, r->d_topk_a, r->d_topk_b,
+                                r->d_topk, st));
             chk(hipMemcpyAsync(h_res + r->slot, d_res + r->slot, sizeof(DevResult),
                                hipMemcpyDeviceToHost, st));
+        }
     }
     chk(hipEventRecord(s->done, st));
     last_slice = s->done;
@@ -444,7 +469,21 @@ void ServerImpl::poll_slices()
         if (hipEventQuery(s.done) != hipSuccess) continue;
         for (Request *r : s.finishing) {
             const DevResult &d = h_res[r->slot];
-            if (d.bad_input) {
+            // the caller's record and top-k buffers: copied from the request's pool
+            // range before that range is returned (the slice is complete)
+            bool copied = true;
+            if (r->host_rec && !d.bad_input)
+                copied = hipMemcpyAsync(r->host_rec, r->d_rec, sizeof(dses_record) * r->k,
+                                        hipMemcpyDeviceToHost, down) == hipSuccess;
+            if (copied && r->top_k > 0 && !d.bad_input && d.rot_index >= 0)
+                copied = hipMemcpyAsync(r->host_topk, r->d_topk,
+                                        sizeof(dses_candidate) * r->top_k,
+                                        hipMemcpyDeviceToHost, down) == hipSuccess;
+            if (copied) copied = hipStreamSynchronize(down) == hipSuccess;
+            if (!copied) {
+                (void)hipGetLastError();
+                r->status = DSES_E_DEVICE;
+            } else if (d.bad_input) {
                 r->status = DSES_E_INVAL;
             } else if (d.rot_index < 0) {
                 r->status = DSES_E_NOCANDIDATE;
@@ -560,7 +599,7 @@ dses_status dses_server_create(const dses_server_opts *opt, dses_server **out)
 
 dses_status dses_server_submit(dses_server *srv, const dses_target *tgt, const dses_rotset *rots,
                                const float *src, int64_t n, float eps, dses_metric metric,
-                               uint64_t *req_id)
+                               const dses_options *opt, uint64_t *req_id)
 {
     set_error("");
     if (!srv || !tgt || !rots || !src || !req_id || n <= 0 || n > kServeMaxSrc ||
@@ -568,9 +607,19 @@ dses_status dses_server_submit(dses_server *srv, const dses_target *tgt, const d
         set_error("invalid request");
         return DSES_E_INVAL;
     }
+    dses_options o;
+    if (copy_options(opt, &o) != DSES_OK) return DSES_E_INVAL;
+    if (o.flags != 0 || o.stream || o.q != 0.0f || o.p != 0.0f || o.lane_group != 0 ||
+        o.top_k < 0 || o.top_k > DSES_TOPK_MAX || (o.top_k > 0 && !o.topk)) {
+        set_error("served requests take delta_t, tau, the box, scorer, df_lookup, records "
+                  "and top_k (with a topk buffer) only");
+        return DSES_E_INVAL;
+    }
     ServerImpl &S = srv->impl;
     auto *r = new Request();
-    dses_status st = resolve_params(eps, metric, 0.0f, 0.0f, nullptr, nullptr, S.opt.scorer, &r->p);
+    dses_status st = resolve_params(eps, metric, o.delta_t, o.tau, o.t_min, o.t_max,
+                                    o.scorer ? o.scorer : S.opt.scorer, &r->p);
+    if (st == DSES_OK) st = apply_metric_options(o, &r->p);
     if (st == DSES_OK && (metric == DSES_TRUNC_LP || metric == DSES_VOTES)) {
         set_error("DSES_TRUNC_LP and DSES_VOTES are plain-path metrics");
         st = DSES_E_INVAL;
@@ -591,6 +640,9 @@ dses_status dses_server_submit(dses_server *srv, const dses_target *tgt, const d
     r->n = (int32_t)n;
     r->m = tgt->res.m;
     r->k = (int32_t)rots->res.k;
+    r->host_rec = static_cast<dses_record *>(o.records);
+    r->host_topk = static_cast<dses_candidate *>(o.topk);
+    r->top_k = o.top_k;
     r->scorer = r->p.scorer;
     if (r->scorer == DSES_SCORER_AUTO)
         r->scorer = (tgt->res.df && tgt->res.df_r == r->p.r && metric != DSES_TRUNC_L1)
@@ -628,7 +680,8 @@ dses_status dses_server_submit(dses_server *srv, const dses_target *tgt, const d
 }
 
 dses_status dses_server_wait(dses_server *srv, uint64_t req_id, int32_t timeout_ms,
-                             dses_result *out, dses_status *req_status)
+                             dses_result *out, dses_status *req_status, double *queue_s,
+                             double *total_s)
 {
     if (!srv || !out || !req_status) return DSES_E_INVAL;
     ServerImpl &S = srv->impl;
@@ -638,16 +691,53 @@ dses_status dses_server_wait(dses_server *srv, uint64_t req_id, int32_t timeout_
         set_error("unknown or already consumed request id");
         return DSES_E_STATE;
     }
-    Request *r = it->second;
-    auto done = [&] { return r->state == Request::DONE; };
+    // the request is looked up afresh at every wake-up: another thread's wait may
+    // consume (and free) it meanwhile
+    auto done = [&] {
+        auto f = S.all.find(req_id);
+        return f == S.all.end() || f->second->state == Request::DONE;
+    };
     if (timeout_ms < 0)
         S.cv_done.wait(lk, done);
     else if (!S.cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done)) {
         set_error("request not finished within the timeout");
         return DSES_E_TIMEOUT;
     }
+    it = S.all.find(req_id);
+    if (it == S.all.end()) {
+        set_error("request consumed by another wait");
+        return DSES_E_STATE;
+    }
+    Request *r = it->second;
     *out = r->out;
     *req_status = r->status;
+    if (queue_s) *queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
+    if (total_s) *total_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    S.all.erase(it);
+    delete r;
+    return DSES_OK;
+}
+
+dses_status dses_server_cancel(dses_server *srv, uint64_t req_id)
+{
+    if (!srv) return DSES_E_INVAL;
+    ServerImpl &S = srv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(req_id);
+    if (it == S.all.end() || it->second->state != Request::QUEUED) {
+        set_error("request unknown, consumed, already on the device or finished");
+        return DSES_E_STATE;
+    }
+    Request *r = it->second;
+    auto q = std::find(S.queue.begin(), S.queue.end(), r);
+    if (q == S.queue.end()) {
+        // taken by the scheduler for admission (memory is being prepared)
+        set_error("request is being admitted to the device");
+        return DSES_E_STATE;
+    }
+    S.queue.erase(q);
+    S.all.erase(it);
+    delete r;
     return DSES_OK;
 }
 

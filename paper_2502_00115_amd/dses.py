@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOCANDIDATE", -3: "E_NOMEM", -4: 
                 -5: "E_DEVICE", -6: "E_STATE"}
 METRICS = {"trunc_l2": 0, "inliers": 1, "tls": 2, "trunc_l1": 3, "trunc_lp": 4, "votes": 5}
 SCORERS = {"auto": 0, "brute": 1, "grid": 2, "df": 3}
+DF_LOOKUPS = {"nearest": 0, "trilinear": 1}
 DEVICE_PTRS, TIMING, BATCH_TUNE = 0x1, 0x2, 0x4
 
 EXPORTED = [
@@ -31,7 +32,7 @@ EXPORTED = [
     "dses_batch_last_config", "dses_measure_lds_atomics", "dses_rotations_euler",
     "dses_register_exhaustive",
     "dses_server_create", "dses_server_submit", "dses_server_wait", "dses_server_poll",
-    "dses_server_timing", "dses_server_destroy",
+    "dses_server_timing", "dses_server_cancel", "dses_server_destroy",
 ]
 
 
@@ -49,7 +50,7 @@ class Options(C.Structure):
                 ("tau", C.c_float), ("t_min", C.c_float * 3), ("t_max", C.c_float * 3),
                 ("scorer", C.c_int32), ("top_k", C.c_int32), ("stream", C.c_void_p),
                 ("records", C.c_void_p), ("topk", C.c_void_p), ("q", C.c_float),
-                ("p", C.c_float), ("lane_group", C.c_int32)]
+                ("p", C.c_float), ("lane_group", C.c_int32), ("df_lookup", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -82,7 +83,7 @@ class Problem(C.Structure):
 class BatchOpts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("flags", C.c_uint32), ("scorer", C.c_int32),
                 ("use_graph", C.c_int32), ("tile_rot", C.c_int32), ("vote_parts", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("df_lookup", C.c_int32)]
 
 
 class BatchConfig(C.Structure):
@@ -137,8 +138,11 @@ def lib():
         L.dses_register_batch.argtypes = [C.POINTER(Problem), i32, C.POINTER(BatchOpts),
                                           C.POINTER(Result), C.POINTER(i32)]
         L.dses_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(vp)]
-        L.dses_server_submit.argtypes = [vp, vp, vp, vp, i64, f, i32, C.POINTER(C.c_uint64)]
-        L.dses_server_wait.argtypes = [vp, C.c_uint64, i32, C.POINTER(Result), C.POINTER(i32)]
+        L.dses_server_submit.argtypes = [vp, vp, vp, vp, i64, f, i32, C.POINTER(Options),
+                                         C.POINTER(C.c_uint64)]
+        L.dses_server_wait.argtypes = [vp, C.c_uint64, i32, C.POINTER(Result), C.POINTER(i32),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.dses_server_cancel.argtypes = [vp, C.c_uint64]
         L.dses_server_poll.argtypes = [vp, C.c_uint64]
         L.dses_server_poll.restype = i32
         L.dses_server_timing.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double),
@@ -179,6 +183,8 @@ class Registration:
     n_valid: int
     records: np.ndarray | None = None
     top: np.ndarray | None = None          # CANDIDATE_DTYPE, best first (top_k > 0)
+    queue_s: float | None = None           # served requests: submission -> admission
+    total_s: float | None = None           # served requests: submission -> completion
 
 
 def _result(r: Result, records=None, top=None) -> Registration:
@@ -233,11 +239,12 @@ def _stream_of(stream):
 
 
 def _options(args: _Args, delta_t, tau, t_min, t_max, scorer, timing, stream, records_ptr,
-             q=0.0, lp=0.0, lane_group=0):
+             q=0.0, lp=0.0, lane_group=0, df_lookup="nearest"):
     o = Options()
     o.q = float(q)
     o.p = float(lp)
     o.lane_group = int(lane_group)
+    o.df_lookup = DF_LOOKUPS[df_lookup]
     o.struct_size = C.sizeof(Options)
     o.flags = (DEVICE_PTRS if args.device else 0) | (TIMING if timing else 0)
     o.delta_t = 0.0 if delta_t is None else float(delta_t)
@@ -291,7 +298,8 @@ def _topk_buffer(args: _Args, k: int, o: Options):
 
 def register(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=None,
              t_min=None, t_max=None, scorer="auto", records=False, top_k=0, q=0.0,
-             lp=0.0, timing=False, stream=None, lane_group=0) -> Registration:
+             lp=0.0, timing=False, stream=None, lane_group=0,
+             df_lookup="nearest") -> Registration:
     """dses_register: the full sweep over the rotation list (top_k > 0: also the best
     top_k candidates in selection order, Registration.top; q > 0: score only the
     rotations with M_k >= q M*; lp: exponent of metric "trunc_lp"; lane_group: vote
@@ -302,7 +310,7 @@ def register(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=N
     pr, k = args.ptr(rotations, 9)
     rbuf, rptr = _records_buffer(args, k) if records else (None, None)
     o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr, q, lp,
-                 lane_group)
+                 lane_group, df_lookup)
     tbuf = _topk_buffer(args, int(top_k), o)
     res = Result()
     _check(lib().dses_register(ps, n, pt, m, pr, k, C.c_float(eps), METRICS[metric],
@@ -391,11 +399,12 @@ class RotationSet:
 def register_resident(target: Target, rotset: RotationSet, src, eps, metric="trunc_l2", *,
                       delta_t=None, tau=None, t_min=None, t_max=None, scorer="auto",
                       records=False, top_k=0, q=0.0, lp=0.0, timing=False,
-                      stream=None) -> Registration:
+                      stream=None, df_lookup="nearest") -> Registration:
     args = _Args()
     ps, n = args.ptr(src, 3)
     rbuf, rptr = _records_buffer(args, rotset.k) if records else (None, None)
-    o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr, q, lp)
+    o = _options(args, delta_t, tau, t_min, t_max, scorer, timing, stream, rptr, q, lp,
+                 df_lookup=df_lookup)
     tbuf = _topk_buffer(args, int(top_k), o)
     res = Result()
     _check(lib().dses_register_resident(target.handle, rotset.handle, ps, n, C.c_float(eps),
@@ -405,7 +414,8 @@ def register_resident(target: Target, rotset: RotationSet, src, eps, metric="tru
 
 
 def register_batch(problems, *, scorer="auto", use_graph=True, tile_rot=0, vote_parts=0,
-                   autotune=False, records=False, timing=False, stream=None):
+                   autotune=False, records=False, timing=False, stream=None,
+                   df_lookup="nearest"):
     """dses_register_batch over dicts with keys src, tgt/target, rotations/rotset, eps,
     and optionally metric, delta_t, tau, t_min, t_max.  Returns (results, statuses).
     autotune=True sets DSES_BATCH_TUNE (time candidate launch layouts on this batch and
@@ -440,7 +450,7 @@ def register_batch(problems, *, scorer="auto", use_graph=True, tile_rot=0, vote_
     o = BatchOpts(C.sizeof(BatchOpts), (DEVICE_PTRS if args.device else 0) |
                   (TIMING if timing else 0) | (BATCH_TUNE if autotune else 0), SCORERS[scorer],
                   int(bool(use_graph)), int(tile_rot), int(vote_parts),
-                  _stream_of(stream) if args.device else None)
+                  _stream_of(stream) if args.device else None, DF_LOOKUPS[df_lookup])
     res = (Result * len(problems))()
     st = (C.c_int32 * len(problems))()
     _check(lib().dses_register_batch(arr, len(problems), C.byref(o), res, st))
@@ -487,30 +497,55 @@ class Server:
         h = C.c_void_p()
         _check(lib().dses_server_create(C.byref(o), C.byref(h)))
         self.handle = h
+        self._pending = {}
 
-    def submit(self, target: Target, rotset: RotationSet, src, eps, metric="trunc_l2") -> int:
+    def submit(self, target: Target, rotset: RotationSet, src, eps, metric="trunc_l2", *,
+               delta_t=None, tau=None, t_min=None, t_max=None, scorer=None,
+               df_lookup="nearest", records=False, top_k=0) -> int:
+        """Queue a request (host source); per-request options as dses_server_submit
+        describes.  records / top_k buffers are kept here until wait() returns them."""
         a = np.ascontiguousarray(np.asarray(src, np.float32).reshape(-1, 3))
+        args = _Args()
+        args.device = False
+        rbuf, rptr = _records_buffer(args, rotset.k) if records else (None, None)
+        o = _options(args, delta_t, tau, t_min, t_max, scorer or "auto", False, None, rptr,
+                     df_lookup=df_lookup)
+        if scorer is None:
+            o.scorer = 0
+        tbuf = _topk_buffer(args, int(top_k), o)
         rid = C.c_uint64()
         _check(lib().dses_server_submit(self.handle, target.handle, rotset.handle,
                                         a.ctypes.data, len(a), C.c_float(eps), METRICS[metric],
-                                        C.byref(rid)))
+                                        C.byref(o), C.byref(rid)))
+        self._pending[int(rid.value)] = (args, rbuf, tbuf)
         return int(rid.value)
 
     def wait(self, req_id: int, timeout_ms: int = -1) -> Registration:
+        """Result of a request (consumes it); .queue_s / .total_s are its latencies."""
         res = Result()
         st = C.c_int32()
+        q, t = C.c_double(), C.c_double()
         _check(lib().dses_server_wait(self.handle, req_id, timeout_ms, C.byref(res),
-                                      C.byref(st)))
+                                      C.byref(st), C.byref(q), C.byref(t)))
+        _, rbuf, tbuf = self._pending.pop(req_id, (None, None, None))
         _check(st.value)
-        return _result(res)
+        out = _result(res, rbuf, tbuf)
+        out.queue_s, out.total_s = q.value, t.value
+        return out
 
     def poll(self, req_id: int) -> int:
         return int(lib().dses_server_poll(self.handle, req_id))
 
     def timing(self, req_id: int):
+        """(queue_s, total_s) of a finished request not yet consumed by wait()."""
         q, t = C.c_double(), C.c_double()
         _check(lib().dses_server_timing(self.handle, req_id, C.byref(q), C.byref(t)))
         return q.value, t.value
+
+    def cancel(self, req_id: int):
+        """Withdraw a request still in the queue (raises E_STATE once it is admitted)."""
+        _check(lib().dses_server_cancel(self.handle, req_id))
+        self._pending.pop(req_id, None)
 
     def close(self):
         if self.handle:

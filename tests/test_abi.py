@@ -87,6 +87,48 @@ def test_argument_errors_need_no_gpu(libpath):
     assert e.value.status == dses.DSES_E_INVAL
 
 
+def test_options_size_and_df_lookup_checked_on_the_host(libpath):
+    """dses_options is versioned by struct_size: a size below the oldest layout or
+    above the current one is rejected, the older layout (without df_lookup) is
+    accepted; an unknown df_lookup is rejected before any device work."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    from paper_2502_00115_amd import dses
+    L = dses.lib()
+    src = np.zeros((3, 3), np.float32)
+    tgt = np.zeros((4, 3), np.float32)
+    rot = np.eye(3, dtype=np.float32).reshape(1, 9)
+
+    def call(o):
+        res = dses.Result()
+        return L.dses_register(src.ctypes.data, 3, tgt.ctypes.data, 4, rot.ctypes.data, 1,
+                               C.c_float(0.05), 0, C.byref(o), C.byref(res))
+
+    o = dses.Options()
+    o.struct_size = C.sizeof(dses.Options)
+    o.df_lookup = 2
+    assert call(o) == dses.DSES_E_INVAL
+    for size in (8, C.sizeof(dses.Options) + 4):
+        o = dses.Options()
+        o.struct_size = size
+        assert call(o) == dses.DSES_E_INVAL, size
+    o = dses.Options()
+    o.struct_size = dses.Options.df_lookup.offset
+    o.df_lookup = 7            # not read: beyond the declared size
+    expect = dses.DSES_OK if torch.cuda.is_available() else dses.DSES_E_DEVICE
+    assert call(o) in (expect, dses.DSES_E_NOCANDIDATE)
+    bo = dses.BatchOpts(C.sizeof(dses.BatchOpts), 0, 0, 0, 0, 0, None, 5)
+    probs = (dses.Problem * 1)()
+    probs[0].src, probs[0].n = src.ctypes.data, 3
+    probs[0].tgt, probs[0].m = tgt.ctypes.data, 4
+    probs[0].rotations, probs[0].k = rot.ctypes.data, 1
+    probs[0].eps = 0.05
+    res = (dses.Result * 1)()
+    st = (C.c_int32 * 1)()
+    assert L.dses_register_batch(probs, 1, C.byref(bo), res, st) == dses.DSES_E_INVAL
+
+
 def test_no_device_is_a_loud_error(libpath):
     import numpy as np
     import torch

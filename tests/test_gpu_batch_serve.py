@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_2502_00115_amd import synth
-from parity import compare_records
+from parity import check_selection, compare_records
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -156,7 +156,7 @@ def test_server_memory_admission_serialises_when_budget_fits_one():
     res = [srv.wait(r, timeout_ms=60000) for r in ids]
     for (t, src), got in zip(reqs, res):
         _same(got, dses.register_resident(targets[t], rotset, src, 0.03))
-    timing = [srv.timing(r) for r in ids]
+    timing = [(g.queue_s, g.total_s) for g in res]
     # requests were admitted one after another: each later one waited in the queue
     for (q0, tot0), (q1, _) in zip(timing, timing[1:]):
         assert q1 >= q0
@@ -181,12 +181,146 @@ def test_server_poll_and_timeout():
     srv = dses.Server()
     rid = srv.submit(targets[0], rotset, reqs[0][1], 0.03)
     assert srv.poll(rid) in (0, 1)
-    got = srv.wait(rid, timeout_ms=60000)
+    while srv.poll(rid) == 0:
+        time.sleep(0.005)
     assert srv.poll(rid) == 1
-    assert got.rot_index >= 0
-    q, tot = srv.timing(rid)
+    q, tot = srv.timing(rid)            # finished, not yet consumed
     assert 0.0 <= q <= tot
+    got = srv.wait(rid, timeout_ms=60000)
+    assert got.rot_index >= 0 and got.queue_s == q and got.total_s == tot
+    # the wait consumed the request: its id is forgotten
+    assert srv.poll(rid) == dses.DSES_E_STATE
+    for call in (lambda: srv.wait(rid, timeout_ms=0), lambda: srv.timing(rid),
+                 lambda: srv.cancel(rid)):
+        with pytest.raises(dses.DsesError) as e:
+            call()
+        assert e.value.status == dses.DSES_E_STATE
     srv.close()
+
+
+def test_server_cancel_withdraws_a_queued_request():
+    targets, rotset, _, reqs = _serving_setup(n_req=3, k=256, seed=9)
+    # room for one request at a time: the later ones wait in the queue
+    need = max(((12 * len(s) + 255) // 256) * 256 + ((24 * 256 + 255) // 256) * 256
+               for _, s in reqs)
+    srv = dses.Server(memory_budget=need + 256)
+    ids = [srv.submit(targets[t], rotset, src, 0.03) for t, src in reqs]
+    srv.cancel(ids[2])
+    with pytest.raises(dses.DsesError) as e:
+        srv.wait(ids[2], timeout_ms=0)
+    assert e.value.status == dses.DSES_E_STATE
+    for rid, (t, src) in zip(ids[:2], reqs[:2]):
+        _same(srv.wait(rid, timeout_ms=60000),
+              dses.register_resident(targets[t], rotset, src, 0.03))
+    srv.close()
+
+
+def test_served_non_default_options_equal_alone():
+    """Per-request options (pitch, truncation, box, scorer, records, top-k) give the
+    result a lone resident registration gives with the same options."""
+    targets, rotset, rots, reqs = _serving_setup(n_targets=2, n_req=4, k=640, seed=10)
+    opts = [dict(delta_t=0.025, tau=0.04, t_min=[-0.8, -0.9, -0.7], t_max=[0.9, 0.8, 0.85]),
+            dict(scorer="brute", tau=0.05),
+            dict(delta_t=0.035, t_min=-0.6, t_max=0.6),
+            dict()]
+    srv = dses.Server()
+    ids = [srv.submit(targets[t], rotset, src, 0.03, "tls" if i == 1 else "trunc_l2",
+                      records=True, top_k=8, **o)
+           for i, ((t, src), o) in enumerate(zip(reqs, opts))]
+    for i, (rid, (t, src), o) in enumerate(zip(ids, reqs, opts)):
+        got = srv.wait(rid, timeout_ms=60000)
+        alone = dses.register_resident(targets[t], rotset, src, 0.03,
+                                       "tls" if i == 1 else "trunc_l2", records=True, top_k=8,
+                                       **{k: v for k, v in o.items()})
+        _same(got, alone)
+        assert got.records.tobytes() == alone.records.tobytes(), i
+        assert got.top.tobytes() == alone.top.tobytes(), i
+    srv.close()
+
+
+def test_served_df_mix_matches_oracle():
+    """Serving workload: requests of different sizes against two resident targets with
+    128^3 distance fields, the later ones submitted while earlier ones run.  Each
+    result equals its lone registration bit for bit; records on sampled rotations and
+    the selection match the oracle's distance-field scoring."""
+    rng = np.random.default_rng(12)
+    tg = synth.make_c4_targets(3, count=8)
+    pick = [int(np.argmin([len(t) for t, _ in tg])), int(np.argsort([len(t) for t, _ in tg])[1])]
+    tgts = [tg[i][0] for i in pick]
+    rots = synth.hopf_grid(3)[rng.permutation(36864)[:2048]].reshape(-1, 9).astype(np.float32)
+    eps = 0.03
+    targets = [dses.Target(t, df_trunc=eps, df_res=128) for t in tgts]
+    rotset = dses.RotationSet(rots)
+    shapes = [tg[i][1] for i in pick]
+    reqs = []
+    for i in range(5):
+        tid = i % 2
+        _, src = synth.make_c4_request(200 + i, [(tgts[tid], shapes[tid])])
+        reqs.append((tid, src))
+    assert len({len(s) for _, s in reqs}) == len(reqs)      # every request its own size
+    srv = dses.Server()
+    ids = [srv.submit(targets[t], rotset, src, eps, records=True) for t, src in reqs[:2]]
+    time.sleep(0.01)
+    ids += [srv.submit(targets[t], rotset, src, eps, records=True) for t, src in reqs[2:]]
+    served = [srv.wait(r, timeout_ms=120000) for r in ids]
+    srv.close()
+    fields = [oracle.df_build(t, eps, 128) for t in tgts]
+    for i, ((t, src), g) in enumerate(zip(reqs, served)):
+        alone = dses.register_resident(targets[t], rotset, src, eps, scorer="df", records=True)
+        _same(g, alone)
+        assert g.records.tobytes() == alone.records.tobytes(), i
+        recs = g.records
+        top = np.argsort(np.where(recs["votes"] > 0, recs["error"], np.inf))[:8]
+        which = np.unique(np.concatenate([rng.choice(len(rots), 40, replace=False), top]))
+        ref = oracle.records(src, tgts[t], rots, eps, which=which, df=fields[t])
+        rep = compare_records(recs[which], ref, len(src), label=f"served df {i}")
+        check_selection(g, rep, eps, label=f"served df {i}")
+
+
+def test_batch_with_distance_field_targets_matches_oracle():
+    """Batched registration against resident targets scored by their distance fields:
+    equal to lone calls, and sampled records and selections match the oracle's
+    distance-field scoring (nearest and trilinear lookups)."""
+    probs = _small_c3(count=4, k=384, seed=11)
+    eps = 0.03
+    fields = [oracle.df_build(p.tgt, eps, 64) for p in probs]
+    T = [dses.Target(p.tgt, df_trunc=eps, df_res=64) for p in probs]
+    S = [dses.RotationSet(p.rotations) for p in probs]
+    rng = np.random.default_rng(2)
+    for lookup in ("nearest", "trilinear"):
+        got, st = dses.register_batch([{"src": p.src, "target": t, "rotset": s, "eps": eps}
+                                       for p, t, s in zip(probs, T, S)], scorer="df",
+                                      records=True, df_lookup=lookup)
+        assert st == [0] * len(probs)
+        for p, t, s, g, df in zip(probs, T, S, got, fields):
+            alone = dses.register_resident(t, s, p.src, eps, scorer="df", records=True,
+                                           df_lookup=lookup)
+            _same(g, alone)
+            assert g.records.tobytes() == alone.records.tobytes()
+            top = np.argsort(np.where(g.records["votes"] > 0, g.records["error"], np.inf))[:8]
+            which = np.unique(np.concatenate([rng.choice(len(p.rotations), 48, replace=False),
+                                              top]))
+            ref = oracle.records(p.src, p.tgt, p.rotations, eps, which=which, df=df,
+                                 df_lookup=lookup)
+            rep = compare_records(g.records[which], ref, len(p.src), label=f"{p.name} {lookup}")
+            check_selection(g, rep, eps, label=f"{p.name} {lookup}")
+
+
+@pytest.mark.slow
+def test_c3_selection_over_full_grids_matches_oracle():
+    """Four instances of the 64-registration batch, every rotation of their grids
+    compared with the oracle and each selection inside the oracle's admissible set."""
+    probs = synth.make_c3(0)
+    got, st = dses.register_batch([_as_dict(p) for p in probs], records=True)
+    assert st == [0] * len(probs)
+    cost = [len(p.src) * len(p.tgt) * len(p.rotations) for p in probs]
+    for i in np.argsort(cost)[:4]:
+        p, g = probs[i], got[i]
+        ref = oracle.records(p.src, p.tgt, p.rotations, p.eps)
+        rep = compare_records(g.records, ref, len(p.src), label=p.name)
+        nW = check_selection(g, rep, p.eps, label=p.name)
+        print(f"{p.name}: n {len(p.src)} m {len(p.tgt)} k {len(p.rotations)} rot {g.rot_index} "
+              f"|W| {nW} ambiguous {rep['ambiguous']} moved {rep['moved']}")
 
 
 def test_server_many_concurrent_clients():

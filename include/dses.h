@@ -36,15 +36,23 @@
  *     k_lo_a = ceil(t_min_a/delta - 1e-4),  k_hi_a = floor(t_max_a/delta + 1e-4)
  * (double precision), size_a = k_hi_a - k_lo_a + 1.  A pair votes for the nearest
  * lattice point, halves rounded up: b_a = floor((y_a - p_a)/delta + 1/2) with
- * p = R x (Lemma 2, Eq. (5)), and only if b lies in the box.  The kernels evaluate
- * this in IEEE single precision (the paper fixes no precision), as
- *     s    = 1.0f / delta
- *     p_a  = fmaf(R[a][2], x_z, fmaf(R[a][1], x_y, R[a][0] * x_x))
- *     Y_a  = (y_a * s) + (0.5f - (float)k_lo_a)          (two roundings, no fma)
- *     c_a  = floorf(Y_a - p_a * s)                        (box-relative bin)
- * voting iff 0 <= c_a < size_a on every axis; so a pair whose exact u + 1/2 lies
- * within float rounding (about 1e-5 bin units at the workloads' magnitudes) of an
- * integer may be counted in the neighbouring bin.  The mode is the bin with the
+ * p = R x (Lemma 2, Eq. (5)), and only if b lies in the box.  The kernels take
+ * this decision on integers (the paper fixes no precision).  With
+ * S_F = (1/delta) 2^F in double, F = 16 on x and y, and on z F = 15 when the
+ * counters are 16-bit (the library proves no bin can reach 2^16 votes) or 16:
+ *     Y_a = rint(y_a S_F + (1/2 - k_lo_a) 2^F)            (reference, once)
+ *     p_a = (R[a][0] x_x + R[a][1] x_y) + R[a][2] x_z     (double, per rotation)
+ *     P_a = rint(p_a S_F), saturated at +-2^30 (no such source value can vote)
+ *     c_a = floor((Y_a - P_a) / 2^F)                      (box-relative bin)
+ * every product and sum one rounded double operation, rint rounding halves to
+ * even, the difference exact int32 arithmetic; a pair votes iff
+ * 0 <= c_a < size_a on every axis.  Each rounding moves u + 1/2 by at most half
+ * a unit, so a pair whose exact u + 1/2 lies within 2^-F bins (at most 3.1e-5) of an
+ * integer may be counted in the neighbouring bin.  The integers stay apart in 32
+ * bits because every reference coordinate is limited to |y| <= (2^13 - K - 8)
+ * delta (K the largest |k_lo_a| or |k_lo_a + size_a|; at most 1e4) and every
+ * source coordinate to |x| <= 1e4: larger ones are rejected with DSES_E_INVAL.
+ * The mode is the bin with the
  * largest count; ties go to the lowest linear index
  * ((c_x * size_y + c_y) * size_z + c_z).  The returned translation is
  * t_a = (float)(c_a + k_lo_a) * delta (no refinement: the paper's answer is exact

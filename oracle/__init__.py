@@ -32,6 +32,8 @@ from .build import LIB, build_oracle
 
 METRICS = {"trunc_l2": 0, "inliers": 1, "tls": 2, "trunc_l1": 3, "trunc_lp": 4, "votes": 5}
 DF_LOOKUPS = {"nearest": 0, "trilinear": 1}
+# vote= of records(): the definition, or the library's formulas with z at 2^-15 / 2^-16 bins
+_LIB_ZBITS = {"f64": 0, "lib": 15, "lib32": 16}
 
 RECORD_DTYPE = np.dtype([("bin", "<i4", (3,)), ("votes", "<u4"), ("inliers", "<i4"),
                          ("boundary", "<i4"), ("error", "<f8"), ("valid", "<i4"),
@@ -58,8 +60,8 @@ def lib():
         L.orc_box.restype = C.c_int
         L.orc_vote64.argtypes = [fp, i32, fp, i32, fp, f32, f64, ip, ip, up, up, up, ip]
         L.orc_vote64.restype = C.c_int
-        L.orc_vote_f32.argtypes = [fp, i32, fp, i32, fp, f32, ip, ip, up, ip]
-        L.orc_vote_f32.restype = C.c_uint32
+        L.orc_vote_lib.argtypes = [fp, i32, fp, i32, fp, f32, i32, ip, ip, up, ip]
+        L.orc_vote_lib.restype = C.c_uint32
         L.orc_nn.argtypes = [dp, i32, fp, i32, i32, dp]
         L.orc_nn.restype = None
         L.orc_df_build.argtypes = [fp, i32, f32, i32, i32, fp, fp, fp, dp]
@@ -113,19 +115,18 @@ def box(delta, t_min=None, t_max=None):
 # fragility margins
 # ---------------------------------------------------------------------------
 def vote_margin(src, tgt, delta, t_min=None, t_max=None):
-    """Fragility margin mu of the bin decision, in bin units.
+    """Fragility margin mu of the bin decision, in bin units: 1e-4.
 
-    A float32 evaluation of (y - R x)/delta + 1/2 relative to the box origin
-    takes a handful of roundings, each at most 2^-24 times a magnitude bounded
-    by (|y| + |x| + |t|)/delta (|R x| = |x|; t the box corner).  Counting 32
-    such roundings bounds the error with a wide margin; mu is never below
-    1e-4 bin units.
+    The library takes the decision on integers: the reference coordinate y/delta
+    + 1/2 - k_lo and the rotated source coordinate (R x)/delta, each evaluated in
+    double and rounded to a multiple of 2^-16 bins (2^-15 on z with 16-bit
+    counters), are subtracted exactly.  Each rounding moves a value by at most half
+    a unit, so u + 1/2 is off by at most 2^-15 bins plus double rounding (below
+    1e-9 bins at any admitted coordinate), whatever the magnitudes: mu = 1e-4
+    covers it three times over.  The arguments are kept for the callers that pass
+    a problem; the margin does not depend on them.
     """
-    t_min, t_max = _box_args(t_min, t_max)
-    mag = (float(np.abs(_f32(tgt)).max(initial=0.0))
-           + float(np.linalg.norm(_f32(src, 3).astype(np.float64), axis=1).max(initial=0.0))
-           + float(max(np.abs(t_min).max(), np.abs(t_max).max())))
-    return max(1e-4, 32 * _U32 * mag / float(np.float32(delta)))
+    return 1e-4
 
 
 def df_margin(src, df, t_min=None, t_max=None):
@@ -171,16 +172,17 @@ def vote64(src, tgt, R, delta, t_min=None, t_max=None, mu=None):
                            "k_lo": k_lo, "size": size}
 
 
-def vote_f32(src, tgt, R, delta, t_min=None, t_max=None):
-    """SECONDARY: the vote by the library's documented single-precision bin formula
-    (dense counts, mode, M).  Used only for a labelled bit-exactness check."""
+def vote_lib(src, tgt, R, delta, t_min=None, t_max=None, zbits=15):
+    """SECONDARY: the vote by the library's documented fixed-point bin formula, z at
+    2^-zbits bins (15 with 16-bit counters, 16 with 32-bit ones): dense counts,
+    mode, M.  Used only for a labelled bit-exactness check."""
     src, tgt = _f32(src, 3), _f32(tgt, 3)
     R = _f32(R).reshape(9)
     k_lo, size = box(delta, t_min, t_max)
     hist = np.zeros(tuple(int(s) for s in size), np.uint32)
     mode = np.zeros(3, np.int32)
-    M = lib().orc_vote_f32(_p(src, C.c_float), len(src), _p(tgt, C.c_float), len(tgt),
-                           _p(R, C.c_float), C.c_float(delta), _p(k_lo, C.c_int32),
+    M = lib().orc_vote_lib(_p(src, C.c_float), len(src), _p(tgt, C.c_float), len(tgt),
+                           _p(R, C.c_float), C.c_float(delta), int(zbits), _p(k_lo, C.c_int32),
                            _p(size, C.c_int32), _p(hist, C.c_uint32), _p(mode, C.c_int32))
     return hist, mode, int(M)
 
@@ -261,7 +263,8 @@ def records(src, tgt, rotations, eps, *, delta=None, tau=None, t_min=None, t_max
     """One Alg. 2 candidate record per rotation (or per listed rotation index).
 
     vote="f64" (default): the definition in double with fragility intervals;
-    vote="f32": the SECONDARY single-precision formula (pinned everywhere)."""
+    vote="lib" / "lib32": the SECONDARY library formulas (fixed-point bins with z at
+    2^-15 / 2^-16 bins, single-precision voxels), for labelled bit-exactness checks."""
     src, tgt = _f32(src, 3), _f32(tgt, 3)
     rots = _f32(rotations, 9)
     delta = eps if delta is None else delta
@@ -283,7 +286,7 @@ def records(src, tgt, rotations, eps, *, delta=None, tau=None, t_min=None, t_max
                            None if which is None else _p(which, C.c_int32), count,
                            C.c_float(eps), C.c_float(delta), C.c_float(tau),
                            _p(t_min, C.c_float), _p(t_max, C.c_float), METRICS[metric],
-                           C.c_float(p), C.c_double(mu), int(vote == "f32"), fld_p, res, lo_p,
+                           C.c_float(p), C.c_double(mu), _LIB_ZBITS[vote], fld_p, res, lo_p,
                            h_p, inv_p, DF_LOOKUPS[df_lookup], C.c_double(mu_df), threads,
                            out.ctypes.data)
     if rc:
@@ -312,7 +315,7 @@ def score_bins(ctx, rot, bins, threads=0):
                               _p(bins, C.c_int32), len(rot), C.c_float(ctx["eps"]),
                               C.c_float(ctx["delta"]), C.c_float(ctx["tau"]),
                               METRICS[ctx["metric"]], C.c_float(ctx["p"]),
-                              int(ctx["vote"] == "f32"), fld_p, res, lo_p, h_p, inv_p,
+                              _LIB_ZBITS[ctx["vote"]], fld_p, res, lo_p, h_p, inv_p,
                               DF_LOOKUPS[ctx["df_lookup"]], C.c_double(ctx["mu_df"]),
                               threads or ctx["threads"], out.ctypes.data)
     if rc:

@@ -29,8 +29,9 @@
  * floor((q - lo)/h) in double, and a coordinate within mu_df voxel units of a
  * voxel face makes the point's value an interval over the voxels it may fall in.
  *
- * A secondary mode (vote_f32 = 1) takes both decisions instead by the library's
- * documented single-precision formulas (bin_of_pair_f32, df_voxel_of_f32 below).
+ * A secondary mode (lib_zbits = 15 or 16) takes both decisions instead by the
+ * library's documented formulas: the fixed-point bin decision with z at 2^-lib_zbits
+ * bins (lib_bin_of_pair) and the single-precision voxel decision (df_voxel_of_f32).
  * It exists only for a labelled, secondary bit-exactness check; every parity
  * claim rests on the double-precision definition.
  *
@@ -232,53 +233,61 @@ int orc_vote64(const float *src, int32_t n, const float *tgt, int32_t m, const f
 }
 
 /* ------------------------------------------------------------------------ */
-/* SECONDARY CHECK ONLY: the library's documented single-precision form of   */
-/* the bin decision,                                                         */
-/*   s = 1/delta, p_a = fma(R_a2, x_z, fma(R_a1, x_y, R_a0 * x_x)),           */
-/*   Y_a = (y_a * s) + (0.5 - k_lo_a), c_a = floor(Y_a - p_a * s)             */
-/* (box-relative).  It agrees with the definition except for pairs within    */
-/* float rounding of a face; it is used for a labelled bit-exactness check   */
-/* of the kernel's arithmetic, never for parity.                             */
+/* SECONDARY CHECK ONLY: the library's documented fixed-point form of the    */
+/* bin decision.  With S_F = (1/delta) 2^F in double (F = 16 on x and y,     */
+/* F = zbits on z),                                                          */
+/*   Y_a = rint(y_a S_F + (1/2 - k_lo_a) 2^F),                               */
+/*   p_a = (R_a0 x_x + R_a1 x_y) + R_a2 x_z,                                 */
+/*   P_a = rint(p_a S_F clamped to [-2^30, 2^30]),                           */
+/*   c_a = floor((Y_a - P_a) / 2^F)           (box-relative),                 */
+/* every product and sum one rounded double operation, rint rounding halves  */
+/* to even.  It agrees with the definition except for pairs within 2^-zbits   */
+/* bins of a face; it is used for a labelled bit-exactness check of the      */
+/* kernel's arithmetic, never for parity.                                    */
 /* ------------------------------------------------------------------------ */
-static void rotate_f32(const float *R, const float *x, float *p)
+static int32_t q_rint(double v) { return (int32_t)nearbyint(v); }
+
+static void lib_quant_src(const float *R, const float *x, const double *S, int32_t *P)
 {
     for (int a = 0; a < 3; ++a) {
-        float acc = R[3 * a + 0] * x[0];
-        acc = fmaf(R[3 * a + 1], x[1], acc);
-        acc = fmaf(R[3 * a + 2], x[2], acc);
-        p[a] = acc;
+        double p = (double)R[3 * a + 0] * (double)x[0];
+        p = p + (double)R[3 * a + 1] * (double)x[1];
+        p = p + (double)R[3 * a + 2] * (double)x[2];
+        double v = p * S[a];
+        v = v < -1073741824.0 ? -1073741824.0 : (v > 1073741824.0 ? 1073741824.0 : v);
+        P[a] = q_rint(v);
     }
 }
 
-static int bin_of_pair_f32(const float *y, const float *p, float s, const int32_t *k_lo,
-                           const int32_t *size, int32_t *c)
+static int lib_bin_of_pair(const float *y, const int32_t *P, const double *S, const int *F,
+                           const int32_t *k_lo, const int32_t *size, int32_t *c)
 {
     int inside = 1;
     for (int a = 0; a < 3; ++a) {
-        float ofs = 0.5f - (float)k_lo[a];
-        float Y = y[a] * s;
-        Y = Y + ofs;
-        float P = p[a] * s;
-        float u = Y - P;
-        c[a] = (int32_t)floorf(u);
+        double v = (double)y[a] * S[a];
+        v = v + (0.5 - (double)k_lo[a]) * ldexp(1.0, F[a]);
+        const int64_t D = (int64_t)q_rint(v) - (int64_t)P[a];
+        c[a] = (int32_t)(D >> F[a]);          /* floor: arithmetic shift */
         if (c[a] < 0 || c[a] >= size[a]) inside = 0;
     }
     return inside;
 }
 
-uint32_t orc_vote_f32(const float *src, int32_t n, const float *tgt, int32_t m, const float *R,
-                      float delta, const int32_t *k_lo, const int32_t *size, uint32_t *hist,
-                      int32_t *mode_bin)
+uint32_t orc_vote_lib(const float *src, int32_t n, const float *tgt, int32_t m, const float *R,
+                      float delta, int32_t zbits, const int32_t *k_lo, const int32_t *size,
+                      uint32_t *hist, int32_t *mode_bin)
 {
     const size_t nbins = (size_t)size[0] * size[1] * size[2];
-    const float s = 1.0f / delta;
+    const double s = 1.0 / (double)delta;
+    const int F[3] = {16, 16, zbits};
+    const double S[3] = {s * 65536.0, s * 65536.0, s * ldexp(1.0, zbits)};
     memset(hist, 0, nbins * sizeof(uint32_t));
     for (int32_t i = 0; i < n; ++i) {
-        float p[3];
-        rotate_f32(R, src + 3 * i, p);
+        int32_t P[3];
+        lib_quant_src(R, src + 3 * i, S, P);
         for (int32_t j = 0; j < m; ++j) {
             int32_t c[3];
-            if (bin_of_pair_f32(tgt + 3 * j, p, s, k_lo, size, c))
+            if (lib_bin_of_pair(tgt + 3 * j, P, S, F, k_lo, size, c))
                 hist[((size_t)c[0] * size[1] + c[1]) * size[2] + c[2]] += 1;
         }
     }
@@ -288,6 +297,18 @@ uint32_t orc_vote_f32(const float *src, int32_t n, const float *tgt, int32_t m, 
         if (hist[l] > best) { best = hist[l]; arg = l; }
     bin_of_lin(arg, k_lo, size, mode_bin);
     return best;
+}
+
+/* The library's single-precision rotation of a source point for scoring,
+   p_a = fma(R_a2, x_z, fma(R_a1, x_y, R_a0 * x_x)) (secondary checks only). */
+static void rotate_f32(const float *R, const float *x, float *p)
+{
+    for (int a = 0; a < 3; ++a) {
+        float acc = R[3 * a + 0] * x[0];
+        acc = fmaf(R[3 * a + 1], x[1], acc);
+        acc = fmaf(R[3 * a + 2], x[2], acc);
+        p[a] = acc;
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -598,9 +619,9 @@ static void score_candidate_df_f32(const float *src, int32_t n, const float *R, 
 /* Score one candidate {R, delta * bin} with the chosen scorer. */
 static void score_bin(const float *src, int32_t n, const float *tgt, int32_t m, const float *R,
                       const int32_t *bin, float delta, int metric, double eps, double tau,
-                      double lp, const df_view *f, int vote_f32, orc_record *rec)
+                      double lp, const df_view *f, int lib_zbits, orc_record *rec)
 {
-    if (f->field && vote_f32) {
+    if (f->field && lib_zbits) {
         float tf[3];
         for (int a = 0; a < 3; ++a) tf[a] = (float)bin[a] * delta;
         score_candidate_df_f32(src, n, R, tf, metric, eps, tau, lp, f, rec);
@@ -621,7 +642,7 @@ typedef struct {
     const float *src; int32_t n; const float *tgt; int32_t m;
     const float *rots; const int32_t *which; const int32_t *bins;
     float delta; double mu; const int32_t *k_lo; const int32_t *size;
-    int metric; double eps, tau, lp; int vote_f32;
+    int metric; double eps, tau, lp; int lib_zbits;
     df_view f;
     orc_record *out;
     int32_t begin, end;
@@ -641,9 +662,9 @@ static void *reg_worker(void *arg)
         orc_record *rec = &jb->out[u];
         memset(rec, 0, sizeof(*rec));
         rec->rot = k;
-        if (jb->vote_f32) {
-            rec->votes = orc_vote_f32(jb->src, jb->n, jb->tgt, jb->m, R, jb->delta, jb->k_lo,
-                                      jb->size, cnt, rec->bin);
+        if (jb->lib_zbits) {
+            rec->votes = orc_vote_lib(jb->src, jb->n, jb->tgt, jb->m, R, jb->delta, jb->lib_zbits,
+                                      jb->k_lo, jb->size, cnt, rec->bin);
             rec->votes_lo = rec->votes_hi = rec->lo_max = rec->votes;
             rec->pinned = 1;
         } else {
@@ -667,7 +688,7 @@ static void *reg_worker(void *arg)
             continue;
         }
         score_bin(jb->src, jb->n, jb->tgt, jb->m, R, rec->bin, jb->delta, jb->metric, jb->eps,
-                  jb->tau, jb->lp, &jb->f, jb->vote_f32, rec);
+                  jb->tau, jb->lp, &jb->f, jb->lib_zbits, rec);
     }
     free(cnt);
     free(outf);
@@ -689,7 +710,7 @@ static void *bins_worker(void *arg)
         rec->valid = 1;
         rec->pinned = 1;
         score_bin(jb->src, jb->n, jb->tgt, jb->m, jb->rots + 9 * (size_t)k, rec->bin, jb->delta,
-                  jb->metric, jb->eps, jb->tau, jb->lp, &jb->f, jb->vote_f32, rec);
+                  jb->metric, jb->eps, jb->tau, jb->lp, &jb->f, jb->lib_zbits, rec);
     }
     return NULL;
 }
@@ -719,7 +740,7 @@ static int run_jobs(reg_job *proto, int32_t count, int32_t nthreads, void *(*fn)
 static int job_setup(reg_job *jb, const float *src, int32_t n, const float *tgt, int32_t m,
                      const float *rots, int32_t k, const int32_t *which, int32_t count,
                      float eps, float delta, float tau, int32_t metric, float lp, double mu,
-                     int32_t vote_f32, const double *field, int32_t res, const float *lo,
+                     int32_t lib_zbits, const double *field, int32_t res, const float *lo,
                      const float *h, const float *inv, int32_t df_lookup, double mu_df,
                      int32_t *k_lo, int32_t *size, const float *t_min, const float *t_max)
 {
@@ -727,6 +748,7 @@ static int job_setup(reg_job *jb, const float *src, int32_t n, const float *tgt,
     if (metric < ORC_TRUNC_L2 || metric > ORC_VOTES || !(lp > 0.0f && lp <= 1.0f)) return -1;
     if (!(mu >= 0.0 && mu < 0.5) || !(mu_df >= 0.0 && mu_df < 0.5)) return -1;
     if (df_lookup != ORC_DF_NEAREST && df_lookup != ORC_DF_TRILINEAR) return -1;
+    if (lib_zbits != 0 && lib_zbits != 15 && lib_zbits != 16) return -1;
     if (orc_box(delta, t_min, t_max, k_lo, size)) return -1;
     if (which)
         for (int32_t u = 0; u < count; ++u)
@@ -734,7 +756,7 @@ static int job_setup(reg_job *jb, const float *src, int32_t n, const float *tgt,
     memset(jb, 0, sizeof(*jb));
     jb->src = src; jb->n = n; jb->tgt = tgt; jb->m = m; jb->rots = rots; jb->which = which;
     jb->delta = delta; jb->mu = mu; jb->k_lo = k_lo; jb->size = size; jb->metric = metric;
-    jb->eps = eps; jb->tau = tau; jb->lp = lp; jb->vote_f32 = vote_f32;
+    jb->eps = eps; jb->tau = tau; jb->lp = lp; jb->lib_zbits = lib_zbits;
     jb->f = (df_view){field, res, eps > tau ? eps : tau, lo, h, inv, df_lookup, mu_df};
     return 0;
 }
@@ -743,21 +765,21 @@ static int job_setup(reg_job *jb, const float *src, int32_t n, const float *tgt,
  * Run Alg. 2 on the rotations listed in `which` (NULL: all k of them), writing one
  * record per listed rotation.  `field` != NULL selects distance-field scoring with
  * the grid from orc_df_build() (df_lookup: 0 nearest voxel, 1 trilinear).  mu and
- * mu_df are the fragility margins in bin and voxel units.  vote_f32 = 1 selects
- * the secondary single-precision formulas.  Returns 0, or -1 on invalid input or
- * no memory.
+ * mu_df are the fragility margins in bin and voxel units.  lib_zbits = 15 or 16 selects
+ * the secondary library formulas (0: the definition).  Returns 0, or -1 on invalid
+ * input or no memory.
  */
 int orc_records(const float *src, int32_t n, const float *tgt, int32_t m, const float *rots,
                 int32_t k, const int32_t *which, int32_t count, float eps, float delta, float tau,
                 const float *t_min, const float *t_max, int32_t metric, float lp, double mu,
-                int32_t vote_f32, const double *field, int32_t res, const float *lo,
+                int32_t lib_zbits, const double *field, int32_t res, const float *lo,
                 const float *h, const float *inv, int32_t df_lookup, double mu_df,
                 int32_t nthreads, orc_record *out)
 {
     int32_t k_lo[3], size[3];
     reg_job jb;
     if (job_setup(&jb, src, n, tgt, m, rots, k, which, count, eps, delta, tau, metric, lp, mu,
-                  vote_f32, field, res, lo, h, inv, df_lookup, mu_df, k_lo, size, t_min, t_max))
+                  lib_zbits, field, res, lo, h, inv, df_lookup, mu_df, k_lo, size, t_min, t_max))
         return -1;
     if (!which) count = k;
     jb.out = out;
@@ -767,7 +789,7 @@ int orc_records(const float *src, int32_t n, const float *tgt, int32_t m, const 
 /* Score the candidates {R_which[u], delta * bins[u]} (no vote); one record each. */
 int orc_score_bins(const float *src, int32_t n, const float *tgt, int32_t m, const float *rots,
                    int32_t k, const int32_t *which, const int32_t *bins, int32_t count,
-                   float eps, float delta, float tau, int32_t metric, float lp, int32_t vote_f32,
+                   float eps, float delta, float tau, int32_t metric, float lp, int32_t lib_zbits,
                    const double *field, int32_t res, const float *lo, const float *h,
                    const float *inv, int32_t df_lookup, double mu_df, int32_t nthreads,
                    orc_record *out)
@@ -777,7 +799,7 @@ int orc_score_bins(const float *src, int32_t n, const float *tgt, int32_t m, con
     reg_job jb;
     if (!which || !bins || metric == ORC_VOTES) return -1;
     if (job_setup(&jb, src, n, tgt, m, rots, k, which, count, eps, delta, tau, metric, lp, 0.0,
-                  vote_f32, field, res, lo, h, inv, df_lookup, mu_df, k_lo, size, wide_lo,
+                  lib_zbits, field, res, lo, h, inv, df_lookup, mu_df, k_lo, size, wide_lo,
                   wide_hi))
         return -1;
     jb.bins = bins;

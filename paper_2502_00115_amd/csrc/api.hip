@@ -176,7 +176,7 @@ dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, i
     g->n = n;
     g->m = m;
     g->delta = p.delta;
-    g->s = 1.0f / p.delta;
+    lattice_scales(p.delta, &g->S16, &g->S15);
     g->eps = p.eps;
     g->tau = p.tau;
     g->r = p.r;
@@ -198,6 +198,7 @@ dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, i
     g->pps = (int32_t)pps;
     g->nslabs = (int32_t)nslabs;
     g->slab_words = (int32_t)(pps * plane_words);
+    g->wide = 4 * plane_words > 0xFFFF ? 1 : 0;
     return DSES_OK;
 }
 
@@ -337,12 +338,16 @@ dses_status build_grid(const float *tgt, int32_t m, float r, HostGrid *out)
 // ---------------------------------------------------------------------------
 // host-side input checks
 // ---------------------------------------------------------------------------
-float coord_limit(const Params &p)
+// The fixed-point vote needs every staged reference value |y s + 1/2 - k_lo|
+// below 2^13 bins, so that every pair difference and the padding values stay
+// apart in 32 bits (a rotated source value is saturated at 2^14 bins instead:
+// beyond it no pair with such a reference can land in the box).
+float ref_coord_limit(const Params &p)
 {
     int32_t kmax = 0;
     for (int a = 0; a < 3; ++a)
         kmax = std::max(kmax, std::max(std::abs(p.klo[a]), std::abs(p.klo[a] + p.size[a])));
-    const double lim = ((double)(1 << 22) - kmax - 4.0) * (double)p.delta / 4.0;
+    const double lim = ((double)(1 << 13) - kmax - 8.0) * (double)p.delta;
     return (float)std::min(std::max(lim, 0.0), 1.0e4);
 }
 
@@ -350,7 +355,7 @@ static dses_status check_host_inputs(const float *src, int64_t n, const float *t
                                      const float *rot, int64_t k, float limit)
 {
     for (int64_t e = 0; e < 3 * n; ++e)
-        if (!(std::fabs(src[e]) <= limit)) {
+        if (!(std::fabs(src[e]) <= kSrcCoordLimit)) {
             set_error("source coordinate is non-finite or too large for the lattice");
             return DSES_E_INVAL;
         }
@@ -401,38 +406,51 @@ void sort_by_x(const float *tgt, int32_t m, std::vector<int32_t> *perm)
     for (int32_t j = 0; j < m; ++j) (*perm)[j] = kv[j].second;
 }
 
-bool ref_x_range(const float *tgt, const std::vector<int32_t> &perm, float s, int32_t klo_x,
+void lattice_scales(float delta, double *S16, double *S15)
+{
+    const double s = 1.0 / (double)delta;
+    *S16 = s * 65536.0;
+    *S15 = s * 32768.0;
+}
+
+// The staging arithmetic of one reference x coordinate (two rounded double
+// operations, then to the nearest integer, halves to even).
+static int32_t stage_x(float y, double S16, int32_t klo_x)
+{
+    double v = (double)y * S16;
+    v = v + (0.5 - (double)klo_x) * 65536.0;
+    return (int32_t)std::nearbyint(v);
+}
+
+bool ref_x_range(const float *tgt, const std::vector<int32_t> &perm, float delta, int32_t klo_x,
                  int32_t *ylo, int32_t *yhi)
 {
     if (perm.empty()) return false;
-    const float ofs = 0.5f - (float)klo_x;
-    const float first = tgt[3 * (size_t)perm.front()] * s;
-    const float last = tgt[3 * (size_t)perm.back()] * s;
-    const double lo = std::floor((double)(first + ofs));
-    const double hi = std::floor((double)(last + ofs));
-    if (!(hi - lo < (double)(1 << 20))) return false;
-    *ylo = (int32_t)lo;
-    *yhi = (int32_t)hi;
-    return true;
+    double S16, S15;
+    lattice_scales(delta, &S16, &S15);
+    *ylo = stage_x(tgt[3 * (size_t)perm.front()], S16, klo_x);
+    *yhi = stage_x(tgt[3 * (size_t)perm.back()], S16, klo_x);
+    return *yhi >= *ylo;
 }
 
-void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, float *sb_scale,
+void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, int32_t *sb_lo, int32_t *sb_shift,
                     int32_t *sb_n)
 {
-    // a source votes only if some Y - P lies in [0, size_x): P in (ylo - size_x, yhi + 1)
-    const double lo = (double)ylo - size_x - 1;
-    const double range = (double)yhi + 2 - lo;
+    // a source votes only if some Y - P lies in [0, size_x 2^16): P in
+    // (ylo - size_x 2^16, yhi]
+    const int64_t lo = (int64_t)ylo - ((int64_t)size_x << 16) + 1;
+    const int64_t range = (int64_t)yhi - lo + 1;
     // 16 buckets per bin when the range fits: window ends are rounded to a bucket,
     // and finer buckets measured faster up to 16 (4,096-point sources against
     // 16,384 points: 2.4% against 4 per bin; 717 against 1,024: 0.3%; 32 per bin
     // no better, 64 slower)
-    double scale = 16.0;
-    while (range * scale > kSrcBuckets && scale > 1.0 / (1 << 20)) scale *= 0.5;
-    *sb_lo = (float)lo;
-    *sb_scale = (float)scale;
+    int shift = 12;
+    while ((range >> shift) + 1 > kSrcBuckets && shift < 31) ++shift;
+    *sb_lo = (int32_t)lo;
+    *sb_shift = shift;
     // only as many buckets as the range needs (the sort clears and scans them all)
-    const int need = (int)std::ceil(range * scale) + 1;
-    *sb_n = std::min(kSrcBuckets, (need + kBlock - 1) / kBlock * kBlock);
+    const int64_t need = (range >> shift) + 2;
+    *sb_n = (int32_t)std::min<int64_t>(kSrcBuckets, (need + kBlock - 1) / kBlock * kBlock);
 }
 
 dses_status apply_metric_options(const dses_options &o, Params *p)
@@ -524,7 +542,7 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
                                 hipMemcpyDeviceToHost, stream));
         DSES_HIP(hipStreamSynchronize(stream));
         for (float v : host_copy)
-            if (!(std::fabs(v) <= coord_limit(p))) {
+            if (!(std::fabs(v) <= ref_coord_limit(p))) {
                 set_error("reference coordinate is non-finite or too large for the lattice");
                 return DSES_E_INVAL;
             }
@@ -537,9 +555,9 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     Geom g;
     if ((st = plan_geom(c, p, job.n, job.m, counter_bits, &g)) != DSES_OK) return st;
 
-    // Reference sorted by x, and a table over its scaled x coordinate
-    // (ys_x = y_x * s + (0.5 - k_lo_x), the same float arithmetic as the staging
-    // kernel) so each wave can restrict its vote loop to reachable points.
+    // Reference sorted by x, and the range of its staged fixed-point x coordinate
+    // (the same arithmetic as the staging kernel) for the source buckets, so each
+    // wave can restrict its vote loop to reachable points.
     std::vector<int32_t> perm_local;
     const std::vector<int32_t> *perm = nullptr;
     if (job.target) {
@@ -552,16 +570,16 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
         perm = &perm_local;
     }
     int32_t ylo = 0, yhi = 0;
-    const bool sorted = job.n <= kSortMax && ref_x_range(ht, *perm, g.s, p.klo[0], &ylo, &yhi);
+    const bool sorted = job.n <= kSortMax && ref_x_range(ht, *perm, p.delta, p.klo[0], &ylo, &yhi);
     const int grid = std::max(1, std::min(job.k, c->n_cu));
     if ((st = c->perm.ensure(m * sizeof(int32_t))) != DSES_OK) return st;
     DSES_HIP(hipMemcpyAsync(c->perm.ptr, perm->data(), m * sizeof(int32_t),
                             hipMemcpyHostToDevice, stream));
     if (sorted &&
-        (st = c->scratch.ensure((size_t)grid * slot_floats(job.n) * sizeof(float))) != DSES_OK)
+        (st = c->scratch.ensure((size_t)grid * slot_words(job.n) * sizeof(int32_t))) != DSES_OK)
         return st;
 
-    if ((st = c->ys.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
+    if ((st = c->yq.ensure(4 * m * sizeof(int32_t))) != DSES_OK) return st;
     if ((st = c->yt.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
     if ((st = c->rec.ensure((size_t)job.k * sizeof(dses_record))) != DSES_OK) return st;
     if ((st = c->res.ensure(sizeof(DevResult))) != DSES_OK) return st;
@@ -571,16 +589,16 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     SweepArgs a{};
     a.src = job.src;
     a.rot = job.rot;
-    a.ys = static_cast<float *>(c->ys.ptr);
+    a.yq = static_cast<int32_t *>(c->yq.ptr);
     a.yt = static_cast<float *>(c->yt.ptr);
     a.rec = static_cast<dses_record *>(c->rec.ptr);
     a.k = job.k;
     a.g = g;
-    a.scratch = sorted ? static_cast<float *>(c->scratch.ptr) : nullptr;
+    a.scratch = sorted ? static_cast<int32_t *>(c->scratch.ptr) : nullptr;
     a.scratch_stride = job.n;
-    source_buckets(ylo, yhi, g.size[0], &a.sb_lo, &a.sb_scale, &a.sb_n);
+    source_buckets(ylo, yhi, g.size[0], &a.sb_lo, &a.sb_shift, &a.sb_n);
     a.lane_group = o.lane_group;
-    a.ref_x_extent = (float)(yhi - ylo) + 1.0f;
+    a.ref_x_extent = ref_x_extent(ylo, yhi);
 
     if (scorer == DSES_SCORER_GRID) {
         const TargetRes *t = job.target;
@@ -624,12 +642,13 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     rec_ev(0);
     DSES_HIP(launch_clear(bad, 16, stream));
     if (check_inputs) {
-        CheckArgs ca{job.src, job.n, job.tgt, job.m, job.rot, job.k, coord_limit(p), bad};
+        CheckArgs ca{job.src,  job.n, job.tgt, job.m, job.rot, job.k, kSrcCoordLimit,
+                     ref_coord_limit(p), bad};
         DSES_HIP(launch_check(ca, stream));
     }
-    DSES_HIP(launch_stage(job.tgt, static_cast<int32_t *>(c->perm.ptr), job.m, g.s, p.klo,
-                          static_cast<float *>(c->ys.ptr), static_cast<float *>(c->yt.ptr),
-                          stream));
+    DSES_HIP(launch_stage(job.tgt, static_cast<int32_t *>(c->perm.ptr), job.m, g.S16, g.S15,
+                          p.klo, static_cast<int32_t *>(c->yq.ptr),
+                          static_cast<float *>(c->yt.ptr), stream));
     rec_ev(1);
     if (job.exhaustive) {
         DSES_HIP(launch_exhaustive(a, scorer, grid, stream));
@@ -749,7 +768,7 @@ dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t
     }
     const bool dev = (o.flags & DSES_DEVICE_PTRS) != 0;
     if (!dev) {
-        st = check_host_inputs(src, n, tgt, m, rotations, k, coord_limit(p));
+        st = check_host_inputs(src, n, tgt, m, rotations, k, ref_coord_limit(p));
         if (st != DSES_OK) return st;
     }
     Context *c = ctx();
@@ -819,7 +838,7 @@ dses_status dses_register_exhaustive(const float *src, int64_t n, const float *t
     }
     const bool dev = (o.flags & DSES_DEVICE_PTRS) != 0;
     if (!dev) {
-        st = check_host_inputs(src, n, tgt, m, rotations, k, coord_limit(p));
+        st = check_host_inputs(src, n, tgt, m, rotations, k, ref_coord_limit(p));
         if (st != DSES_OK) return st;
     }
     Context *c = ctx();

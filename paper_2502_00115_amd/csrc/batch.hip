@@ -46,7 +46,7 @@ struct Prepared {
     const float *grid_pts = nullptr;        // device (resident cache)
     const int32_t *grid_start = nullptr;
     // offsets into the arena (bytes)
-    size_t off_src = 0, off_tgt = 0, off_rot = 0, off_ys = 0, off_yt = 0, off_perm = 0,
+    size_t off_src = 0, off_tgt = 0, off_rot = 0, off_yq = 0, off_yt = 0, off_perm = 0,
            off_rec = 0, off_gpts = 0, off_gstart = 0;
     void *records = nullptr;
     bool ready = false;
@@ -284,11 +284,11 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
             }
             ht = x.tgt_copy.data();
         }
-        const float lim = coord_limit(x.p);
+        const float lim = ref_coord_limit(x.p);
         bool ok = true;
         for (int64_t e = 0; e < 3 * m && ok; ++e) ok = std::fabs(ht[e]) <= lim;
         if (!dev)
-            for (int64_t e = 0; e < 3 * q.n && ok; ++e) ok = std::fabs(q.src[e]) <= lim;
+            for (int64_t e = 0; e < 3 * q.n && ok; ++e) ok = std::fabs(q.src[e]) <= kSrcCoordLimit;
         if (!dev && !q.rotset)
             for (int64_t r = 0; r < k && ok; ++r) {
                 const float *R = q.rotations + 9 * r;
@@ -317,7 +317,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
             sort_by_x(ht, x.m, &x.perm_local);
             x.perm = &x.perm_local;
         }
-        x.sorted = x.n <= kSortMax && ref_x_range(ht, *x.perm, x.g.s, x.p.klo[0], &x.ylo, &x.yhi);
+        x.sorted = x.n <= kSortMax && ref_x_range(ht, *x.perm, x.p.delta, x.p.klo[0], &x.ylo, &x.yhi);
         if (x.scorer == DSES_SCORER_GRID) {
             if (T) {
                 CellGrid cg{};
@@ -366,7 +366,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
             if (!T) x.off_tgt = bump(arena_bytes, 3 * (size_t)x.m * sizeof(float));
             if (!q.rotset) x.off_rot = bump(arena_bytes, 9 * (size_t)x.k * sizeof(float));
         }
-        x.off_ys = bump(arena_bytes, 3 * (size_t)x.m * sizeof(float));
+        x.off_yq = bump(arena_bytes, 4 * (size_t)x.m * sizeof(int32_t));
         x.off_yt = bump(arena_bytes, 3 * (size_t)x.m * sizeof(float));
         x.off_perm = bump(arena_bytes, (size_t)x.m * sizeof(int32_t));
         x.off_rec = bump(arena_bytes, (size_t)x.k * sizeof(dses_record));
@@ -452,7 +452,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
     build_items(lay.items_per_cu, &items);
     int n_items = (int)items.size();
     if ((st = ensure_capacity(b, count, max_items,
-                              (size_t)grid * slot_floats(max_n) * sizeof(float))) != DSES_OK)
+                              (size_t)grid * slot_words(max_n) * sizeof(int32_t))) != DSES_OK)
         return st;
 
     std::vector<SweepArgs> inst(b->cap_count);
@@ -465,7 +465,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         StageDesc &sd = stage[i];
         SelectDesc &sl = sel[i];
         if (x.status != DSES_OK) {       // empty stage/select entries
-            sd = StageDesc{nullptr, nullptr, 0, 1.0f, {0, 0, 0}, nullptr, nullptr};
+            sd = StageDesc{nullptr, nullptr, 0, 1.0, 1.0, {0, 0, 0}, nullptr, nullptr};
             sl = SelectDesc{nullptr, 0, 1.0f, nullptr, res_dev + i, nullptr};
             continue;
         }
@@ -491,12 +491,12 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         a = SweepArgs{};
         a.src = x.src;
         a.rot = x.rot;
-        a.ys = reinterpret_cast<float *>(arena + x.off_ys);
+        a.yq = reinterpret_cast<int32_t *>(arena + x.off_yq);
         a.yt = reinterpret_cast<float *>(arena + x.off_yt);
-        a.scratch = x.sorted ? static_cast<float *>(b->scratch.ptr) : nullptr;
+        a.scratch = x.sorted ? static_cast<int32_t *>(b->scratch.ptr) : nullptr;
         a.scratch_stride = max_n;
-        source_buckets(x.ylo, x.yhi, x.g.size[0], &a.sb_lo, &a.sb_scale, &a.sb_n);
-        a.ref_x_extent = (float)(x.yhi - x.ylo) + 1.0f;
+        source_buckets(x.ylo, x.yhi, x.g.size[0], &a.sb_lo, &a.sb_shift, &a.sb_n);
+        a.ref_x_extent = ref_x_extent(x.ylo, x.yhi);
         a.g = x.g;
         a.rec = reinterpret_cast<dses_record *>(arena + x.off_rec);
         a.k = x.k;
@@ -528,8 +528,9 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
                 a.field.inv[q] = x.target->df_inv[q];
             }
         }
-        sd = StageDesc{x.tgt, perm_dev, x.m, x.g.s, {x.p.klo[0], x.p.klo[1], x.p.klo[2]},
-                       const_cast<float *>(a.ys), const_cast<float *>(a.yt)};
+        sd = StageDesc{x.tgt, perm_dev, x.m, x.g.S16, x.g.S15,
+                       {x.p.klo[0], x.p.klo[1], x.p.klo[2]}, const_cast<int32_t *>(a.yq),
+                       const_cast<float *>(a.yt)};
         sl = SelectDesc{a.rec, x.k, x.p.delta, x.rot, res_dev + i, status_dev + i};
     }
     int32_t header[2] = {n_items, count};
@@ -547,7 +548,8 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         for (int i = 0; i < count; ++i) {
             const Prepared &x = P[i];
             if (x.status != DSES_OK) continue;
-            CheckArgs ca{x.src, x.n, x.tgt, x.m, x.rot, x.k, coord_limit(x.p), status_dev + i};
+            CheckArgs ca{x.src,          x.n, x.tgt, x.m, x.rot, x.k, kSrcCoordLimit,
+                         ref_coord_limit(x.p), status_dev + i};
             DSES_HIP(launch_check(ca, stream));
         }
     // everything above must land before a captured graph is replayed

@@ -55,7 +55,7 @@ struct Context {
     hipStream_t stream = nullptr;
     std::mutex mu;                       // serialises the plain entry points
     // workspace of the plain path
-    DevBuf in_src, in_tgt, in_rot, ys, yt, rec, res, status, grid_pts, grid_start, perm, scratch;
+    DevBuf in_src, in_tgt, in_rot, yq, yt, rec, res, status, grid_pts, grid_start, perm, scratch;
     DevBuf topk_a, topk_b, topk_out;     // top-k passes and output staging
     DevBuf prune;                        // q-pruning: M* and the work cursor
     DevResult *host_res = nullptr;       // pinned
@@ -88,7 +88,12 @@ dses_status apply_metric_options(const dses_options &o, Params *p);
 dses_status resolve_params(float eps, int metric, float delta_t, float tau, const float *t_min,
                            const float *t_max, int scorer, Params *p);
 // Largest |coordinate| accepted for a registration with these parameters.
-float coord_limit(const Params &p);
+// Largest accepted |coordinate|: reference points must keep the fixed-point
+// lattice values in range (ref_coord_limit); a source point of any magnitude up
+// to kSrcCoordLimit is accepted (its lattice value saturates where it can no
+// longer vote).
+float ref_coord_limit(const Params &p);
+constexpr float kSrcCoordLimit = 1.0e4f;
 
 dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, int counter_bits,
                       Geom *g);
@@ -99,15 +104,23 @@ dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, i
 int64_t ref_block_population(const float *tgt_aos, int32_t m, const Params &p);
 int64_t counter_bound(const float *tgt_aos, int32_t m, int32_t n, const Params &p);
 
-// Reference order sorted by x; the floors of the first and last scaled x
-// coordinates (ys_x = y_x * s + (0.5 - k_lo_x), the staging arithmetic) of that
-// order (false if they are too far apart for the sorted sweep); the source
-// bucket origin and scale of a box of size_x x-planes.
+// Fixed-point lattice scales (1/delta) 2^16 and (1/delta) 2^15, in double.
+void lattice_scales(float delta, double *S16, double *S15);
+
+// Reference order sorted by x; the staged fixed-point x coordinates (2^-16 bins,
+// lattice offset folded in, the staging arithmetic) of the first and last point
+// of that order (false if the sorted sweep cannot be used); the source bucket
+// origin, shift and count of a box of size_x x-planes.
 void sort_by_x(const float *tgt_aos, int32_t m, std::vector<int32_t> *perm);
-bool ref_x_range(const float *tgt_aos, const std::vector<int32_t> &perm, float s, int32_t klo_x,
-                 int32_t *ylo, int32_t *yhi);
-void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, float *sb_lo, float *sb_scale,
+bool ref_x_range(const float *tgt_aos, const std::vector<int32_t> &perm, float delta,
+                 int32_t klo_x, int32_t *ylo, int32_t *yhi);
+void source_buckets(int32_t ylo, int32_t yhi, int32_t size_x, int32_t *sb_lo, int32_t *sb_shift,
                     int32_t *sb_n);
+// x extent in bins of the staged reference (lane-group choice).
+inline float ref_x_extent(int32_t ylo, int32_t yhi)
+{
+    return (float)((double)(yhi - ylo) / 65536.0) + 1.0f;
+}
 
 // Exact cell grid for the GRID scorer, built on the host from reference points.
 struct HostGrid {
@@ -125,6 +138,7 @@ struct TargetRes {
     float *aos = nullptr;            // m x 3 device copy
     float *yt = nullptr;             // SoA device copy
     std::vector<float> host_aos;     // host copy (grid builds)
+    float max_abs = 0.0f;            // largest |coordinate| (lattice range check)
     // distance field
     float *df = nullptr;
     int32_t df_res = 0;
@@ -138,7 +152,8 @@ struct TargetRes {
     struct Stage {                           // staged copy for one (delta, box)
         float delta;
         int32_t klo[3];
-        float *ys, *yt;
+        int32_t *yq;                         // fixed-point copy (4 m int32)
+        float *yt;
         bool sorted;                         // ref_x_range succeeded
         int32_t ylo = 0, yhi = 0;            // its result
     };

@@ -16,8 +16,8 @@ constexpr int kHistWordsMax = kLdsWords - kScratchWords;
 
 // Per-registration constants of the sweep.
 struct Geom {
+    double S16, S15;       // (1/delta) 2^16 and (1/delta) 2^15: fixed-point lattice scales
     int32_t n, m;          // source / reference sizes
-    float s;               // 1/delta (float division)
     float delta;           // lattice pitch
     float eps, tau;        // inlier threshold, truncation
     float r;               // max(eps, tau): the only neighbourhood that matters
@@ -30,6 +30,7 @@ struct Geom {
     int32_t pps;           // x-planes per LDS slab
     int32_t nslabs;        // slabs covering size[0]
     int32_t slab_words;    // LDS words of one full slab (<= kHistWordsMax)
+    int32_t wide;          // 1: the x stride in bytes (4 size_y row_words) exceeds 16 bits
 };
 
 // Uniform cell grid over the reference for the exact GRID scorer.
@@ -52,8 +53,8 @@ struct Field {
 };
 
 // Per-rotation source sort: sb_n buckets (a multiple of the block size, at most
-// kSrcBuckets) over the scaled x coordinate, sb_scale buckets per bin (a power
-// of two, 16 when the reachable range fits).
+// kSrcBuckets) over the fixed-point x coordinate, 2^(16 - sb_shift) buckets per
+// bin (16 when the reachable range fits).
 constexpr int kSrcBuckets = 8192;
 constexpr int kSortMax = 16384;         // largest source cloud that is bucket-sorted
 // Vote work units per 64-point lane group when not fixed by the caller: enough
@@ -63,30 +64,32 @@ __host__ __device__ inline int vote_parts_auto(int groups)
     const int g = 64 / (groups > 0 ? groups : 1);
     return g < 1 ? 1 : (g > 8 ? 8 : g);
 }
-// Lane groups of the sorted-source vote: 2^lg reference points (64, 32 or 16),
-// each held by 64 >> lg sub-groups of lanes that take alternate 4-source pieces of
-// the same stream window, so a wave step covers 2^lg points x (64 >> lg) sources.
-// Smaller groups span less x, so their windows carry less slack (about
-// 2^lg * X source-bins per slab over all groups, X the reference's x extent in
-// bins), but there are more work units, each costing about kUnitSteps wave steps
-// of set-up, padding and slab-end imbalance (fitted); rho = n / (X + size_x)
-// sources per bin turns a step into 64 / rho source-bins.  The size with the least modelled cost wins
-// (ties: the larger group).  It picks 16 for a 717-point source against a
-// 1,024-point reference with eps 0.03 (measured fastest, 10% below 64) and 64 for
-// 64 / 256 points and for 4,096 / 16,384 points (both measured fastest).
+// Lane groups of the sorted-source vote: 2^(lg+1) reference points (64, 32 or
+// 16), two per lane on 2^lg lanes, repeated on the wave's 64 >> lg lane
+// sub-groups, which take alternate 4-source pieces of the same stream window, so
+// a wave step covers 2^(lg+1) points x (64 >> lg) sources.  Smaller groups span
+// less x, so their windows carry less slack (about 2^(lg+1) * X source-bins per
+// slab over all groups, X the reference's x extent in bins), but there are more
+// work units, each costing about kUnitSteps wave steps of set-up, padding and
+// slab-end imbalance (fitted); rho = n / (X + size_x) sources per bin turns a step
+// into 64 / rho source-bins.  The size with the least modelled cost wins (ties:
+// the larger group).  It picks 16 points for a 717-point source against a
+// 1,024-point reference with eps 0.03 and 64 for 64 / 256 points and for 4,096 /
+// 16,384 points.
 constexpr float kUnitSteps = 4.9f;
 __host__ __device__ inline int lane_group_log2(int m, int n, int size_x, float x_extent,
                                                int vote_parts)
 {
     const float per_unit = kUnitSteps * 64.0f * (x_extent + (float)size_x) /
                            (float)(n > 0 ? n : 1);
-    int best = 6;
+    int best = 5;
     float best_cost = 0.0f;
-    for (int lg = 6; lg >= 4; --lg) {
-        const int groups = (m + (1 << lg) - 1) >> lg;
+    for (int lg = 5; lg >= 3; --lg) {
+        const int gref = 2 << lg;
+        const int groups = (m + gref - 1) / gref;
         const int parts = vote_parts > 0 ? vote_parts : vote_parts_auto(groups);
-        const float cost = (float)(1 << lg) * x_extent + per_unit * (float)(groups * parts);
-        if (lg == 6 || cost < best_cost) {
+        const float cost = (float)gref * x_extent + per_unit * (float)(groups * parts);
+        if (lg == 5 || cost < best_cost) {
             best_cost = cost;
             best = lg;
         }
@@ -108,11 +111,12 @@ constexpr int kExhaustiveMaxSrc = 12288;
 struct SweepArgs {
     const float *src;      // n x 3 AoS
     const float *rot;      // K x 9
-    const float *ys;       // scaled + offset reference, SoA (3 * m), sorted by x
+    const int32_t *yq;     // fixed-point reference (lattice offset folded in), sorted by x:
+                           // four arrays of m, x, y, z at 2^-16 bins and z at 2^-15 bins
     const float *yt;       // reference, SoA (3 * m), same order
-    float *scratch;        // per workgroup slot: the rotation's sources sorted by x (below)
+    int32_t *scratch;      // per workgroup slot: the rotation's sources sorted by x (below)
     int64_t scratch_stride;   // sources a slot holds (>= n)
-    float sb_lo, sb_scale;    // source bucket of P: floor((P - sb_lo) * sb_scale), clamped
+    int32_t sb_lo, sb_shift;  // source bucket of P: (P - sb_lo) >> sb_shift, clamped
     int32_t sb_n;             // to [0, sb_n)
     Geom g;
     CellGrid grid;
@@ -124,12 +128,13 @@ struct SweepArgs {
     float ref_x_extent;    // x extent of the scaled reference in bins (lane-group choice)
 };
 
-// Scratch slot of one workgroup (floats): rotated scaled sources sorted by x as
-// three arrays x, y, z of src_stride(cap) floats each (entries n .. stride-1 hold
-// sentinels that never vote, so windows can be padded to a multiple of 4), then the
-// bucket table T[0 .. kSrcBuckets] (int32: T[b] = sources in buckets below b).
+// Scratch slot of one workgroup (int32 words): rotated fixed-point sources sorted
+// by x as three arrays x, y, z of src_stride(cap) entries each (entries n ..
+// stride-1 hold padding that never votes, so windows can be padded to a multiple
+// of 4), then the bucket table T[0 .. kSrcBuckets] (T[b] = sources in buckets
+// below b).
 __host__ __device__ inline int64_t src_stride(int64_t cap) { return (cap + 15) & ~int64_t(15); }
-__host__ __device__ inline int64_t slot_floats(int64_t cap)
+__host__ __device__ inline int64_t slot_words(int64_t cap)
 {
     return (3 * src_stride(cap) + kSrcBuckets + 1 + 3) & ~int64_t(3);
 }
@@ -146,7 +151,7 @@ struct BatchArgs {
     const BatchItem *items;    // work list, most expensive first
     const int32_t *header;     // header[0] = items, header[1] = instances
     uint32_t *cursor;          // work-list cursor, cleared before each launch
-    float *scratch;            // if set: this launch's source-sort scratch (overrides
+    int32_t *scratch;          // if set: this launch's source-sort scratch (overrides
                                // the instances' own, so concurrent launches never share)
 };
 
@@ -154,9 +159,10 @@ struct StageDesc {
     const float *tgt;
     const int32_t *perm;
     int32_t m;
-    float s;
+    double S16, S15;
     int32_t klo[3];
-    float *ys, *yt;
+    int32_t *yq;
+    float *yt;
 };
 
 struct DevResult;
@@ -185,14 +191,15 @@ struct CheckArgs {
     const float *src; int32_t n;
     const float *tgt; int32_t m;
     const float *rot; int32_t k;
-    float coord_limit;     // max |coordinate| accepted
+    float src_limit;       // max |source coordinate| accepted
+    float ref_limit;       // max |reference coordinate| accepted
     uint32_t *bad;         // set to non-zero on invalid input
 };
 
 // Launchers (defined in kernels.hip); all enqueue on `stream`.
 hipError_t launch_check(const CheckArgs &a, hipStream_t stream);
-hipError_t launch_stage(const float *tgt, const int32_t *perm, int32_t m, float s,
-                        const int32_t *klo, float *ys, float *yt, hipStream_t stream);
+hipError_t launch_stage(const float *tgt, const int32_t *perm, int32_t m, double S16, double S15,
+                        const int32_t *klo, int32_t *yq, float *yt, hipStream_t stream);
 hipError_t launch_sweep(const SweepArgs &a, int scorer, int grid, hipStream_t stream);
 hipError_t launch_select(const dses_record *rec, int32_t k, const float *rot, float delta,
                          DevResult *res, const uint32_t *status, hipStream_t stream);

@@ -90,10 +90,10 @@ __global__ void k_check(CheckArgs a)
         bool bad = false;
         if (e < (int64_t)a.n * 3) {
             float v = a.src[e];
-            bad = !(fabsf(v) <= a.coord_limit);
+            bad = !(fabsf(v) <= a.src_limit);
         } else if (e < (int64_t)a.n * 3 + (int64_t)a.m * 3) {
             float v = a.tgt[e - (int64_t)a.n * 3];
-            bad = !(fabsf(v) <= a.coord_limit);
+            bad = !(fabsf(v) <= a.ref_limit);
         } else {
             const float *R = a.rot + 9 * (e - (int64_t)a.n * 3 - (int64_t)a.m * 3);
             float worst = 0.0f;
@@ -120,29 +120,80 @@ hipError_t launch_check(const CheckArgs &a, hipStream_t stream)
 }
 
 // --------------------------------------------------------------------------
-// staging: reference AoS -> SoA, plus the scaled/offset copy used for binning
-//   ys_a = (y_a * s) + (0.5 - k_lo_a)   (two float roundings, as in the header)
+// Fixed-point lattice coordinates.  A coordinate v (a reference coordinate, or a
+// rotated source coordinate) becomes an integer in units of 2^-F bins:
+//     q(v) = rint(v * S_F [+ (1/2 - k_lo) 2^F])     S_F = (1/delta) 2^F,
+// every product and sum a separately rounded double operation (the products of
+// two floats are exact in double), rint rounding halves to even.  The pair
+// difference D = Y - P of a reference value Y and a source value P is then exact
+// integer arithmetic, and floor(D / 2^F) is the box-relative bin of Alg. 2's
+// ROUND up to the two roundings of q, at most 2^-F bins together: F = 16 on x and
+// y, and on z 15 with 16-bit counters (the two counters of a word are z
+// neighbours, so D >> 16 is the word and bit 15 the half), 16 with 32-bit ones.
 // --------------------------------------------------------------------------
-__global__ void k_stage(const float *tgt, const int32_t *perm, int32_t m, float s, int32_t klo0,
-                        int32_t klo1, int32_t klo2, float *ys, float *yt)
+__device__ __forceinline__ int32_t quant(double v) { return __double2int_rn(v); }
+
+// A rotated source value saturates at +-2^30 units (2^14 bins): every reference
+// value is below 2^29 units and a voting difference below 2^28, so no pair with a
+// source value beyond 2^30 can vote, before or after the saturation.
+__device__ __forceinline__ int32_t quant_src(double v)
+{
+    return quant(fmin(fmax(v, -1073741824.0), 1073741824.0));
+}
+
+__device__ __forceinline__ int32_t quant_ref(float y, double S, double ofs)
+{
+    return quant(__dadd_rn(__dmul_rn((double)y, S), ofs));
+}
+
+// p_a = (R_a0 x + R_a1 y) + R_a2 z in double, then q(p_a) with S16 on x and y and
+// Sz (S15 or S16) on z, saturated.
+__device__ __forceinline__ void rotate_quant(const float *R, float x, float y, float z, double S16,
+                                             double Sz, int32_t &Px, int32_t &Py, int32_t &Pz)
+{
+    const double dx = (double)x, dy = (double)y, dz = (double)z;
+    const double p0 = __dadd_rn(__dadd_rn(__dmul_rn((double)R[0], dx), __dmul_rn((double)R[1], dy)),
+                                __dmul_rn((double)R[2], dz));
+    const double p1 = __dadd_rn(__dadd_rn(__dmul_rn((double)R[3], dx), __dmul_rn((double)R[4], dy)),
+                                __dmul_rn((double)R[5], dz));
+    const double p2 = __dadd_rn(__dadd_rn(__dmul_rn((double)R[6], dx), __dmul_rn((double)R[7], dy)),
+                                __dmul_rn((double)R[8], dz));
+    Px = quant_src(__dmul_rn(p0, S16));
+    Py = quant_src(__dmul_rn(p1, S16));
+    Pz = quant_src(__dmul_rn(p2, Sz));
+}
+
+// --------------------------------------------------------------------------
+// staging: reference AoS -> SoA float (scoring) and the fixed-point copy used
+// for binning, four arrays of m: x, y, z at 2^-16 bins and z at 2^-15 bins,
+//   Y_a = q(y_a) with the offset (1/2 - k_lo_a) 2^F folded in.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void stage_point(const float *tgt, int src, int j, int32_t m,
+                                            double S16, double S15, const int32_t *klo,
+                                            int32_t *yq, float *yt)
+{
+    for (int a = 0; a < 3; ++a) {
+        const float y = tgt[3 * src + a];
+        yq[a * m + j] = quant_ref(y, S16, (0.5 - (double)klo[a]) * 65536.0);
+        yt[a * m + j] = y;
+    }
+    yq[3 * m + j] = quant_ref(tgt[3 * src + 2], S15, (0.5 - (double)klo[2]) * 32768.0);
+}
+
+__global__ void k_stage(const float *tgt, const int32_t *perm, int32_t m, double S16, double S15,
+                        int32_t klo0, int32_t klo1, int32_t klo2, int32_t *yq, float *yt)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
-    const int klo[3] = {klo0, klo1, klo2};
-    const int src = perm ? perm[j] : j;
-    for (int a = 0; a < 3; ++a) {
-        float y = tgt[3 * src + a];
-        float ofs = 0.5f - (float)klo[a];
-        ys[a * m + j] = __fadd_rn(__fmul_rn(y, s), ofs);
-        yt[a * m + j] = y;
-    }
+    const int32_t klo[3] = {klo0, klo1, klo2};
+    stage_point(tgt, perm ? perm[j] : j, j, m, S16, S15, klo, yq, yt);
 }
 
-hipError_t launch_stage(const float *tgt, const int32_t *perm, int32_t m, float s,
-                        const int32_t *klo, float *ys, float *yt, hipStream_t stream)
+hipError_t launch_stage(const float *tgt, const int32_t *perm, int32_t m, double S16, double S15,
+                        const int32_t *klo, int32_t *yq, float *yt, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_stage, dim3((m + 255) / 256), dim3(256), 0, stream, tgt, perm, m, s,
-                       klo[0], klo[1], klo[2], ys, yt);
+    hipLaunchKernelGGL(k_stage, dim3((m + 255) / 256), dim3(256), 0, stream, tgt, perm, m, S16,
+                       S15, klo[0], klo[1], klo[2], yq, yt);
     return hipGetLastError();
 }
 
@@ -206,90 +257,118 @@ __device__ __forceinline__ ChunkLayout chunk_layout(int c0, int n, int wave, int
     return L;
 }
 
-// One pair's vote.  c* are box-relative bin coordinates; the x range check is
-// against the current slab [x0, x0 + np).  LDS byte address (16-bit counters):
-//   ((cx - x0) * Sy + cy) * row_words * 4 + (cz >> 1) * 4, half = cz & 1
-// (32-bit: ((cx - x0) * Sy + cy) * Sz * 4 + cz * 4).
-// Each width is one asm block: three v_cmpx narrow EXEC to the in-box lanes,
+// One pair's vote from its fixed-point differences D_a = Y_a - P_a (x with the
+// slab's first plane folded into Y, so every range starts at 0).  The pair votes
+// iff D_x < np 2^16, D_y < S_y 2^16 and D_z < S_z 2^Fz as unsigned numbers (a
+// negative difference is a huge one); then its counter is at LDS byte address
+//     base + (D_x >> 16) sx4 + (D_y >> 16) sy4 + (D_z >> 16) 4
+// (16-bit counters: D_z >> 16 is the z bin halved, bit 15 its half, so the
+// increment is 1 or 1 << 16; 32-bit counters: D_z >> 16 is the z bin).  The
+// upper halves of the differences feed v_mad_u32_u16 directly through op_sel, so
+// the address costs three multiply-adds and no extraction; WIDE (x stride in
+// bytes above 16 bits) multiplies word strides and scales the sum by 4 at the end.
+// Without XT the x test is left out: the caller has proven 0 <= D_x < np 2^16
+// for every lane (the interior of a window).
+// Each variant is one asm block: the v_cmpx narrow EXEC to the voting lanes,
 // the address arithmetic and the ds_add_u32 run on those lanes only, and EXEC is
-// restored.  Compared with a compiler-generated branch this removes the per-pair
-// VALU -> SALU -> branch round trip (v_cmp, s_and, s_and_saveexec, s_cbranch,
-// s_or), which left the vector ALU idle about half of the time.
-template <int CW>
-__device__ __forceinline__ void vote_pair(uint32_t *hist, int cx, int cy, int cz, int x0,
-                                          uint32_t np, uint32_t Sy, uint32_t Sz, uint32_t sx4,
-                                          uint32_t sy4, uint32_t negc)
+// restored -- no branch, no VALU -> SALU round trip per pair.
+struct VoteConst {
+    uint32_t npx, syx, szx;    // range limits: np << 16, S_y << 16, S_z << Fz
+    uint32_t sx, sy;           // x and y strides: bytes (sx4, sy4), or words when WIDE
+    uint32_t base;             // LDS byte address of the slab's first counter
+};
+
+#define DSES_VP_X "v_cmpx_gt_u32 vcc, %[npx], %[dx]\n\t"
+#define DSES_VP_YZ                                                                           \
+    "v_cmpx_gt_u32 vcc, %[syx], %[dy]\n\t"                                                   \
+    "v_cmpx_gt_u32 vcc, %[szx], %[dz]\n\t"
+#define DSES_VP_ADDR_BYTES                                                                   \
+    "v_mad_u32_u16 %[t1], %[dz], 4, %[base] op_sel:[1,0,0,0]\n\t"                             \
+    "v_mad_u32_u16 %[t1], %[dy], %[sy], %[t1] op_sel:[1,0,0,0]\n\t"                           \
+    "v_mad_u32_u16 %[t1], %[dx], %[sx], %[t1] op_sel:[1,0,0,0]\n\t"
+#define DSES_VP_ADDR_WORDS                                                                   \
+    "v_lshrrev_b32 %[t1], 16, %[dz]\n\t"                                                     \
+    "v_mad_u32_u16 %[t1], %[dy], %[sy], %[t1] op_sel:[1,0,0,0]\n\t"                           \
+    "v_mad_u32_u16 %[t1], %[dx], %[sx], %[t1] op_sel:[1,0,0,0]\n\t"                           \
+    "v_lshl_add_u32 %[t1], %[t1], 2, %[base]\n\t"
+#define DSES_VP_HALF                                                                         \
+    "v_bfe_u32 %[t2], %[dz], 15, 1\n\t"                                                      \
+    "v_mad_u32_u24 %[t2], %[t2], %[ffff], 1\n\t"
+// 16-bit counters: the increment t2 is computed in the block; 32-bit: it is 1
+#define DSES_VP_OPERANDS                                                                     \
+    [dx] "v"(dx), [dy] "v"(dy), [dz] "v"(dz), [npx] "s"(v.npx), [syx] "s"(v.syx),            \
+        [szx] "s"(v.szx), [sx] "s"(v.sx), [sy] "s"(v.sy), [base] "s"(v.base)
+#define DSES_VP_ASM16(TEXT)                                                                  \
+    asm volatile("s_mov_b64 %[save], exec\n\t" TEXT "ds_add_u32 %[t1], %[t2]\n\t"            \
+                 "s_mov_b64 exec, %[save]"                                                   \
+                 : [save] "=&s"(save), [t1] "=&v"(t1), [t2] "=&v"(t2)                          \
+                 : DSES_VP_OPERANDS, [ffff] "s"(0xFFFFu)                                      \
+                 : "vcc", "memory")
+#define DSES_VP_ASM32(TEXT)                                                                  \
+    asm volatile("s_mov_b64 %[save], exec\n\t" TEXT "ds_add_u32 %[t1], %[t2]\n\t"            \
+                 "s_mov_b64 exec, %[save]"                                                   \
+                 : [save] "=&s"(save), [t1] "=&v"(t1)                                         \
+                 : DSES_VP_OPERANDS, [t2] "v"(1u)                                            \
+                 : "vcc", "memory")
+
+template <int CW, bool WIDE, bool XT = true>
+__device__ __forceinline__ void vote_pair(uint32_t dx, uint32_t dy, uint32_t dz, const VoteConst &v)
 {
-    if (CW == 16) {
-        const uint32_t base =
-            negc + (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t *)hist;
-        uint64_t save;
-        uint32_t t0, t1, t2;
-        asm volatile(
-            "s_mov_b64 %[save], exec\n\t"
-            "v_subrev_u32 %[t0], %[x0], %[cx]\n\t"
-            "v_cmpx_gt_u32 vcc, %[np], %[t0]\n\t"
-            "v_cmpx_gt_u32 vcc, %[sy], %[cy]\n\t"
-            "v_cmpx_gt_u32 vcc, %[sz], %[cz]\n\t"
-            "v_lshrrev_b32 %[t1], 1, %[cz]\n\t"
-            "v_lshl_add_u32 %[t1], %[t1], 2, %[base]\n\t"
-            "v_mad_u32_u24 %[t1], %[cy], %[sy4], %[t1]\n\t"
-            "v_mad_u32_u24 %[t1], %[cx], %[sx4], %[t1]\n\t"
-            "v_lshlrev_b32 %[t2], 4, %[cz]\n\t"
-            "v_lshlrev_b32_e64 %[t2], %[t2], 1\n\t"
-            "ds_add_u32 %[t1], %[t2]\n\t"
-            "s_mov_b64 exec, %[save]"
-            : [save] "=&s"(save), [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2)
-            : [cx] "v"(cx), [cy] "v"(cy), [cz] "v"(cz), [x0] "s"(x0), [np] "s"(np),
-              [sy] "s"(Sy), [sz] "s"(Sz), [sx4] "s"(sx4), [sy4] "s"(sy4), [base] "s"(base)
-            : "vcc", "memory");
-        return;
-    }
-    // 32-bit counters: the same single block, address cz * 4 and increment 1
-    const uint32_t base =
-        negc + (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t *)hist;
     uint64_t save;
-    uint32_t t0, t1;
-    asm volatile(
-        "s_mov_b64 %[save], exec\n\t"
-        "v_subrev_u32 %[t0], %[x0], %[cx]\n\t"
-        "v_cmpx_gt_u32 vcc, %[np], %[t0]\n\t"
-        "v_cmpx_gt_u32 vcc, %[sy], %[cy]\n\t"
-        "v_cmpx_gt_u32 vcc, %[sz], %[cz]\n\t"
-        "v_lshl_add_u32 %[t1], %[cz], 2, %[base]\n\t"
-        "v_mad_u32_u24 %[t1], %[cy], %[sy4], %[t1]\n\t"
-        "v_mad_u32_u24 %[t1], %[cx], %[sx4], %[t1]\n\t"
-        "ds_add_u32 %[t1], %[one]\n\t"
-        "s_mov_b64 exec, %[save]"
-        : [save] "=&s"(save), [t0] "=&v"(t0), [t1] "=&v"(t1)
-        : [cx] "v"(cx), [cy] "v"(cy), [cz] "v"(cz), [x0] "s"(x0), [np] "s"(np), [sy] "s"(Sy),
-          [sz] "s"(Sz), [sx4] "s"(sx4), [sy4] "s"(sy4), [base] "s"(base), [one] "v"(1u)
-        : "vcc", "memory");
+    uint32_t t1, t2;
+    if (CW == 16) {
+        if (XT && !WIDE) DSES_VP_ASM16(DSES_VP_X DSES_VP_YZ DSES_VP_ADDR_BYTES DSES_VP_HALF);
+        if (XT && WIDE) DSES_VP_ASM16(DSES_VP_X DSES_VP_YZ DSES_VP_ADDR_WORDS DSES_VP_HALF);
+        if (!XT && !WIDE) DSES_VP_ASM16(DSES_VP_YZ DSES_VP_ADDR_BYTES DSES_VP_HALF);
+        if (!XT && WIDE) DSES_VP_ASM16(DSES_VP_YZ DSES_VP_ADDR_WORDS DSES_VP_HALF);
+    } else {
+        if (XT && !WIDE) DSES_VP_ASM32(DSES_VP_X DSES_VP_YZ DSES_VP_ADDR_BYTES);
+        if (XT && WIDE) DSES_VP_ASM32(DSES_VP_X DSES_VP_YZ DSES_VP_ADDR_WORDS);
+        if (!XT && !WIDE) DSES_VP_ASM32(DSES_VP_YZ DSES_VP_ADDR_BYTES);
+        if (!XT && WIDE) DSES_VP_ASM32(DSES_VP_YZ DSES_VP_ADDR_WORDS);
+        (void)t2;
+    }
 }
+#undef DSES_VP_ASM32
+#undef DSES_VP_ASM16
+#undef DSES_VP_OPERANDS
+#undef DSES_VP_HALF
+#undef DSES_VP_ADDR_WORDS
+#undef DSES_VP_ADDR_BYTES
+#undef DSES_VP_YZ
+#undef DSES_VP_X
 
 typedef uint32_t f4u __attribute__((ext_vector_type(4)));
 
-// Buffer resource over a point set stored as three arrays (x, y, z) of `stride`
-// floats each (the staged reference, or a slot's sorted sources).  The hardware
-// range check covers the per-lane (VGPR) offset only; the stream loads below
-// address by scalar offset and stay inside the arrays by construction.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t soa_rsrc(const float *base, int64_t stride)
+// Buffer resource over `bytes` bytes from `base`.  The hardware range check covers
+// the per-lane (VGPR) offset only; the stream loads below address by scalar offset
+// and stay inside their arrays by construction.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, int64_t bytes)
 {
     // word 3: 32-bit data format, no swizzle (raw buffer)
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), 0, (int)(12 * stride),
-                                             0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
 }
 
 // The same descriptor as four scalar words, for the asm loads below.
-__device__ __forceinline__ f4u soa_desc(const float *base, int64_t stride)
+__device__ __forceinline__ f4u desc_words(const void *base, int64_t bytes)
 {
     const uint64_t p = (uint64_t)(uintptr_t)base;
     f4u d;
     d.x = __builtin_amdgcn_readfirstlane((uint32_t)p);
     d.y = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
-    d.z = (uint32_t)(12 * stride);
+    d.z = (uint32_t)bytes;
     d.w = 0x00020000u;
     return d;
+}
+
+// Byte offsets of the x, y and z arrays of a point set held as int32 arrays of
+// `stride` entries (z is array zsel: 2, or 3 for the reference's 2^-15 z).
+struct SoaOffs {
+    int o0, o1, o2;
+};
+__device__ __forceinline__ SoaOffs soa_offs(int stride, int zsel)
+{
+    return SoaOffs{0, 4 * stride, 4 * zsel * stride};
 }
 
 // Points j .. j+3 (x, y, z) of such a set: three 16-byte loads, the same address
@@ -299,10 +378,10 @@ __device__ __forceinline__ f4u soa_desc(const float *base, int64_t stride)
 // for a full memory round trip.  Every group issued here must be waited for
 // (soa_wait) before its registers die, or a late load could overwrite registers
 // the compiler has reused.
-__device__ __forceinline__ void soa_issue4(const f4u &desc, int stride, int j, f4u &x, f4u &y,
-                                           f4u &z)
+__device__ __forceinline__ void soa_issue4(const f4u &desc, const SoaOffs &so, int j, f4u &x,
+                                           f4u &y, f4u &z)
 {
-    const int o0 = 4 * j, o1 = 4 * (stride + j), o2 = 4 * (2 * stride + j);
+    const int o0 = so.o0 + 4 * j, o1 = so.o1 + 4 * j, o2 = so.o2 + 4 * j;
     asm volatile("buffer_load_dwordx4 %0, off, %3, %4\n\t"
                  "buffer_load_dwordx4 %1, off, %3, %5\n\t"
                  "buffer_load_dwordx4 %2, off, %3, %6"
@@ -311,10 +390,10 @@ __device__ __forceinline__ void soa_issue4(const f4u &desc, int stride, int j, f
 }
 
 // Points j + 4h .. j + 4h + 3 of such a set, h = hoff / 16 per lane.
-__device__ __forceinline__ void soa_issue_lanes(const f4u &desc, int stride, int j,
+__device__ __forceinline__ void soa_issue_lanes(const f4u &desc, const SoaOffs &so, int j,
                                                 uint32_t hoff, f4u &x, f4u &y, f4u &z)
 {
-    const int o0 = 4 * j, o1 = 4 * (stride + j), o2 = 4 * (2 * stride + j);
+    const int o0 = so.o0 + 4 * j, o1 = so.o1 + 4 * j, o2 = so.o2 + 4 * j;
     asm volatile("buffer_load_dwordx4 %0, %3, %4, %5 offen\n\t"
                  "buffer_load_dwordx4 %1, %3, %4, %6 offen\n\t"
                  "buffer_load_dwordx4 %2, %3, %4, %7 offen"
@@ -334,150 +413,182 @@ __device__ __forceinline__ void soa_wait(f4u &x, f4u &y, f4u &z)
         asm volatile("s_waitcnt vmcnt(0)" : "+v"(x), "+v"(y), "+v"(z));
 }
 
-// One float of such a set (index into the x, y, z arrays).
-__device__ __forceinline__ float soa_load1(__amdgpu_buffer_rsrc_t rs, int i)
+// One int32 of such a set at byte offset `off` (+ the per-lane offset vo).
+__device__ __forceinline__ uint32_t load1(__amdgpu_buffer_rsrc_t rs, uint32_t vo, int off)
 {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 0, 4 * i, 0));
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, off, 0);
 }
 
 // Votes of one lane point (Lx, Ly, Lz) against four streamed points (x, y, z).
-// LREF: the lane holds a reference point Y and the stream source points P,
-// else the reverse; either way the bin is floor(Y - P) per axis.
-template <int CW, bool LREF>
-__device__ __forceinline__ void vote4(uint32_t *hist, f4u x, f4u y, f4u z, float Lx, float Ly,
-                                      float Lz, int x0, uint32_t np, uint32_t Sy, uint32_t Sz,
-                                      uint32_t sx4, uint32_t sy4, uint32_t negc)
+// LREF: the lane holds a reference point Y and the stream source points P, else
+// the reverse; either way D = Y - P per axis.
+template <int CW, bool WIDE, bool LREF, bool XT = true>
+__device__ __forceinline__ void vote4(f4u x, f4u y, f4u z, uint32_t Lx, uint32_t Ly, uint32_t Lz,
+                                      const VoteConst &v)
 {
-    int cx[4], cy[4], cz[4];
+    uint32_t dx[4], dy[4], dz[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (LREF) {
-            cx[q] = cvt_flr(Lx - __uint_as_float(x[q]));
-            cy[q] = cvt_flr(Ly - __uint_as_float(y[q]));
-            cz[q] = cvt_flr(Lz - __uint_as_float(z[q]));
-        } else {
-            cx[q] = cvt_flr(__uint_as_float(x[q]) - Lx);
-            cy[q] = cvt_flr(__uint_as_float(y[q]) - Ly);
-            cz[q] = cvt_flr(__uint_as_float(z[q]) - Lz);
-        }
+        dx[q] = LREF ? Lx - x[q] : x[q] - Lx;
+        dy[q] = LREF ? Ly - y[q] : y[q] - Ly;
+        dz[q] = LREF ? Lz - z[q] : z[q] - Lz;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        vote_pair<CW>(hist, cx[q], cy[q], cz[q], x0, np, Sy, Sz, sx4, sy4, negc);
+    for (int q = 0; q < 4; ++q) vote_pair<CW, WIDE, XT>(dx[q], dy[q], dz[q], v);
 }
 
-// Votes of the lane point L against the streamed points [j0, j1) of a three-array
-// point set: groups of 4 points with two groups in flight, then single points.
+// Votes of the lane source point P against the streamed reference points
+// [j0, j1): groups of 4 points with two groups in flight, then single points.
 // The streamed coordinates come through the vector memory path (buffer loads):
 // scalar loads would share the LDS counter, and waiting for them would also wait
 // for every outstanding ds_add of the wave.
-template <int CW, bool LREF>
-__device__ __forceinline__ void vote_span(uint32_t *hist, const f4u &desc,
-                                          __amdgpu_buffer_rsrc_t rs, int stride, int j0, int j1,
-                                          float Lx, float Ly, float Lz, int x0, uint32_t np,
-                                          uint32_t Sy, uint32_t Sz, uint32_t sx4, uint32_t sy4,
-                                          uint32_t negc)
+template <int CW, bool WIDE>
+__device__ __forceinline__ void vote_span(const f4u &desc, __amdgpu_buffer_rsrc_t rs,
+                                          const SoaOffs &so, int j0, int j1, uint32_t Px,
+                                          uint32_t Py, uint32_t Pz, const VoteConst &v)
 {
     int j = j0;
     if (j + 4 <= j1) {
         f4u ax, ay, az, bx, by, bz;
-        soa_issue4(desc, stride, j, ax, ay, az);
+        soa_issue4(desc, so, j, ax, ay, az);
         for (; j + 8 <= j1; j += 8) {
-            soa_issue4(desc, stride, j + 4, bx, by, bz);
+            soa_issue4(desc, so, j + 4, bx, by, bz);
             soa_wait<3>(ax, ay, az);
-            vote4<CW, LREF>(hist, ax, ay, az, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
-            soa_issue4(desc, stride, min(j + 8, j1 - 4), ax, ay, az);
+            vote4<CW, WIDE, false>(ax, ay, az, Px, Py, Pz, v);
+            soa_issue4(desc, so, min(j + 8, j1 - 4), ax, ay, az);
             soa_wait<3>(bx, by, bz);
-            vote4<CW, LREF>(hist, bx, by, bz, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
+            vote4<CW, WIDE, false>(bx, by, bz, Px, Py, Pz, v);
         }
         soa_wait<0>(ax, ay, az);          // the last group issued, used or not
         if (j + 4 <= j1) {
-            vote4<CW, LREF>(hist, ax, ay, az, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
+            vote4<CW, WIDE, false>(ax, ay, az, Px, Py, Pz, v);
             j += 4;
         }
     }
     for (; j < j1; ++j) {
-        const float ux = soa_load1(rs, j), uy = soa_load1(rs, stride + j);
-        const float uz = soa_load1(rs, 2 * stride + j);
-        if (LREF)
-            vote_pair<CW>(hist, cvt_flr(Lx - ux), cvt_flr(Ly - uy), cvt_flr(Lz - uz), x0, np,
-                          Sy, Sz, sx4, sy4, negc);
-        else
-            vote_pair<CW>(hist, cvt_flr(ux - Lx), cvt_flr(uy - Ly), cvt_flr(uz - Lz), x0, np,
-                          Sy, Sz, sx4, sy4, negc);
+        const uint32_t yx = load1(rs, 0, so.o0 + 4 * j), yy = load1(rs, 0, so.o1 + 4 * j);
+        const uint32_t yz = load1(rs, 0, so.o2 + 4 * j);
+        vote_pair<CW, WIDE>(yx - Px, yy - Py, yz - Pz, v);
     }
 }
 
-// Votes of the lane point L against the streamed points [j0, j1), j1 - j0 a
-// multiple of 4: in each whole block of B = 4 * 64 / (lane-group size) points,
-// lane sub-group h (its hoff = 16 h bytes) takes points 4h .. 4h + 3; the r < B
-// points after the last whole block go in r / S steps (S = B / 4 sub-groups),
-// sub-group h taking point S q + h in step q (every index stays below j1).
-template <int CW>
-__device__ __forceinline__ void vote_span_lanes(uint32_t *hist, const f4u &desc,
-                                                __amdgpu_buffer_rsrc_t rs, int stride, int j0,
-                                                int j1, int B, uint32_t hoff, float Lx,
-                                                float Ly, float Lz, int x0, uint32_t np,
-                                                uint32_t Sy, uint32_t Sz, uint32_t sx4,
-                                                uint32_t sy4, uint32_t negc)
+// Values that never vote: a padding source (every coordinate INT32_MIN) or a
+// padding lane point (INT32_MAX): with every real coordinate below 2^29 in
+// magnitude, each difference they take part in lies at 2^30 or more from the
+// range [0, 2^28) of a voting one, also with each other (-1).
+constexpr uint32_t kPadSrc = 0x80000000u;
+constexpr uint32_t kPadRef = 0x7FFFFFFFu;
+
+// A lane's two reference points (vote_slab's sorted layout).
+struct LanePts {
+    uint32_t x0, y0, z0, x1, y1, z1;
+};
+
+// Votes of a lane's two reference points against four streamed sources: each
+// 48 bytes a lane loads serve eight pairs (the vector-memory return path, 64
+// bytes per clock per CU, bounded the vote at one point per lane).
+template <int CW, bool WIDE, bool XT>
+__device__ __forceinline__ void vote8(f4u x, f4u y, f4u z, const LanePts &L, const VoteConst &v)
+{
+    uint32_t d0[3][4], d1[3][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        d0[0][q] = L.x0 - x[q];
+        d0[1][q] = L.y0 - y[q];
+        d0[2][q] = L.z0 - z[q];
+        d1[0][q] = L.x1 - x[q];
+        d1[1][q] = L.y1 - y[q];
+        d1[2][q] = L.z1 - z[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        vote_pair<CW, WIDE, XT>(d0[0][q], d0[1][q], d0[2][q], v);
+        vote_pair<CW, WIDE, XT>(d1[0][q], d1[1][q], d1[2][q], v);
+    }
+}
+
+// Votes of the lane's reference points against the streamed sources [j0, j1),
+// j1 - j0 a multiple of 4: in each whole block of B = 4 * 64 / (lanes per copy of
+// the group) points, lane sub-group h (its hoff = 16 h bytes) takes points
+// 4h .. 4h + 3; the r < B points after the last whole block go in r / S steps
+// (S = B / 4 sub-groups), sub-group h taking point S q + h in step q (every index
+// stays below j1).  A whole block inside [i0, i1) (the window's interior) is voted
+// without the x test; the choice is a uniform branch per block, so the loads stay
+// one pipeline, two blocks in flight, across the whole range.
+template <int CW, bool WIDE>
+__device__ __forceinline__ void vote_span_lanes(const f4u &desc, __amdgpu_buffer_rsrc_t rs,
+                                                const SoaOffs &so, int j0, int j1, int i0,
+                                                int i1, int B, uint32_t hoff, const LanePts &L,
+                                                const VoteConst &v)
 {
     const int jb = B > 4 ? j0 + (j1 - j0) / B * B : j1;   // B == 4: no tail
     for (int t = jb; t < j1; t += B >> 2) {
+        // with 8 sub-groups the last step may reach 4 points past j1: those lanes
+        // take padding (their loads stay inside the slot's arrays)
         const uint32_t vo = 4u * (uint32_t)(t - jb) + (hoff >> 2);
-        const float ux = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, 4 * jb, 0));
-        const float uy = __uint_as_float(
-            __builtin_amdgcn_raw_buffer_load_b32(rs, vo, 4 * (stride + jb), 0));
-        const float uz = __uint_as_float(
-            __builtin_amdgcn_raw_buffer_load_b32(rs, vo, 4 * (2 * stride + jb), 0));
-        vote_pair<CW>(hist, cvt_flr(Lx - ux), cvt_flr(Ly - uy), cvt_flr(Lz - uz), x0, np, Sy,
-                      Sz, sx4, sy4, negc);
+        uint32_t px = load1(rs, vo, so.o0 + 4 * jb), py = load1(rs, vo, so.o1 + 4 * jb);
+        uint32_t pz = load1(rs, vo, so.o2 + 4 * jb);
+        if (t + (int)(hoff >> 4) >= j1) px = py = pz = kPadSrc;
+        vote_pair<CW, WIDE>(L.x0 - px, L.y0 - py, L.z0 - pz, v);
+        vote_pair<CW, WIDE>(L.x1 - px, L.y1 - py, L.z1 - pz, v);
     }
     j1 = jb;
     if (j0 >= j1) return;
     f4u ax, ay, az, bx, by, bz;
     int j = j0;
-    soa_issue_lanes(desc, stride, j, hoff, ax, ay, az);
+    soa_issue_lanes(desc, so, j, hoff, ax, ay, az);
     for (; j + 2 * B <= j1; j += 2 * B) {
-        soa_issue_lanes(desc, stride, j + B, hoff, bx, by, bz);
+        soa_issue_lanes(desc, so, j + B, hoff, bx, by, bz);
         soa_wait<3>(ax, ay, az);
-        vote4<CW, true>(hist, ax, ay, az, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
-        soa_issue_lanes(desc, stride, min(j + 2 * B, j1 - B), hoff, ax, ay, az);
+        if (j >= i0 && j + B <= i1)
+            vote8<CW, WIDE, false>(ax, ay, az, L, v);
+        else
+            vote8<CW, WIDE, true>(ax, ay, az, L, v);
+        soa_issue_lanes(desc, so, min(j + 2 * B, j1 - B), hoff, ax, ay, az);
         soa_wait<3>(bx, by, bz);
-        vote4<CW, true>(hist, bx, by, bz, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
+        if (j + B >= i0 && j + 2 * B <= i1)
+            vote8<CW, WIDE, false>(bx, by, bz, L, v);
+        else
+            vote8<CW, WIDE, true>(bx, by, bz, L, v);
     }
     soa_wait<0>(ax, ay, az);              // the last block issued, used or not
-    if (j + B <= j1)
-        vote4<CW, true>(hist, ax, ay, az, Lx, Ly, Lz, x0, np, Sy, Sz, sx4, sy4, negc);
+    if (j + B <= j1) vote8<CW, WIDE, true>(ax, ay, az, L, v);
 }
 
-// Source bucket of a scaled x coordinate: floor((P - sb_lo) * sb_scale), clamped
+// Source bucket of a fixed-point x coordinate: (P - sb_lo) >> sb_shift, clamped
 // to the table.  Monotone in P, which is all the vote windows rely on.
-__device__ __forceinline__ int src_bucket(const SweepArgs &a, float P)
+__device__ __forceinline__ int src_bucket(const SweepArgs &a, int32_t P)
 {
-    return min(max(cvt_flr(__fmul_rn(__fsub_rn(P, a.sb_lo), a.sb_scale)), 0), a.sb_n - 1);
+    return min(max(P - a.sb_lo, 0) >> a.sb_shift, a.sb_n - 1);
 }
 
 // Index range [lo, hi) of the rotation's x-sorted sources whose pairs with any
-// reference point of x coordinate in [ymin, ymax] can fall in box x-planes
-// [x0, x1): floor(Y - P) in [x0, x1) implies P in (Y - x1, Y - x0], widened by a
-// margin that exceeds the float rounding of Y - P and of the bounds.  Bucketing
-// is monotone in P, so buckets b(ymin - x1 - e) .. b(ymax - x0 + e) hold every
-// voting source; the per-pair x test stays exact, so the range only has to
-// contain them.
+// reference point of slab-relative x in [ymin, ymax] can fall in the slab's np
+// x-planes: 0 <= Y - P < np 2^16 means ymin - np 2^16 < P <= ymax, exactly (the
+// arithmetic is integer).  Bucketing is monotone in P, so buckets
+// b(ymin - np 2^16 + 1) .. b(ymax) hold every voting source; the per-pair test
+// decides the rest.  [ilo, ihi) is the window's interior: sources whose pairs with
+// every such reference point fall in the slab's x-planes, ymax - np 2^16 < P <=
+// ymin, taken as the whole buckets strictly inside that range (an edge bucket, and
+// the two end buckets that also hold clamped values, are left out).
 __device__ __forceinline__ void src_window(const SweepArgs &a, __amdgpu_buffer_rsrc_t trs,
-                                           int bmin, int bmax, float ymin, float ymax, int x0,
-                                           int x1, int &lo, int &hi)
+                                           int bmin, int bmax, int32_t ymin, int32_t ymax,
+                                           int np, int &lo, int &hi, int &ilo, int &ihi)
 {
-    const float e = 0.015625f + 3.8e-6f * (fabsf(ymin) + fabsf(ymax) + fabsf((float)x0) +
-                                           fabsf((float)x1) + fabsf(a.sb_lo));
     // the table holds buckets bmin .. bmax only (0 below, n above)
-    const int blo = max(src_bucket(a, ymin - (float)x1 - e), bmin);
-    const int bhi = max(src_bucket(a, ymax - (float)x0 + e) + 1, bmin);
-    // both loads issued unconditionally (one memory round trip), then n selected
+    const int blo = max(src_bucket(a, ymin - (np << 16) + 1), bmin);
+    const int bhi = max(src_bucket(a, ymax) + 1, bmin);
+    const int bif = max(src_bucket(a, ymax - (np << 16)) + 1, bmin);
+    const int bie = max(src_bucket(a, ymin + 1), bmin);
+    // the four loads issued unconditionally (one memory round trip), then n selected
     const int tlo = (int)__builtin_amdgcn_raw_buffer_load_b32(trs, 4 * min(blo, bmax), 0, 0);
     const int thi = (int)__builtin_amdgcn_raw_buffer_load_b32(trs, 4 * min(bhi, bmax), 0, 0);
+    const int tif = (int)__builtin_amdgcn_raw_buffer_load_b32(trs, 4 * min(bif, bmax), 0, 0);
+    const int tie = (int)__builtin_amdgcn_raw_buffer_load_b32(trs, 4 * min(bie, bmax), 0, 0);
     lo = blo > bmax ? a.g.n : tlo;
     hi = bhi > bmax ? a.g.n : thi;
+    ilo = bif > bmax ? a.g.n : tif;
+    ihi = bie <= bif ? ilo : (bie > bmax ? a.g.n : tie);
 }
 
 // Votes of all pairs whose bin falls in the box x-planes [x0, x0 + np) into the
@@ -485,30 +596,40 @@ __device__ __forceinline__ void src_window(const SweepArgs &a, __amdgpu_buffer_r
 // G parts per group; waves take units one at a time from an LDS counter
 // (cleared with the slab), so a wave whose ranges were short takes more units
 // instead of idling at the slab's closing barrier.
-//   sorted: a lane group is 2^lg consecutive points of the x-sorted reference,
-//           held by each of the wave's 64 >> lg lane sub-groups; the stream is
+//   sorted: a lane group is 2^(lg+1) consecutive points of the x-sorted
+//           reference, two per lane (points j and j + 2^lg of the group for lane
+//           j), held by each of the wave's 64 >> lg lane sub-groups; the stream is
 //           the window of the rotation's x-sorted sources, padded to a multiple
 //           of 4 and taken in blocks of B = 256 >> lg sources (sub-group h takes
 //           4h .. 4h + 3) plus a strided tail (vote_span_lanes);
 //   else:   lanes hold 64 rotated sources, the stream is the whole reference.
 // lg is a template constant (one instantiation per lane-group size): as a
 // run-time value it cost 1.5% of the sweep.
-template <int CW, int LG, bool SORTED>
+template <int CW, int LG, bool SORTED, bool WIDE>
 __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, uint32_t *hist,
                           int slot)
 {
     const Geom &g = a.g;
     const int tid = threadIdx.x, lane = tid & 63;
     const uint32_t Sy = g.size[1], Sz = g.size[2];
-    const uint32_t sy4 = 4u * (uint32_t)g.row_words, sx4 = sy4 * Sy;
-    const uint32_t negc = 0u - (uint32_t)x0 * sx4;
+    const uint32_t syw = (uint32_t)g.row_words, sxw = syw * Sy;
+    VoteConst v;
+    v.npx = (uint32_t)np << 16;
+    v.syx = Sy << 16;
+    v.szx = Sz << (CW == 16 ? 15 : 16);
+    v.sx = WIDE ? sxw : 4u * sxw;
+    v.sy = WIDE ? syw : 4u * syw;
+    v.base = (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t *)hist;
+    const uint32_t xofs = (uint32_t)x0 << 16;
     const int m = g.m;
+    const int zsel = CW == 16 ? 3 : 2;         // the reference's z array for this width
     uint32_t *ctr = hist + kHistWordsMax + kUnitCounter;
     if (SORTED) {
         constexpr int lg = LG;
-        const int gsz = 1 << lg;
+        const int gsz = 1 << lg;               // lanes per copy of the group
+        const int gref = 2 * gsz;              // reference points per group
         const int B = 256 >> lg;
-        const int ngr = (m + gsz - 1) >> lg;
+        const int ngr = (m + gref - 1) / gref;
         const int G = a.vote_parts > 0 ? a.vote_parts : vote_parts_auto(ngr);
         const int total = ngr * G;
         const uint32_t hoff = 16u * (uint32_t)(lane >> lg);
@@ -516,12 +637,12 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
         // nb <= kSortMax / 4 and p * gmul < 8192, so the product stays below 2^32
         const uint32_t gmul = 8192u / (uint32_t)G;
         const int64_t ns = src_stride(a.scratch_stride);
-        const float *sp = a.scratch + (size_t)slot * slot_floats(a.scratch_stride);
-        const f4u sdesc = soa_desc(sp, ns);
-        const __amdgpu_buffer_rsrc_t srs = soa_rsrc(sp, ns);
-        const __amdgpu_buffer_rsrc_t yrs = soa_rsrc(a.ys, m);
-        const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float *>(sp + 3 * ns), 0, 4 * (kSrcBuckets + 1), 0x00020000);
+        const int32_t *sp = a.scratch + (size_t)slot * slot_words(a.scratch_stride);
+        const f4u sdesc = desc_words(sp, 12 * ns);
+        const __amdgpu_buffer_rsrc_t srs = rsrc(sp, 12 * ns);
+        const SoaOffs so = soa_offs((int)ns, 2);
+        const __amdgpu_buffer_rsrc_t yrs = rsrc(a.yq, 16 * (int64_t)m);
+        const __amdgpu_buffer_rsrc_t trs = rsrc(sp + 3 * ns, 4 * (kSrcBuckets + 1));
         const uint32_t *scr = hist + kHistWordsMax;
         const int bmin = (int)__builtin_amdgcn_readfirstlane(scr[kSrcBmin]);
         const int bmax = (int)__builtin_amdgcn_readfirstlane(scr[kSrcBmax]);
@@ -532,41 +653,56 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             if (u >= total) break;
             const int part = G == 1 ? 0 : u / ngr;
             const int gi = u - part * ngr;
-            const int j = gi * gsz + (lane & (gsz - 1));
-            // padding lanes (j >= m) never vote; their loads stay inside ys (clamped)
-            const uint32_t yo = 4u * (uint32_t)min(j, m - 1);
-            float Yx = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(yrs, yo, 0, 0));
-            float Yy = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(yrs, yo, 4 * m, 0));
-            float Yz = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(yrs, yo, 8 * m, 0));
-            if (j >= m) Yx = Yy = Yz = -1.0e7f;
+            const int j = gi * gref + (lane & (gsz - 1));
+            // padding points (index >= m) never vote; their loads stay inside yq
+            const uint32_t yo0 = 4u * (uint32_t)min(j, m - 1);
+            const uint32_t yo1 = 4u * (uint32_t)min(j + gsz, m - 1);
+            LanePts L;
+            L.x0 = load1(yrs, yo0, 0);
+            L.y0 = load1(yrs, yo0, 4 * m);
+            L.z0 = load1(yrs, yo0, 4 * zsel * m);
+            L.x1 = load1(yrs, yo1, 0);
+            L.y1 = load1(yrs, yo1, 4 * m);
+            L.z1 = load1(yrs, yo1, 4 * zsel * m);
+            if (j >= m) L.x0 = L.y0 = L.z0 = kPadRef;
+            if (j + gsz >= m) L.x1 = L.y1 = L.z1 = kPadRef;
+            L.x0 -= xofs;
+            L.x1 -= xofs;
             // the group's x range: its first and last point (the reference is sorted),
-            // read from lanes 0 and gsz - 1 of the first lane sub-group
-            const float ymin = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Yx), 0));
-            const float ymax = __int_as_float(
-                __builtin_amdgcn_readlane(__float_as_int(Yx), min(m - gi * gsz, gsz) - 1));
-            int lo, hi;
-            src_window(a, trs, bmin, bmax, ymin, ymax, x0, x0 + np, lo, hi);
+            // read from the first lane sub-group
+            const int last = min(m - gi * gref, gref) - 1;
+            const int32_t ymin = (int32_t)__builtin_amdgcn_readlane(L.x0, 0);
+            const int32_t ymax = (int32_t)(last < gsz ? __builtin_amdgcn_readlane(L.x0, last)
+                                                      : __builtin_amdgcn_readlane(L.x1, last - gsz));
+            int lo, hi, ilo, ihi;
+            src_window(a, trs, bmin, bmax, ymin, ymax, np, lo, hi, ilo, ihi);
             lo = uni(lo);
             hi = uni(max(hi, lo));
             // a multiple of 4 inside the padded arrays: the extra points are
-            // sources outside the window or sentinels, rejected by the range tests
+            // sources outside the window or padding, rejected by the range tests
             const int len4 = (hi - lo + 3) & ~3;
             hi = min((int)ns, lo + len4);
             lo = hi - len4;
+            // the interior rounded inwards to the same multiples of 4 (it lies inside
+            // the window, and only real sources are in it)
+            int i0 = lo + ((max(uni(ilo), lo) - lo + 3) & ~3);
+            int i1 = lo + ((min(uni(ihi), hi) - lo) & ~3);
+            if (i1 <= i0) i0 = i1 = hi;
             const uint32_t nb = (uint32_t)(len4 >> 2);
             const int j0 = uni(lo + 4 * (int)((nb * (uint32_t)part * gmul) >> 13));
             const int j1 = part + 1 == G
                                ? hi
                                : uni(lo + 4 * (int)((nb * (uint32_t)(part + 1) * gmul) >> 13));
-            vote_span_lanes<CW>(hist, sdesc, srs, (int)ns, j0, j1, B, hoff, Yx, Yy, Yz, x0,
-                                (uint32_t)np, Sy, Sz, sx4, sy4, negc);
+            vote_span_lanes<CW, WIDE>(sdesc, srs, so, j0, j1, i0, i1, B, hoff, L, v);
         }
     } else {
         const int nsg = (g.n + 63) >> 6;
         const int G = a.vote_parts > 0 ? a.vote_parts : vote_parts_auto(nsg);
         const int total = nsg * G;
-        const f4u rdesc = soa_desc(a.ys, m);
-        const __amdgpu_buffer_rsrc_t rrs = soa_rsrc(a.ys, m);
+        const f4u rdesc = desc_words(a.yq, 16 * (int64_t)m);
+        const __amdgpu_buffer_rsrc_t rrs = rsrc(a.yq, 16 * (int64_t)m);
+        const SoaOffs so = soa_offs(m, zsel);
+        const double Sz = CW == 16 ? g.S15 : g.S16;
         for (;;) {
             int u = 0;
             if (lane == 0) u = (int)atomicAdd(ctr, 1u);
@@ -574,27 +710,30 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             if (u >= total) break;
             const int part = u / nsg;
             const int i = (u - part * nsg) * 64 + lane;
-            float Px = 1.0e7f, Py = 1.0e7f, Pz = 1.0e7f;      // padding lanes never vote
+            uint32_t Px = kPadSrc, Py = kPadSrc, Pz = kPadSrc;      // padding lanes never vote
             if (i < g.n) {
-                float px, py, pz;
-                rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
-                Px = __fmul_rn(px, g.s);
-                Py = __fmul_rn(py, g.s);
-                Pz = __fmul_rn(pz, g.s);
+                int32_t qx, qy, qz;
+                rotate_quant(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], g.S16, Sz, qx,
+                             qy, qz);
+                Px = (uint32_t)qx;
+                Py = (uint32_t)qy;
+                Pz = (uint32_t)qz;
             }
+            // the slab's first plane folded into the source: D_x = Y_x - (P_x + x0 2^16)
+            Px += xofs;
             const int j0 = uni((int)((int64_t)m * part / G));
             const int j1 = uni((int)((int64_t)m * (part + 1) / G));
-            vote_span<CW, false>(hist, rdesc, rrs, m, j0, j1, Px, Py, Pz, x0, (uint32_t)np, Sy,
-                                 Sz, sx4, sy4, negc);
+            vote_span<CW, WIDE>(rdesc, rrs, so, j0, j1, Px, Py, Pz, v);
         }
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // asm-issued LDS atomics
 }
 
-// Bucket-sort the rotated, scaled source points of one rotation by x into this
+// Bucket-sort the rotated sources of one rotation, in fixed point, by x into this
 // workgroup's scratch slot (x, y, z arrays) and write the bucket table after
 // them, so that the vote can restrict each reference lane group to the sources
 // whose pairs can land in the current slab.
+template <int CW>
 __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, uint32_t *scr,
                              int slot)
 {
@@ -603,33 +742,31 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
     uint32_t *cnt = lds;                       // kSrcBuckets counters
     uint32_t *key = lds + kSrcBuckets;         // per source: bucket << 16 | rank
     const int64_t ns = src_stride(a.scratch_stride);
-    float *ox = a.scratch + (size_t)slot * slot_floats(a.scratch_stride);
-    float *oy = ox + ns, *oz = ox + 2 * ns;
-    int32_t *T = reinterpret_cast<int32_t *>(ox + 3 * ns);
+    int32_t *ox = a.scratch + (size_t)slot * slot_words(a.scratch_stride);
+    int32_t *oy = ox + ns, *oz = ox + 2 * ns;
+    int32_t *T = ox + 3 * ns;
+    const double S16 = g.S16, Sz = CW == 16 ? g.S15 : g.S16;
     for (int b = tid; b < a.sb_n; b += kBlock) cnt[b] = 0u;
     __syncthreads();
     // the first kCarry points of each thread stay in registers between the two
     // passes (no second load and rotation)
     constexpr int kCarry = 4;
-    float cpx[kCarry], cpy[kCarry], cpz[kCarry];
+    int32_t cpx[kCarry], cpy[kCarry], cpz[kCarry];
     uint32_t ckey[kCarry];
 #pragma unroll
     for (int r = 0; r < kCarry; ++r) {
         const int i = tid + r * kBlock;
         if (i < g.n) {
-            float px, py, pz;
-            rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
-            cpx[r] = __fmul_rn(px, g.s);
-            cpy[r] = __fmul_rn(py, g.s);
-            cpz[r] = __fmul_rn(pz, g.s);
+            rotate_quant(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], S16, Sz, cpx[r],
+                         cpy[r], cpz[r]);
             const int b = src_bucket(a, cpx[r]);
             ckey[r] = ((uint32_t)b << 16) | atomicAdd(&cnt[b], 1u);
         }
     }
     for (int i = tid + kCarry * kBlock; i < g.n; i += kBlock) {
-        float px, py, pz;
-        rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
-        const int b = src_bucket(a, __fmul_rn(px, g.s));
+        int32_t px, py, pz;
+        rotate_quant(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], S16, Sz, px, py, pz);
+        const int b = src_bucket(a, px);
         key[i] = ((uint32_t)b << 16) | atomicAdd(&cnt[b], 1u);
     }
     __syncthreads();
@@ -681,20 +818,20 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
         }
     }
     for (int i = tid + kCarry * kBlock; i < g.n; i += kBlock) {
-        float px, py, pz;
-        rotate(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], px, py, pz);
+        int32_t px, py, pz;
+        rotate_quant(R, a.src[3 * i], a.src[3 * i + 1], a.src[3 * i + 2], S16, Sz, px, py, pz);
         const uint32_t kk = key[i];
         const uint32_t pos = cnt[kk >> 16] + (kk & 0xFFFFu);
-        ox[pos] = __fmul_rn(px, g.s);
-        oy[pos] = __fmul_rn(py, g.s);
-        oz[pos] = __fmul_rn(pz, g.s);
+        ox[pos] = px;
+        oy[pos] = py;
+        oz[pos] = pz;
     }
-    // sentinels up to the padded stride: windows padded to a multiple of 4 may
-    // stream them, and no pair with them passes the range tests
+    // padding up to the padded stride: windows padded to a multiple of 4 may
+    // stream it, and no pair with it passes the range tests
     if (tid < (int)(ns - g.n)) {
-        ox[g.n + tid] = 1.0e7f;
-        oy[g.n + tid] = 1.0e7f;
-        oz[g.n + tid] = 1.0e7f;
+        ox[g.n + tid] = (int32_t)kPadSrc;
+        oy[g.n + tid] = (int32_t)kPadSrc;
+        oz[g.n + tid] = (int32_t)kPadSrc;
     }
     __syncthreads();
 }
@@ -1032,6 +1169,21 @@ __device__ void score_candidate(const SweepArgs &a, int k, const float *R, int b
     __syncthreads();                          // LDS scratch reused by the caller
 }
 
+// The vote of one slab with the lane-group size and source layout of this call.
+template <int CW, bool WIDE>
+__device__ __forceinline__ void vote_slab_any(const SweepArgs &a, const float *R, int x0, int np,
+                                              uint32_t *hist, int slot, bool sorted, int lg)
+{
+    if (!sorted)
+        vote_slab<CW, 6, false, WIDE>(a, R, x0, np, hist, slot);
+    else if (lg == 3)
+        vote_slab<CW, 3, true, WIDE>(a, R, x0, np, hist, slot);
+    else if (lg == 4)
+        vote_slab<CW, 4, true, WIDE>(a, R, x0, np, hist, slot);
+    else
+        vote_slab<CW, 5, true, WIDE>(a, R, x0, np, hist, slot);
+}
+
 // Vote, mode and score one rotation k with the whole workgroup; `slot` selects
 // the workgroup's source-sort scratch.  Writes a.rec[k].
 template <int CW, int SCORER>
@@ -1044,16 +1196,16 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
     const uint32_t Sy = g.size[1];
     const uint32_t RW = (uint32_t)g.row_words;
     const bool sorted = a.scratch != nullptr;
-    const int lg = a.lane_group == 16   ? 4
-                   : a.lane_group == 32 ? 5
-                   : a.lane_group == 64 ? 6
+    const int lg = a.lane_group == 16   ? 3
+                   : a.lane_group == 32 ? 4
+                   : a.lane_group == 64 ? 5
                                         : lane_group_log2(g.m, g.n, g.size[0], a.ref_x_extent,
                                                           a.vote_parts);
   {
     float R[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) R[e] = kc(a.rot)[9 * k + e];
-    if (sorted) sort_sources(a, R, lds, scr, slot);
+    if (sorted) sort_sources<CW>(a, R, lds, scr, slot);
 
     // ---------------- vote + mode over the slabs ----------------
     // Barriers per slab: after the clear, after the vote, and one inside each
@@ -1069,14 +1221,10 @@ __device__ void sweep_one(const SweepArgs &a, int k, uint32_t *lds, int slot)
         for (int w = tid; w < words4; w += kBlock) h4[w] = make_uint4(0, 0, 0, 0);
         if (tid == 0) scr[kUnitCounter] = 0u;
         __syncthreads();
-        if (!sorted)
-            vote_slab<CW, 6, false>(a, R, x0, np, hist, slot);
-        else if (lg == 4)
-            vote_slab<CW, 4, true>(a, R, x0, np, hist, slot);
-        else if (lg == 5)
-            vote_slab<CW, 5, true>(a, R, x0, np, hist, slot);
+        if (g.wide)
+            vote_slab_any<CW, true>(a, R, x0, np, hist, slot, sorted, lg);
         else
-            vote_slab<CW, 6, true>(a, R, x0, np, hist, slot);
+            vote_slab_any<CW, false>(a, R, x0, np, hist, slot, sorted, lg);
         __syncthreads();
         // the slab's largest count first (cheap), and only when it beats the best of
         // the earlier slabs its lowest position (a later slab never wins a tie: its
@@ -1559,15 +1707,9 @@ __global__ void k_stage_batch(const StageDesc *d, const int32_t *header)
     const int count = header[1];
     for (int inst = blockIdx.y; inst < count; inst += gridDim.y) {
         const StageDesc sd = d[inst];
-        for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < sd.m; j += gridDim.x * blockDim.x) {
-            const int src = sd.perm ? sd.perm[j] : j;
-            for (int a = 0; a < 3; ++a) {
-                const float y = sd.tgt[3 * src + a];
-                const float ofs = 0.5f - (float)sd.klo[a];
-                sd.ys[a * sd.m + j] = __fadd_rn(__fmul_rn(y, sd.s), ofs);
-                sd.yt[a * sd.m + j] = y;
-            }
-        }
+        for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < sd.m; j += gridDim.x * blockDim.x)
+            stage_point(sd.tgt, sd.perm ? sd.perm[j] : j, j, sd.m, sd.S16, sd.S15, sd.klo, sd.yq,
+                        sd.yt);
     }
 }
 

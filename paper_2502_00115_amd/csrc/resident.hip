@@ -92,12 +92,13 @@ dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stre
         DSES_HIP(hipMalloc(&tm->d_perm, 4 * m));
         DSES_HIP(hipMemcpy(tm->d_perm, tm->perm_x.data(), 4 * m, hipMemcpyHostToDevice));
     }
-    const float s = 1.0f / p.delta;
+    double S16, S15;
+    lattice_scales(p.delta, &S16, &S15);
     TargetRes::Stage st{p.delta, {p.klo[0], p.klo[1], p.klo[2]}, nullptr, nullptr, false, 0, 0};
-    st.sorted = ref_x_range(tm->host_aos.data(), tm->perm_x, s, p.klo[0], &st.ylo, &st.yhi);
-    DSES_HIP(hipMalloc(&st.ys, 12 * m));
+    st.sorted = ref_x_range(tm->host_aos.data(), tm->perm_x, p.delta, p.klo[0], &st.ylo, &st.yhi);
+    DSES_HIP(hipMalloc(&st.yq, 16 * m));
     DSES_HIP(hipMalloc(&st.yt, 12 * m));
-    DSES_HIP(launch_stage(tm->aos, tm->d_perm, tm->m, s, p.klo, st.ys, st.yt, stream));
+    DSES_HIP(launch_stage(tm->aos, tm->d_perm, tm->m, S16, S15, p.klo, st.yq, st.yt, stream));
     DSES_HIP(hipStreamSynchronize(stream));
     tm->stages.push_back(st);
     *out = &tm->stages.back();
@@ -132,12 +133,14 @@ dses_status dses_target_create(const float *tgt, int64_t m, const dses_target_op
     dses_status st = copy_to_host(tgt, 3 * (size_t)m, (o.flags & DSES_DEVICE_PTRS) != 0,
                                   &T.host_aos);
     if (st != DSES_OK) { delete t; return st; }
-    for (float v : T.host_aos)
+    for (float v : T.host_aos) {
         if (!std::isfinite(v) || std::fabs(v) > 1e4f) {
             delete t;
             set_error("reference coordinate is non-finite or larger than 1e4");
             return DSES_E_INVAL;
         }
+        T.max_abs = std::max(T.max_abs, std::fabs(v));
+    }
     auto fail = [&](dses_status s) {
         dses_target_destroy(t);
         return s;
@@ -209,7 +212,7 @@ dses_status dses_target_destroy(dses_target *t)
     if (!t) return DSES_E_INVAL;
     TargetRes &T = t->res;
     for (auto &st : T.stages)
-        for (void *q : {(void *)st.ys, (void *)st.yt})
+        for (void *q : {(void *)st.yq, (void *)st.yt})
             if (q) (void)hipFree(q);
     for (auto &g : T.grids) {
         if (g.pts) (void)hipFree(g.pts);
@@ -322,12 +325,15 @@ dses_status dses_register_resident(const dses_target *tgt, const dses_rotset *ro
     job.rot = rots->res.rot;
     job.target = &tgt->res;
     job.host_tgt = tgt->res.host_aos.data();
+    if (!(tgt->res.max_abs <= ref_coord_limit(p))) {
+        set_error("reference coordinate too large for the lattice of this delta and box");
+        return DSES_E_INVAL;
+    }
     if (dev) {
         job.src = src;
     } else {
-        const float lim = coord_limit(p);
         for (int64_t e = 0; e < 3 * n; ++e)
-            if (!(std::fabs(src[e]) <= lim)) {
+            if (!(std::fabs(src[e]) <= kSrcCoordLimit)) {
                 set_error("source coordinate is non-finite or too large for the lattice");
                 return DSES_E_INVAL;
             }

@@ -115,7 +115,7 @@ struct SliceSet {
     SelectDesc *h_sel = nullptr;             // pinned
     int32_t *h_header = nullptr;             // pinned
     void *d_items = nullptr, *d_sel = nullptr, *d_header = nullptr, *d_cursor = nullptr;
-    float *d_scratch = nullptr;              // source-sort scratch of this slice's launch
+    int32_t *d_scratch = nullptr;            // source-sort scratch of this slice's launch
     hipEvent_t done = nullptr;
     hipStream_t stream = nullptr;            // stream the slice ran on
     bool busy = false;
@@ -234,7 +234,7 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
         DSES_HIP(hipMalloc(&s.d_sel, max_slots * sizeof(SelectDesc)));
         DSES_HIP(hipMalloc(&s.d_header, 64));
         DSES_HIP(hipMalloc(&s.d_cursor, 64));
-        DSES_HIP(hipMalloc(&s.d_scratch, (size_t)grid * slot_floats(kServeMaxSrc) * sizeof(float)));
+        DSES_HIP(hipMalloc(&s.d_scratch, (size_t)grid * slot_words(kServeMaxSrc) * sizeof(int32_t)));
         DSES_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
     }
     for (int i = max_slots - 1; i >= 0; --i) free_slots.push_back(i);
@@ -316,13 +316,13 @@ dses_status ServerImpl::prepare(Request *r)
     a = SweepArgs{};
     a.src = d_src;
     a.rot = r->rots->rot;
-    a.ys = stg->ys;
+    a.yq = stg->yq;
     a.yt = stg->yt;
     const bool sorted = r->n <= kSortMax && stg->sorted;
-    a.scratch = sorted ? reinterpret_cast<float *>(4) : nullptr;   // per-slice scratch at launch
+    a.scratch = sorted ? reinterpret_cast<int32_t *>(4) : nullptr;   // per-slice scratch at launch
     a.scratch_stride = kServeMaxSrc;
-    source_buckets(stg->ylo, stg->yhi, g.size[0], &a.sb_lo, &a.sb_scale, &a.sb_n);
-    a.ref_x_extent = (float)(stg->yhi - stg->ylo) + 1.0f;
+    source_buckets(stg->ylo, stg->yhi, g.size[0], &a.sb_lo, &a.sb_shift, &a.sb_n);
+    a.ref_x_extent = ref_x_extent(stg->ylo, stg->yhi);
     a.g = g;
     a.grid = cg;
     if (r->scorer == DSES_SCORER_DF) {
@@ -624,13 +624,16 @@ dses_status dses_server_submit(dses_server *srv, const dses_target *tgt, const d
         set_error("DSES_TRUNC_LP and DSES_VOTES are plain-path metrics");
         st = DSES_E_INVAL;
     }
+    if (st == DSES_OK && !(tgt->res.max_abs <= ref_coord_limit(r->p))) {
+        set_error("reference coordinate too large for the lattice of this delta and box");
+        st = DSES_E_INVAL;
+    }
     if (st != DSES_OK) {
         delete r;
         return st;
     }
-    const float lim = coord_limit(r->p);
     for (int64_t e = 0; e < 3 * n; ++e)
-        if (!(std::fabs(src[e]) <= lim)) {
+        if (!(std::fabs(src[e]) <= kSrcCoordLimit)) {
             delete r;
             set_error("source coordinate is non-finite or too large for the lattice");
             return DSES_E_INVAL;

@@ -26,8 +26,8 @@ evaluation accurate to mu.  The bar, per rotation:
     to the oracle's unique choice when |W| = 1;
   * translation: |t_gpu - delta b| <= 1e-5 max(|delta b|, delta) for the GPU's bin b.
 
-A secondary, labelled check (`compare_f32_formula`) compares bins and votes bit
-for bit with the library's documented single-precision bin formula.
+A secondary, labelled check (`compare_library_formula`) compares bins and votes
+bit for bit with the library's documented fixed-point bin formula.
 """
 import numpy as np
 
@@ -197,13 +197,14 @@ def check_selection(got, rep, delta, label="", among=None):
     return len(W)
 
 
-def compare_f32_formula(gpu, src, tgt, rotations, eps, which=None, label="", **kw):
+def compare_library_formula(gpu, src, tgt, rotations, eps, which=None, label="", zbits=15, **kw):
     """SECONDARY, labelled check of the kernel's arithmetic: bins and votes bit for bit
-    equal to the library's documented single-precision bin formula."""
-    ref = oracle.records(src, tgt, rotations, eps, which=which, vote="f32", metric="votes",
-                         **kw)
+    equal to the library's documented fixed-point bin formula (z at 2^-zbits bins:
+    15 with 16-bit counters, 16 with 32-bit ones)."""
+    ref = oracle.records(src, tgt, rotations, eps, which=which,
+                         vote="lib" if zbits == 15 else "lib32", metric="votes", **kw)
     np.testing.assert_array_equal(gpu["votes"], ref["votes"],
-                                  err_msg=f"{label}: votes (single-precision formula)")
+                                  err_msg=f"{label}: votes (library fixed-point formula)")
     v = ref["valid"].astype(bool)
     np.testing.assert_array_equal(gpu["bin"][v], ref["bin"][v],
-                                  err_msg=f"{label}: bins (single-precision formula)")
+                                  err_msg=f"{label}: bins (library fixed-point formula)")

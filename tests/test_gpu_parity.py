@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 from paper_2502_00115_amd import synth
-from parity import check_selection, compare_f32_formula, compare_records
+from parity import check_selection, compare_library_formula, compare_records
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -39,7 +39,7 @@ def test_c1_records_and_selection(seed):
     rep = compare_records(got.records, ref, len(p.src), label=p.name)
     check_selection(got, rep, p.eps, label=p.name)
     # secondary, labelled: the kernel's arithmetic is the documented float formula
-    compare_f32_formula(got.records, p.src, p.tgt, p.rotations, p.eps, label=p.name)
+    compare_library_formula(got.records, p.src, p.tgt, p.rotations, p.eps, label=p.name)
     print(p.name, {k: v for k, v in rep.items() if np.isscalar(v)})
 
 

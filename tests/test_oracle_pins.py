@@ -240,24 +240,48 @@ def test_pinned_and_admissible_modes_by_enumeration(seed):
 
 
 @pytest.mark.parametrize("seed", range(2))
-def test_vote_margin_covers_the_single_precision_formula(seed):
-    """The margin mu bounds the float32 rounding of the bin decision: on an
-    object-scale draw every pair whose bin under the library's single-precision
-    formula differs from the definition's lies within mu of a face."""
+@pytest.mark.parametrize("zbits", [15, 16])
+def test_vote_margin_covers_the_fixed_point_formula(seed, zbits):
+    """The library's fixed-point bin decision is off the definition by at most
+    2^-zbits bins (two roundings to half a unit of 2^-16 or 2^-zbits bins): on an
+    object-scale draw, and on the same draw moved far from the origin (large
+    magnitudes, where a float32 evaluation would lose digits), every pair whose
+    bin under that formula differs from the definition's lies within 2^-zbits
+    bins of a face, so the margin mu = 1e-4 covers it."""
     p = synth.make_c2(seed)
     rng = np.random.default_rng(seed)
     src = p.src[rng.choice(len(p.src), 200, replace=False)]
     tgt = p.tgt
-    mu = oracle.vote_margin(src, tgt, p.eps)
-    for R in p.rotations[rng.choice(len(p.rotations), 6, replace=False)]:
-        c64, out, inn, info = oracle.vote64(src, tgt, R, p.eps, mu=mu)
-        c32, mode32, M32 = oracle.vote_f32(src, tgt, R, p.eps)
-        diff = c32.astype(np.int64) - c64
-        # every change is explained by fragile pairs
-        assert np.all(diff <= inn) and np.all(-diff <= out)
-        if info["pinned"]:
-            assert tuple(mode32) == info["mode"]
-            assert info["lo"] <= M32 <= info["hi"]
+    assert oracle.vote_margin(src, tgt, p.eps) == 1e-4
+    tight = 2.0 ** -zbits + 1e-9
+    far = np.float32(37.0)
+    for shift in (np.float32(0.0), far):
+        t2 = (tgt + shift).astype(np.float32)
+        box = dict(t_min=np.full(3, float(shift) - 1.0, np.float32),
+                   t_max=np.full(3, float(shift) + 1.0, np.float32))
+        for R in p.rotations[rng.choice(len(p.rotations), 4, replace=False)]:
+            c64, out, inn, info = oracle.vote64(src, t2, R, p.eps, mu=tight, **box)
+            cl, model, Ml = oracle.vote_lib(src, t2, R, p.eps, zbits=zbits, **box)
+            diff = cl.astype(np.int64) - c64
+            # every change is explained by pairs within 2^-zbits of a face
+            assert np.all(diff <= inn) and np.all(-diff <= out)
+            if info["pinned"]:
+                assert tuple(model) == info["mode"]
+                assert info["lo"] <= Ml <= info["hi"]
+
+
+def test_fixed_point_formula_is_not_the_definition_at_faces():
+    """A pair whose u + 1/2 lies 2^-18 bins below a face: the definition puts it in
+    the lower bin, the 2^-15 fixed-point formula may not -- the disagreement the
+    fragility margin exists for.  The oracle marks that pair fragile."""
+    d = 0.0625                                 # dyadic pitch: the exact u is known
+    y = np.float32((3.0 - 0.5 - 2.0 ** -18) * d)   # u + 1/2 = 3 - 2^-18
+    src = np.zeros((1, 3), np.float32)
+    tgt = np.array([[0.0, 0.0, y]], np.float32)
+    cnt, out, inn, info = oracle.vote64(src, tgt, np.eye(3, dtype=np.float32), d)
+    assert info["mode"] == (0, 0, 2) and info["frag"] == 1 and not info["pinned"]
+    _, mode_lib, _ = oracle.vote_lib(src, tgt, np.eye(3, dtype=np.float32), d, zbits=15)
+    assert tuple(mode_lib) in {(0, 0, 2), (0, 0, 3)}
 
 
 def test_round_half_goes_up():

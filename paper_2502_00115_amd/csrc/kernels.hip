@@ -389,16 +389,19 @@ __device__ __forceinline__ void soa_issue4(const f4u &desc, const SoaOffs &so, i
                  : "s"(desc), "s"(o0), "s"(o1), "s"(o2));
 }
 
-// Points j + 4h .. j + 4h + 3 of such a set, h = hoff / 16 per lane.
-__device__ __forceinline__ void soa_issue_lanes(const f4u &desc, const SoaOffs &so, int j,
-                                                uint32_t hoff, f4u &x, f4u &y, f4u &z)
+// Sources j + 4h .. j + 4h + 3 of a sorted-source slot (x array of ns int32 at
+// byte 0, then the 64-bit yz array at byte 4 ns), h = hoff / 16 per lane: x
+// through hoff, the yz pairs of sources 4h, 4h + 1 and 4h + 2, 4h + 3 through
+// 2 hoff.
+__device__ __forceinline__ void src_issue_lanes(const f4u &desc, int ns, int j, uint32_t hoff,
+                                                uint32_t hoff2, f4u &x, f4u &yz01, f4u &yz23)
 {
-    const int o0 = so.o0 + 4 * j, o1 = so.o1 + 4 * j, o2 = so.o2 + 4 * j;
-    asm volatile("buffer_load_dwordx4 %0, %3, %4, %5 offen\n\t"
-                 "buffer_load_dwordx4 %1, %3, %4, %6 offen\n\t"
-                 "buffer_load_dwordx4 %2, %3, %4, %7 offen"
-                 : "=&v"(x), "=&v"(y), "=&v"(z)
-                 : "v"(hoff), "s"(desc), "s"(o0), "s"(o1), "s"(o2));
+    const int o0 = 4 * j, o1 = 4 * ns + 8 * j, o2 = o1 + 16;
+    asm volatile("buffer_load_dwordx4 %0, %3, %5, %6 offen\n\t"
+                 "buffer_load_dwordx4 %1, %4, %5, %7 offen\n\t"
+                 "buffer_load_dwordx4 %2, %4, %5, %8 offen"
+                 : "=&v"(x), "=&v"(yz01), "=&v"(yz23)
+                 : "v"(hoff), "v"(hoff2), "s"(desc), "s"(o0), "s"(o1), "s"(o2));
 }
 
 // Wait until all but the newest N vector-memory operations are complete; the
@@ -479,31 +482,53 @@ __device__ __forceinline__ void vote_span(const f4u &desc, __amdgpu_buffer_rsrc_
 constexpr uint32_t kPadSrc = 0x80000000u;
 constexpr uint32_t kPadRef = 0x7FFFFFFFu;
 
-// A lane's two reference points (vote_slab's sorted layout).
+// A lane's two reference points (vote_slab's sorted layout): x, and y and z as
+// one 64-bit value (y << 32) | (z + 2^31).
 struct LanePts {
-    uint32_t x0, y0, z0, x1, y1, z1;
+    uint32_t x0, x1;
+    uint64_t yz0, yz1;
 };
+
+// The sorted sources keep x, and -((y << 32) | (z + 2^31)) as one 64-bit value, so
+// one 64-bit add gives both differences of a pair: the low word is
+// D_z = z_ref - z_src (mod 2^32) and the high word y_ref - y_src - [D_z < 0]
+// (the bias 2^31 makes the unsigned borrow that of the signed difference).  A
+// pair with D_z < 0 fails the z test, so every pair that votes has its exact D_y.
+__device__ __forceinline__ uint64_t yz_pack(uint32_t y, uint32_t z)
+{
+    return ((uint64_t)y << 32) | (uint64_t)(z + 0x80000000u);
+}
+
+__device__ __forceinline__ uint64_t add64(uint64_t a, uint64_t b)
+{
+    uint64_t r;
+    asm("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 
 // Votes of a lane's two reference points against four streamed sources: each
 // 48 bytes a lane loads serve eight pairs (the vector-memory return path, 64
 // bytes per clock per CU, bounded the vote at one point per lane).
 template <int CW, bool WIDE, bool XT>
-__device__ __forceinline__ void vote8(f4u x, f4u y, f4u z, const LanePts &L, const VoteConst &v)
+__device__ __forceinline__ void vote8(f4u x, f4u yz01, f4u yz23, const LanePts &L,
+                                      const VoteConst &v)
 {
-    uint32_t d0[3][4], d1[3][4];
+    typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+    const u64x2 n01 = __builtin_bit_cast(u64x2, yz01), n23 = __builtin_bit_cast(u64x2, yz23);
+    uint32_t dx0[4], dx1[4];
+    uint64_t e0[4], e1[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        d0[0][q] = L.x0 - x[q];
-        d0[1][q] = L.y0 - y[q];
-        d0[2][q] = L.z0 - z[q];
-        d1[0][q] = L.x1 - x[q];
-        d1[1][q] = L.y1 - y[q];
-        d1[2][q] = L.z1 - z[q];
+        const uint64_t nq = q < 2 ? n01[q] : n23[q - 2];
+        dx0[q] = L.x0 - x[q];
+        dx1[q] = L.x1 - x[q];
+        e0[q] = add64(L.yz0, nq);
+        e1[q] = add64(L.yz1, nq);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        vote_pair<CW, WIDE, XT>(d0[0][q], d0[1][q], d0[2][q], v);
-        vote_pair<CW, WIDE, XT>(d1[0][q], d1[1][q], d1[2][q], v);
+        vote_pair<CW, WIDE, XT>(dx0[q], (uint32_t)(e0[q] >> 32), (uint32_t)e0[q], v);
+        vote_pair<CW, WIDE, XT>(dx1[q], (uint32_t)(e1[q] >> 32), (uint32_t)e1[q], v);
     }
 }
 
@@ -516,35 +541,41 @@ __device__ __forceinline__ void vote8(f4u x, f4u y, f4u z, const LanePts &L, con
 // without the x test; the choice is a uniform branch per block, so the loads stay
 // one pipeline, two blocks in flight, across the whole range.
 template <int CW, bool WIDE>
-__device__ __forceinline__ void vote_span_lanes(const f4u &desc, __amdgpu_buffer_rsrc_t rs,
-                                                const SoaOffs &so, int j0, int j1, int i0,
-                                                int i1, int B, uint32_t hoff, const LanePts &L,
+__device__ __forceinline__ void vote_span_lanes(const f4u &desc, __amdgpu_buffer_rsrc_t rs, int ns,
+                                                int j0, int j1, int i0, int i1, int B,
+                                                uint32_t hoff, const LanePts &L,
                                                 const VoteConst &v)
 {
     const int jb = B > 4 ? j0 + (j1 - j0) / B * B : j1;   // B == 4: no tail
+    const uint32_t hoff2 = 2u * hoff;
     for (int t = jb; t < j1; t += B >> 2) {
         // with 8 sub-groups the last step may reach 4 points past j1: those lanes
         // take padding (their loads stay inside the slot's arrays)
         const uint32_t vo = 4u * (uint32_t)(t - jb) + (hoff >> 2);
-        uint32_t px = load1(rs, vo, so.o0 + 4 * jb), py = load1(rs, vo, so.o1 + 4 * jb);
-        uint32_t pz = load1(rs, vo, so.o2 + 4 * jb);
-        if (t + (int)(hoff >> 4) >= j1) px = py = pz = kPadSrc;
-        vote_pair<CW, WIDE>(L.x0 - px, L.y0 - py, L.z0 - pz, v);
-        vote_pair<CW, WIDE>(L.x1 - px, L.y1 - py, L.z1 - pz, v);
+        uint32_t px = load1(rs, vo, 4 * jb);
+        uint64_t nyz = ((uint64_t)load1(rs, 2u * vo, 4 * ns + 8 * jb + 4) << 32) |
+                       (uint64_t)load1(rs, 2u * vo, 4 * ns + 8 * jb);
+        if (t + (int)(hoff >> 4) >= j1) {
+            px = kPadSrc;
+            nyz = 0x8000000000000000ull;        // -yz_pack(kPadSrc, kPadSrc)
+        }
+        const uint64_t e0 = add64(L.yz0, nyz), e1 = add64(L.yz1, nyz);
+        vote_pair<CW, WIDE>(L.x0 - px, (uint32_t)(e0 >> 32), (uint32_t)e0, v);
+        vote_pair<CW, WIDE>(L.x1 - px, (uint32_t)(e1 >> 32), (uint32_t)e1, v);
     }
     j1 = jb;
     if (j0 >= j1) return;
     f4u ax, ay, az, bx, by, bz;
     int j = j0;
-    soa_issue_lanes(desc, so, j, hoff, ax, ay, az);
+    src_issue_lanes(desc, ns, j, hoff, hoff2, ax, ay, az);
     for (; j + 2 * B <= j1; j += 2 * B) {
-        soa_issue_lanes(desc, so, j + B, hoff, bx, by, bz);
+        src_issue_lanes(desc, ns, j + B, hoff, hoff2, bx, by, bz);
         soa_wait<3>(ax, ay, az);
         if (j >= i0 && j + B <= i1)
             vote8<CW, WIDE, false>(ax, ay, az, L, v);
         else
             vote8<CW, WIDE, true>(ax, ay, az, L, v);
-        soa_issue_lanes(desc, so, min(j + 2 * B, j1 - B), hoff, ax, ay, az);
+        src_issue_lanes(desc, ns, min(j + 2 * B, j1 - B), hoff, hoff2, ax, ay, az);
         soa_wait<3>(bx, by, bz);
         if (j + B >= i0 && j + 2 * B <= i1)
             vote8<CW, WIDE, false>(bx, by, bz, L, v);
@@ -640,7 +671,6 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
         const int32_t *sp = a.scratch + (size_t)slot * slot_words(a.scratch_stride);
         const f4u sdesc = desc_words(sp, 12 * ns);
         const __amdgpu_buffer_rsrc_t srs = rsrc(sp, 12 * ns);
-        const SoaOffs so = soa_offs((int)ns, 2);
         const __amdgpu_buffer_rsrc_t yrs = rsrc(a.yq, 16 * (int64_t)m);
         const __amdgpu_buffer_rsrc_t trs = rsrc(sp + 3 * ns, 4 * (kSrcBuckets + 1));
         const uint32_t *scr = hist + kHistWordsMax;
@@ -657,17 +687,17 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             // padding points (index >= m) never vote; their loads stay inside yq
             const uint32_t yo0 = 4u * (uint32_t)min(j, m - 1);
             const uint32_t yo1 = 4u * (uint32_t)min(j + gsz, m - 1);
+            uint32_t x0 = load1(yrs, yo0, 0), y0 = load1(yrs, yo0, 4 * m);
+            uint32_t z0 = load1(yrs, yo0, 4 * zsel * m);
+            uint32_t x1 = load1(yrs, yo1, 0), y1 = load1(yrs, yo1, 4 * m);
+            uint32_t z1 = load1(yrs, yo1, 4 * zsel * m);
+            if (j >= m) x0 = y0 = z0 = kPadRef;
+            if (j + gsz >= m) x1 = y1 = z1 = kPadRef;
             LanePts L;
-            L.x0 = load1(yrs, yo0, 0);
-            L.y0 = load1(yrs, yo0, 4 * m);
-            L.z0 = load1(yrs, yo0, 4 * zsel * m);
-            L.x1 = load1(yrs, yo1, 0);
-            L.y1 = load1(yrs, yo1, 4 * m);
-            L.z1 = load1(yrs, yo1, 4 * zsel * m);
-            if (j >= m) L.x0 = L.y0 = L.z0 = kPadRef;
-            if (j + gsz >= m) L.x1 = L.y1 = L.z1 = kPadRef;
-            L.x0 -= xofs;
-            L.x1 -= xofs;
+            L.x0 = x0 - xofs;
+            L.x1 = x1 - xofs;
+            L.yz0 = yz_pack(y0, z0);
+            L.yz1 = yz_pack(y1, z1);
             // the group's x range: its first and last point (the reference is sorted),
             // read from the first lane sub-group
             const int last = min(m - gi * gref, gref) - 1;
@@ -693,7 +723,7 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
             const int j1 = part + 1 == G
                                ? hi
                                : uni(lo + 4 * (int)((nb * (uint32_t)(part + 1) * gmul) >> 13));
-            vote_span_lanes<CW, WIDE>(sdesc, srs, so, j0, j1, i0, i1, B, hoff, L, v);
+            vote_span_lanes<CW, WIDE>(sdesc, srs, (int)ns, j0, j1, i0, i1, B, hoff, L, v);
         }
     } else {
         const int nsg = (g.n + 63) >> 6;
@@ -729,6 +759,12 @@ __device__ void vote_slab(const SweepArgs &a, const float *R, int x0, int np, ui
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // asm-issued LDS atomics
 }
 
+// A source's (y, z) pair as the reference's: (y << 32) | (z + 2^31).
+__device__ __forceinline__ uint64_t yz_src(int32_t y, int32_t z)
+{
+    return ((uint64_t)(uint32_t)y << 32) | (uint64_t)((uint32_t)z + 0x80000000u);
+}
+
 // Bucket-sort the rotated sources of one rotation, in fixed point, by x into this
 // workgroup's scratch slot (x, y, z arrays) and write the bucket table after
 // them, so that the vote can restrict each reference lane group to the sources
@@ -743,7 +779,7 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
     uint32_t *key = lds + kSrcBuckets;         // per source: bucket << 16 | rank
     const int64_t ns = src_stride(a.scratch_stride);
     int32_t *ox = a.scratch + (size_t)slot * slot_words(a.scratch_stride);
-    int32_t *oy = ox + ns, *oz = ox + 2 * ns;
+    uint64_t *oyz = reinterpret_cast<uint64_t *>(ox + ns);
     int32_t *T = ox + 3 * ns;
     const double S16 = g.S16, Sz = CW == 16 ? g.S15 : g.S16;
     for (int b = tid; b < a.sb_n; b += kBlock) cnt[b] = 0u;
@@ -813,8 +849,7 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
         if (i < g.n) {
             const uint32_t pos = cnt[ckey[r] >> 16] + (ckey[r] & 0xFFFFu);
             ox[pos] = cpx[r];
-            oy[pos] = cpy[r];
-            oz[pos] = cpz[r];
+            oyz[pos] = 0ull - yz_src(cpy[r], cpz[r]);
         }
     }
     for (int i = tid + kCarry * kBlock; i < g.n; i += kBlock) {
@@ -823,15 +858,13 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
         const uint32_t kk = key[i];
         const uint32_t pos = cnt[kk >> 16] + (kk & 0xFFFFu);
         ox[pos] = px;
-        oy[pos] = py;
-        oz[pos] = pz;
+        oyz[pos] = 0ull - yz_src(py, pz);
     }
     // padding up to the padded stride: windows padded to a multiple of 4 may
     // stream it, and no pair with it passes the range tests
     if (tid < (int)(ns - g.n)) {
         ox[g.n + tid] = (int32_t)kPadSrc;
-        oy[g.n + tid] = (int32_t)kPadSrc;
-        oz[g.n + tid] = (int32_t)kPadSrc;
+        oyz[g.n + tid] = 0ull - yz_src((int32_t)kPadSrc, (int32_t)kPadSrc);
     }
     __syncthreads();
 }

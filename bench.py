@@ -67,13 +67,14 @@ def load_traffic(workload):
     return rec.get("hbm_bytes_per_launch")
 
 
-def make_workload(name):
+def make_workload(name, grid_level=4):
     from paper_2502_00115_amd import synth
     if name == "c1":
         return synth.make_c1(0), "plain DSES, 256-pt ellipsoid, 64-pt source, 577 rotations"
     if name == "c5":
-        return synth.make_c5(0), ("scene-scale, 16,384-pt reference, 4,096-pt source, "
-                                  "294,912-rotation Hopf grid")
+        p = synth.make_c5(0, grid_level=grid_level)
+        return p, (f"scene-scale, 16,384-pt reference, 4,096-pt source, "
+                   f"{len(p.rotations):,}-rotation Hopf grid")
     if name == "local":
         return synth.make_local(0), ("local registration with an initial guess: 0.1 m object, "
                                      "2,048-pt reference, 1,434-pt partial source, Euler grid "
@@ -163,7 +164,7 @@ def bench_batch(args):
     return {"metric": "candidate poses {R,t} scored/sec (1 GPU), batched",
             "value": cands / batched, "unit": "candidates/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": batched * 1e3, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "scaling": "weak", "vs_baseline": None, "dtype": "i32 vote, f32 score", "data": "synthetic",
             "config": {"workload": "64 registrations, M 512-4096 log-uniform, N 30-80% cut, "
                                    "K 4,608-36,864 rotations, one persistent launch replayed "
                                    "from a HIP graph", "candidates": cands},
@@ -207,7 +208,7 @@ def bench_fig2(args):
     return {"metric": "registration time vs search range (1 GPU)", "value": total / secs,
             "unit": "candidates/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
             "ms_per_step": secs * 1e3, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "vs_baseline": None, "dtype": "i32 vote, f32 score", "data": "synthetic",
             "config": {"workload": "object-scale registration (717-pt source, 1,024-pt "
                                    "reference, eps = delta = 0.03) over Euler grids of 2.5 deg "
                                    "steps; rotation range at +-0.2 translation, translation "
@@ -243,7 +244,7 @@ def bench_exhaustive(args):
     return {"metric": "candidate poses {R,t} scored/sec (1 GPU), exhaustive Alg. 1 vs DSES",
             "value": k * bins ** 3 / t_exh, "unit": "candidates/s", "n_gpus": 1,
             "steps": args.steps, "warmup": 1, "ms_per_step": t_exh * 1e3,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32 vote, f32 score",
             "data": "synthetic",
             "config": {"workload": f"64-pt source, 256-pt reference, {k} rotations, translation "
                                    f"box +-0.5 at delta 0.05 ({bins}^3 lattice points); exact "
@@ -345,7 +346,7 @@ def bench_serve(args, n_req=None, quiet=False):
     return {"metric": "registration latency p50/p99, served vs plain (1 GPU)",
             "value": cands / served_wall, "unit": "candidates/s", "n_gpus": 1,
             "steps": n_req, "warmup": 8, "ms_per_step": served_wall / n_req * 1e3,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32 vote, f32 score",
             "data": "synthetic",
             "config": {"workload": f"{n_req} Poisson requests (rate 0.8x plain capacity = "
                                    f"{rate:.2f}/s) vs 8 resident references with 128^3 "
@@ -377,7 +378,7 @@ def bench_plain(args, workload, steps, warmup, cpu_sample, scorer="auto", q=0.0)
     import torch
     from paper_2502_00115_amd import dses
 
-    p, desc = make_workload(workload)
+    p, desc = make_workload(workload, getattr(args, "grid_level", 4))
     dev = torch.device("cuda:0")
     src = torch.from_numpy(p.src).to(dev)
     tgt = torch.from_numpy(p.tgt).to(dev)
@@ -435,7 +436,8 @@ def bench_plain(args, workload, steps, warmup, cpu_sample, scorer="auto", q=0.0)
     achieved = flop_per_launch / (sweep_ms * 1e-3) / 1e12
     # the counters were taken on the default configuration of the workload (every
     # rotation scored, automatic scorer); other configurations run other kernels
-    traffic = load_traffic(workload) if q == 0.0 and scorer == "auto" else None
+    full = workload != "c5" or getattr(args, "grid_level", 4) == 4
+    traffic = load_traffic(workload) if q == 0.0 and scorer == "auto" and full else None
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": "candidate poses {R,t} scored/sec (1 GPU) + p50/p99 registration latency, "
@@ -449,7 +451,7 @@ def bench_plain(args, workload, steps, warmup, cpu_sample, scorer="auto", q=0.0)
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "i32 vote, f32 score",
         "data": "synthetic",
         "config": {"workload": desc, "n_src": n, "n_ref": m, "rotations": k, "eps": p.eps,
                    "metric": "trunc_l2", "scorer": scorer, "q": q,
@@ -487,6 +489,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=WORKLOADS, default="c5")
     ap.add_argument("--scorer", default="auto")
+    ap.add_argument("--grid-level", type=int, default=4, choices=(0, 1, 2, 3, 4),
+                    help="c5: Hopf grid level of the rotation list (4: 294,912 rotations, the "
+                         "workload; lower levels are samples for profiling)")
     ap.add_argument("--q", type=float, default=0.0,
                     help="pruning of Alg. 2: score only rotations with M_k >= q M* (0: all)")
     ap.add_argument("--cpu-sample", type=int, default=-1,
@@ -540,7 +545,8 @@ def main():
         return
     out = bench_plain(args, args.workload, args.steps, args.warmup, args.cpu_sample,
                       args.scorer, args.q)
-    if args.workload == "c5" and not args.alone and args.scorer == "auto" and args.q == 0.0:
+    if (args.workload == "c5" and not args.alone and args.scorer == "auto" and args.q == 0.0
+            and args.grid_level == 4):
         # the metric's second half: served vs plain latency on the serving workload
         sv = bench_serve(args, n_req=min(args.requests, 100))
         out["served_vs_plain"] = {"workload": sv["config"]["workload"],

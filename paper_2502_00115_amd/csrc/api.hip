@@ -169,6 +169,16 @@ dses_status resolve_params(float eps, int metric, float delta_t, float tau, cons
     return DSES_OK;
 }
 
+int counter_bits_for(int64_t bound, int32_t n, int32_t m, const Params &p)
+{
+    if (bound > 65535) return 32;
+    const int64_t plane_words = (int64_t)p.size[1] * p.size[2];
+    const int64_t pps = std::max<int64_t>(1, std::min<int64_t>((kHistWordsMax & ~3) / plane_words,
+                                                               p.size[0]));
+    const int64_t nslabs32 = (p.size[0] + pps - 1) / pps;
+    return (int64_t)n * m >= (int64_t)nslabs32 << 20 ? 32 : 16;
+}
+
 dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, int counter_bits,
                       Geom *g)
 {
@@ -551,7 +561,7 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     const int64_t bound =
         job.target ? target_block_population(const_cast<TargetRes *>(job.target), p) * job.n
                    : counter_bound(ht, job.m, job.n, p);
-    const int counter_bits = bound <= 65535 ? 16 : 32;
+    const int counter_bits = counter_bits_for(bound, job.n, job.m, p);
     Geom g;
     if ((st = plan_geom(c, p, job.n, job.m, counter_bits, &g)) != DSES_OK) return st;
 

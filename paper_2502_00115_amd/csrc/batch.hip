@@ -306,7 +306,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
         x.host_tgt = ht;
         const int64_t bound = T ? target_block_population(const_cast<TargetRes *>(T), x.p) * x.n
                                 : counter_bound(ht, x.m, x.n, x.p);
-        const int bits = bound <= 65535 ? 16 : 32;
+        const int bits = counter_bits_for(bound, x.n, x.m, x.p);
         if ((st = plan_geom(c, x.p, x.n, x.m, bits, &x.g)) != DSES_OK) { x.status = st; return; }
         if (T) {
             auto *tm = const_cast<TargetRes *>(T);

@@ -95,6 +95,12 @@ dses_status resolve_params(float eps, int metric, float delta_t, float tau, cons
 float ref_coord_limit(const Params &p);
 constexpr float kSrcCoordLimit = 1.0e4f;
 
+// Counter width of the vote: 32 bits when some bin could reach 2^16 votes (the
+// proven bound), and also when every 32-bit slab would still carry at least
+// 2^20 pairs, where the two VALU of the 16-bit increment cost more than the
+// doubled per-slab work (4,096 x 16,384 points, box 101^3, 2.0M pairs per 32-bit
+// slab: 3.4% faster; 717 x 1,024 points, box 69^3, 82K pairs: 25% slower).
+int counter_bits_for(int64_t bound, int32_t n, int32_t m, const Params &p);
 dses_status plan_geom(const Context *c, const Params &p, int32_t n, int32_t m, int counter_bits,
                       Geom *g);
 // Upper bound on any bin's vote count (decides 16- vs 32-bit LDS counters):

@@ -290,7 +290,7 @@ ServerImpl::~ServerImpl()
 dses_status ServerImpl::prepare(Request *r)
 {
     auto *tm = const_cast<TargetRes *>(r->target);
-    const int bits = target_block_population(tm, r->p) * r->n <= 65535 ? 16 : 32;
+    const int bits = counter_bits_for(target_block_population(tm, r->p) * r->n, r->n, r->m, r->p);
     Geom g;
     dses_status st = plan_geom(c, r->p, r->n, r->m, bits, &g);
     if (st != DSES_OK) return st;

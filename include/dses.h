@@ -236,6 +236,30 @@ dses_status dses_register(const float *src, int64_t n, const float *tgt, int64_t
                           const float *rotations, int64_t k, float eps, dses_metric metric,
                           const dses_options *opt, dses_result *out);
 
+/* dses_register for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and records as dses_register, with these limits:
+ *  - src, tgt, rotations (and opt->records, if given) are device pointers:
+ *    opt->flags must be exactly DSES_DEVICE_PTRS; top_k and q must be 0; the DF
+ *    scorer is not available (it needs a resident target);
+ *  - every device buffer of the call (staged reference, cell grid, source-sort
+ *    slots, records unless opt->records is given, result, status) comes from one
+ *    static device array of dses_noalloc_scratch_bytes() (64 MiB) per GPU; the
+ *    call makes no hipMalloc, hipFree or pinned-host allocation.  A call that
+ *    needs more returns DSES_E_NOMEM with a message naming the limit (the
+ *    scene-scale registration, 4,096 x 16,384 points and 294,912 rotations,
+ *    needs about 33 MiB);
+ *  - the array is shared by every call on that GPU and keeps the last call's
+ *    contents; calls are serialised by the library and synchronous, but work of
+ *    another process or library writing the same addresses would race.
+ * Host working memory for the reference's sort and cell grid is ordinary heap. */
+dses_status dses_register_noalloc(const float *src, int64_t n, const float *tgt, int64_t m,
+                                  const float *rotations, int64_t k, float eps,
+                                  dses_metric metric, const dses_options *opt, dses_result *out);
+
+/* Size in bytes of the per-GPU scratch array of dses_register_noalloc. */
+size_t dses_noalloc_scratch_bytes(void);
+
 /* Alg. 1, the pure exhaustive search, as a baseline: every rotation of the list
  * with every lattice translation b delta_t of the box, each scored like a DSES
  * candidate (BRUTE or GRID scorer; any metric but DSES_VOTES).  opt->records gets

@@ -516,8 +516,25 @@ static int effective_scorer(const Job &job)
 // the plain driver
 // ---------------------------------------------------------------------------
 dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check_inputs,
-                      dses_result *out, const dses_options &o)
+                      dses_result *out, const dses_options &o, Arena *arena)
 {
+    // a device buffer of the call: from the arena when given, else the context's
+    auto dbuf = [&](DevBuf &b, size_t bytes, void **ptr) -> dses_status {
+        if (arena) {
+            *ptr = arena->take(bytes);
+            if (*ptr) return DSES_OK;
+            set_error("the call needs more than the " + std::to_string(arena->cap >> 20) +
+                      " MiB scratch array of the no-allocation entry point");
+            return DSES_E_NOMEM;
+        }
+        const dses_status s = b.ensure(bytes);
+        *ptr = b.ptr;
+        return s;
+    };
+    if (arena && (o.q > 0.0f || o.top_k > 0 || c->timing_enabled || job.exhaustive)) {
+        set_error("the no-allocation path takes no pruning, top-k, timing or Alg. 1");
+        return DSES_E_INVAL;
+    }
     const Params &p = job.p;
     void *records = o.records;
     const bool on_device = (o.flags & DSES_DEVICE_PTRS) != 0;
@@ -582,29 +599,35 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     int32_t ylo = 0, yhi = 0;
     const bool sorted = job.n <= kSortMax && ref_x_range(ht, *perm, p.delta, p.klo[0], &ylo, &yhi);
     const int grid = std::max(1, std::min(job.k, c->n_cu));
-    if ((st = c->perm.ensure(m * sizeof(int32_t))) != DSES_OK) return st;
-    DSES_HIP(hipMemcpyAsync(c->perm.ptr, perm->data(), m * sizeof(int32_t),
-                            hipMemcpyHostToDevice, stream));
-    if (sorted &&
-        (st = c->scratch.ensure((size_t)grid * slot_words(job.n) * sizeof(int32_t))) != DSES_OK)
+    void *d_perm = nullptr, *d_scratch = nullptr, *d_yq = nullptr, *d_yt = nullptr;
+    void *d_rec = nullptr, *d_res = nullptr, *d_status = nullptr;
+    if ((st = dbuf(c->perm, m * sizeof(int32_t), &d_perm)) != DSES_OK) return st;
+    DSES_HIP(hipMemcpyAsync(d_perm, perm->data(), m * sizeof(int32_t), hipMemcpyHostToDevice,
+                            stream));
+    if (sorted && (st = dbuf(c->scratch, (size_t)grid * slot_words(job.n) * sizeof(int32_t),
+                             &d_scratch)) != DSES_OK)
         return st;
 
-    if ((st = c->yq.ensure(4 * m * sizeof(int32_t))) != DSES_OK) return st;
-    if ((st = c->yt.ensure(3 * m * sizeof(float))) != DSES_OK) return st;
-    if ((st = c->rec.ensure((size_t)job.k * sizeof(dses_record))) != DSES_OK) return st;
-    if ((st = c->res.ensure(sizeof(DevResult))) != DSES_OK) return st;
-    if ((st = c->status.ensure(64)) != DSES_OK) return st;
-    uint32_t *bad = static_cast<uint32_t *>(c->status.ptr);
+    if ((st = dbuf(c->yq, 4 * m * sizeof(int32_t), &d_yq)) != DSES_OK) return st;
+    if ((st = dbuf(c->yt, 3 * m * sizeof(float), &d_yt)) != DSES_OK) return st;
+    // with an arena the records go straight to the caller's buffer when it gives one
+    if (arena && records)
+        d_rec = records;
+    else if ((st = dbuf(c->rec, (size_t)job.k * sizeof(dses_record), &d_rec)) != DSES_OK)
+        return st;
+    if ((st = dbuf(c->res, sizeof(DevResult), &d_res)) != DSES_OK) return st;
+    if ((st = dbuf(c->status, 64, &d_status)) != DSES_OK) return st;
+    uint32_t *bad = static_cast<uint32_t *>(d_status);
 
     SweepArgs a{};
     a.src = job.src;
     a.rot = job.rot;
-    a.yq = static_cast<int32_t *>(c->yq.ptr);
-    a.yt = static_cast<float *>(c->yt.ptr);
-    a.rec = static_cast<dses_record *>(c->rec.ptr);
+    a.yq = static_cast<int32_t *>(d_yq);
+    a.yt = static_cast<float *>(d_yt);
+    a.rec = static_cast<dses_record *>(d_rec);
     a.k = job.k;
     a.g = g;
-    a.scratch = sorted ? static_cast<int32_t *>(c->scratch.ptr) : nullptr;
+    a.scratch = sorted ? static_cast<int32_t *>(d_scratch) : nullptr;
     a.scratch_stride = job.n;
     source_buckets(ylo, yhi, g.size[0], &a.sb_lo, &a.sb_shift, &a.sb_n);
     a.lane_group = o.lane_group;
@@ -619,18 +642,28 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
             HostGrid hg;
             if ((st = build_grid(ht, job.m, p.r, &hg)) != DSES_OK) return st;
             const size_t pb = hg.pts.size() * sizeof(float), sb = hg.start.size() * sizeof(int32_t);
-            if ((st = c->grid_pts.ensure(pb)) != DSES_OK) return st;
-            if ((st = c->grid_start.ensure(sb)) != DSES_OK) return st;
-            // through pinned staging: the copies stay asynchronous (the buffer is
-            // reused by the next call only after this call's final synchronisation)
-            if ((st = c->host_stage.ensure(pb + sb)) != DSES_OK) return st;
-            char *hs = static_cast<char *>(c->host_stage.ptr);
-            std::memcpy(hs, hg.pts.data(), pb);
-            std::memcpy(hs + pb, hg.start.data(), sb);
-            DSES_HIP(hipMemcpyAsync(c->grid_pts.ptr, hs, pb, hipMemcpyHostToDevice, stream));
-            DSES_HIP(hipMemcpyAsync(c->grid_start.ptr, hs + pb, sb, hipMemcpyHostToDevice, stream));
-            a.grid.pts = static_cast<float *>(c->grid_pts.ptr);
-            a.grid.start = static_cast<int32_t *>(c->grid_start.ptr);
+            void *d_pts = nullptr, *d_start = nullptr;
+            if ((st = dbuf(c->grid_pts, pb, &d_pts)) != DSES_OK) return st;
+            if ((st = dbuf(c->grid_start, sb, &d_start)) != DSES_OK) return st;
+            if (arena) {
+                // no pinned staging: the copies read the host vectors, which live
+                // until this call's final synchronisation
+                DSES_HIP(hipMemcpyAsync(d_pts, hg.pts.data(), pb, hipMemcpyHostToDevice, stream));
+                DSES_HIP(hipMemcpyAsync(d_start, hg.start.data(), sb, hipMemcpyHostToDevice,
+                                        stream));
+                DSES_HIP(hipStreamSynchronize(stream));
+            } else {
+                // through pinned staging: the copies stay asynchronous (the buffer is
+                // reused by the next call only after this call's final synchronisation)
+                if ((st = c->host_stage.ensure(pb + sb)) != DSES_OK) return st;
+                char *hs = static_cast<char *>(c->host_stage.ptr);
+                std::memcpy(hs, hg.pts.data(), pb);
+                std::memcpy(hs + pb, hg.start.data(), sb);
+                DSES_HIP(hipMemcpyAsync(d_pts, hs, pb, hipMemcpyHostToDevice, stream));
+                DSES_HIP(hipMemcpyAsync(d_start, hs + pb, sb, hipMemcpyHostToDevice, stream));
+            }
+            a.grid.pts = static_cast<float *>(d_pts);
+            a.grid.start = static_cast<int32_t *>(d_start);
             for (int q = 0; q < 3; ++q) { a.grid.lo[q] = hg.lo[q]; a.grid.dim[q] = hg.dim[q]; }
             a.grid.inv = hg.inv;
         }
@@ -656,9 +689,8 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
                      ref_coord_limit(p), bad};
         DSES_HIP(launch_check(ca, stream));
     }
-    DSES_HIP(launch_stage(job.tgt, static_cast<int32_t *>(c->perm.ptr), job.m, g.S16, g.S15,
-                          p.klo, static_cast<int32_t *>(c->yq.ptr),
-                          static_cast<float *>(c->yt.ptr), stream));
+    DSES_HIP(launch_stage(job.tgt, static_cast<int32_t *>(d_perm), job.m, g.S16, g.S15, p.klo,
+                          static_cast<int32_t *>(d_yq), static_cast<float *>(d_yt), stream));
     rec_ev(1);
     if (job.exhaustive) {
         DSES_HIP(launch_exhaustive(a, scorer, grid, stream));
@@ -671,11 +703,10 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
         DSES_HIP(launch_sweep(a, scorer, grid, stream));
     }
     rec_ev(2);
-    DSES_HIP(launch_select(a.rec, job.k, job.rot, p.delta, static_cast<DevResult *>(c->res.ptr),
-                           bad, stream));
+    DSES_HIP(launch_select(a.rec, job.k, job.rot, p.delta, static_cast<DevResult *>(d_res), bad,
+                           stream));
     rec_ev(3);
-    DSES_HIP(hipMemcpyAsync(c->host_res, c->res.ptr, sizeof(DevResult), hipMemcpyDeviceToHost,
-                            stream));
+    DSES_HIP(hipMemcpyAsync(c->host_res, d_res, sizeof(DevResult), hipMemcpyDeviceToHost, stream));
     DSES_HIP(hipStreamSynchronize(stream));
     const DevResult r = *c->host_res;
     if (timing) {
@@ -695,7 +726,7 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
         set_error("no rotation received a vote inside the translation box");
         return DSES_E_NOCANDIDATE;
     }
-    if (records) {
+    if (records && records != (void *)a.rec) {
         DSES_HIP(hipMemcpyAsync(records, a.rec, (size_t)job.k * sizeof(dses_record),
                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                 stream));

@@ -202,9 +202,25 @@ struct Job {
 // full current size) and copied; missing trailing fields stay 0 (defaults).
 dses_status copy_options(const dses_options *opt, dses_options *o);
 
+// Device memory handed out from a fixed region instead of allocated: takes of
+// 256-byte-aligned blocks from [base, base + cap); null when the region is spent.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    void *take(size_t bytes)
+    {
+        const size_t at = (used + 255) & ~size_t(255);
+        if (at > cap || bytes > cap - at) return nullptr;
+        used = at + bytes;
+        return base + at;
+    }
+};
+
 // Run one registration on `stream` using the context workspace (caller holds c->mu).
+// With an arena every device buffer of the call comes from it and nothing is
+// allocated (no timing events, no pinned staging, no top-k or pruning buffers).
 dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check_inputs,
-                      dses_result *out, const dses_options &o);
+                      dses_result *out, const dses_options &o, Arena *arena = nullptr);
 
 void add_stats(Context *c, double vote_ms, double score_ms, double select_ms, double stage_ms,
                int64_t launches, int64_t pairs_voted, int64_t pairs_scored, int64_t cands);

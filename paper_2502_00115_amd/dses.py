@@ -30,7 +30,7 @@ EXPORTED = [
     "dses_target_create", "dses_target_destroy", "dses_target_field", "dses_rotations_create",
     "dses_rotations_destroy", "dses_register_resident", "dses_register_batch",
     "dses_batch_last_config", "dses_measure_lds_atomics", "dses_rotations_euler",
-    "dses_register_exhaustive",
+    "dses_register_exhaustive", "dses_register_noalloc", "dses_noalloc_scratch_bytes",
     "dses_server_create", "dses_server_submit", "dses_server_wait", "dses_server_poll",
     "dses_server_timing", "dses_server_cancel", "dses_server_destroy",
 ]
@@ -133,6 +133,8 @@ def lib():
         L.dses_rotations_euler.argtypes = [vp, i32, f, vp]
         L.dses_register_exhaustive.argtypes = [vp, i64, vp, i64, vp, i64, f, i32,
                                                C.POINTER(Options), C.POINTER(Result)]
+        L.dses_register_noalloc.argtypes = [vp, i64, vp, i64, vp, i64, f, i32,
+                                            C.POINTER(Options), C.POINTER(Result)]
         L.dses_measure_lds_atomics.argtypes = [i32, C.POINTER(C.c_double),
                                                C.POINTER(C.c_double)]
         L.dses_register_batch.argtypes = [C.POINTER(Problem), i32, C.POINTER(BatchOpts),
@@ -149,8 +151,9 @@ def lib():
                                          C.POINTER(C.c_double)]
         L.dses_server_destroy.argtypes = [vp]
         for name in EXPORTED:
-            if name not in ("dses_last_error", "dses_version"):
+            if name not in ("dses_last_error", "dses_version", "dses_noalloc_scratch_bytes"):
                 getattr(L, name).restype = i32
+        L.dses_noalloc_scratch_bytes.restype = C.c_size_t
         _lib = L
     return _lib
 
@@ -317,6 +320,31 @@ def register(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=N
                                C.byref(o), C.byref(res)))
     return _result(res, _records_out(rbuf) if records else None,
                    _records_out(tbuf, CANDIDATE_DTYPE) if tbuf is not None else None)
+
+
+def register_noalloc(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=None,
+                     t_min=None, t_max=None, scorer="auto", records=False, lp=0.0,
+                     stream=None, lane_group=0) -> Registration:
+    """dses_register_noalloc: dses_register on device tensors with every device buffer
+    taken from the library's static scratch array (no allocation in the call; the
+    records buffer, when asked for, is allocated here by torch, outside the call)."""
+    args = _Args()
+    ps, n = args.ptr(src, 3)
+    pt, m = args.ptr(tgt, 3)
+    pr, k = args.ptr(rotations, 9)
+    if not args.device:
+        raise ValueError("register_noalloc takes device tensors")
+    rbuf, rptr = _records_buffer(args, k) if records else (None, None)
+    o = _options(args, delta_t, tau, t_min, t_max, scorer, False, stream, rptr, 0.0, lp,
+                 lane_group, "nearest")
+    res = Result()
+    _check(lib().dses_register_noalloc(ps, n, pt, m, pr, k, C.c_float(eps), METRICS[metric],
+                                       C.byref(o), C.byref(res)))
+    return _result(res, _records_out(rbuf) if records else None)
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().dses_noalloc_scratch_bytes())
 
 
 def register_exhaustive(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=None,

@@ -416,13 +416,13 @@ typedef struct {
     int32_t scorer;           /* dses_scorer for every request                         */
     float aging;              /* scheduling: a request's priority is its estimated
                                  remaining GPU time minus aging x its age (smallest
-                                 first); 0 -> 2.0 (on the serving workload: median
+                                 first); 0 -> 3.0 (on the serving workload: median
                                  and mean latency below one launch per request in
-                                 arrival order, p99 about 8% above), < 0 -> 0
-                                 (shortest remaining work first), very large ->
-                                 first come first served                           */
+                                 arrival order, p99 within 1%), < 0 -> 0 (shortest
+                                 remaining work first), very large -> first come
+                                 first served                                      */
     int32_t slice_mpairs;     /* work per slice (one batched launch), in millions of
-                                 rotated point pairs; 0 -> 12000                       */
+                                 rotated point pairs; 0 -> 48000                       */
 } dses_server_opts;
 
 dses_status dses_server_create(const dses_server_opts *opt, dses_server **out);

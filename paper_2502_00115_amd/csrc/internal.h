@@ -140,6 +140,8 @@ __host__ __device__ inline int64_t slot_words(int64_t cap)
 }
 
 // Batched registration.
+struct DevResult;
+
 struct BatchItem {
     int32_t inst;          // instance index
     int32_t k0, k1;        // rotation range [k0, k1)
@@ -152,7 +154,17 @@ struct BatchArgs {
     const int32_t *header;     // header[0] = items, header[1] = instances
     uint32_t *cursor;          // work-list cursor, cleared before each launch
     int32_t *scratch;          // if set: this launch's source-sort scratch (overrides
-                               // the instances' own, so concurrent launches never share)
+                               // the instances' own, so concurrent launches never share),
+    int64_t scratch_slot;      // slot_words() of each workgroup's part of it
+    // In-kernel completion (serving; unused when done_rot is null).  The cursor is
+    // then never cleared: a launch fetches exactly items + grid times, so the host
+    // passes the value it holds at launch.  done_rot counts each instance's swept
+    // rotations (zero at rest); the workgroup whose tile completes an instance
+    // selects its result into res, returns the count to zero and sets the flag.
+    uint32_t cursor_base;
+    uint32_t *done_rot;        // per instance (device memory)
+    DevResult *res;            // per instance (host memory mapped for the device)
+    uint32_t *done_flag;       // per instance, set to 1 after res (host memory)
 };
 
 struct StageDesc {
@@ -165,7 +177,6 @@ struct StageDesc {
     float *yt;
 };
 
-struct DevResult;
 struct SelectDesc {
     const dses_record *rec;
     int32_t k;

@@ -1696,26 +1696,64 @@ hipError_t launch_topk(const dses_record *rec, int32_t K, int32_t k, float delta
 // Each rotation runs the same sweep_one() as the single-registration kernel, so
 // a registration's records do not depend on what it is batched with.
 // --------------------------------------------------------------------------
+// In-kernel completion of a batched instance (serving): after its tile the
+// workgroup adds the tile's rotations to the instance's count; the one that
+// brings it to K selects the result exactly as k_select does, returns the count
+// to zero for the slot's next instance and raises the flag the host polls.
+// Records are written by thread 0 only (sweep_one), so its release fence before
+// the count covers the tile.
+__device__ void finish_item(const BatchArgs &b, const BatchItem &w, const SweepArgs &a,
+                            uint32_t *lds)
+{
+    uint32_t *last = lds + kLdsWords - 2;
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t cnt = (uint32_t)(w.k1 - w.k0);
+        const uint32_t prev = atomicAdd(b.done_rot + w.inst, cnt);
+        const bool done = prev + cnt == (uint32_t)a.k;
+        if (done) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the others' records
+        *last = done ? 1u : 0u;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane((int)*last) == 0) return;
+    // selection scratch in the (now unused) vote array
+    float *se = reinterpret_cast<float *>(lds);
+    int *si = reinterpret_cast<int *>(lds + 16), *sk = si + 16, *sv = si + 32;
+    select_body(a.rec, a.k, a.rot, a.g.delta, b.res + w.inst, nullptr, se, si, sk, sv);
+    if (threadIdx.x == 0) {
+        atomicExch(b.done_rot + w.inst, 0u);
+        __threadfence_system();                   // the result before the flag
+        __hip_atomic_store(b.done_flag + w.inst, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __syncthreads();
+}
+
 template <int SCORER>
 __global__ void __launch_bounds__(kBlock) k_sweep_batch(BatchArgs b)
 {
     __shared__ __align__(16) uint32_t lds[kLdsWords];
     const int n_items = __builtin_amdgcn_readfirstlane(*(kint)(const int32_t *)b.header);
     for (;;) {
-        if (threadIdx.x == 0) lds[kLdsWords - 1] = atomicAdd(b.cursor, 1u);
+        if (threadIdx.x == 0) lds[kLdsWords - 1] = atomicAdd(b.cursor, 1u) - b.cursor_base;
         __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane((int)lds[kLdsWords - 1]);
+        const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)lds[kLdsWords - 1]);
         __syncthreads();
-        if (it >= n_items) break;
+        if (it >= (uint32_t)n_items) break;
         const BatchItem w = kload(b.items + it);
         SweepArgs a = kload(b.inst + w.inst);
-        if (b.scratch && a.scratch) a.scratch = b.scratch;
+        int slot = blockIdx.x;
+        if (b.scratch && a.scratch) {
+            // this launch's slot; the instance's own stride lays out the arrays in it
+            a.scratch = b.scratch + (size_t)blockIdx.x * (size_t)b.scratch_slot;
+            slot = 0;
+        }
         for (int k = w.k0; k < w.k1; ++k) {
             if (a.g.counter_bits == 16)
-                sweep_one<16, SCORER>(a, k, lds, blockIdx.x);
+                sweep_one<16, SCORER>(a, k, lds, slot);
             else
-                sweep_one<32, SCORER>(a, k, lds, blockIdx.x);
+                sweep_one<32, SCORER>(a, k, lds, slot);
         }
+        if (b.done_rot) finish_item(b, w, a, lds);
     }
 }
 

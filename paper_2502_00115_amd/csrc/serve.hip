@@ -13,8 +13,9 @@
 //    (estimated remaining GPU time minus `aging` x time since submission), so
 //    requests that arrive while others run join the next slice and their
 //    rotations overlap on the device with the older requests';
-//  * a request whose last tile is in a slice is selected at the end of that
-//    slice; its result is copied back and its memory returned to the pool.
+//  * a request completes inside the sweep: the workgroup whose tile finishes
+//    its last rotations selects its result into host memory and raises a flag
+//    the scheduler polls; its memory then returns to the pool.
 // Each rotation runs the same sweep_one() as a lone registration, so a request's
 // result does not depend on what it was served with.
 #include <hip/hip_runtime.h>
@@ -99,6 +100,8 @@ struct Request {
     // device residency
     size_t off = 0, bytes = 0;
     int slot = -1;
+    bool ready = false;                      // its uploads are complete
+    bool copying = false;                    // top-k / record copies enqueued on `down`
     int32_t next_k = 0;                      // rotations handed to slices so far
     double pair_cost = 0.0;                  // n * m per rotation
     dses_record *d_rec = nullptr;            // records inside the request's pool range
@@ -111,17 +114,19 @@ struct Request {
 };
 
 struct SliceSet {
-    BatchItem *h_items = nullptr;            // pinned
-    SelectDesc *h_sel = nullptr;             // pinned
-    int32_t *h_header = nullptr;             // pinned
-    void *d_items = nullptr, *d_sel = nullptr, *d_header = nullptr, *d_cursor = nullptr;
+    BatchItem *h_items = nullptr;            // host memory the slice's kernel reads in place
+    int32_t *h_header = nullptr;             // host memory: items in the slice
+    const BatchItem *dv_items = nullptr;     // their device addresses
+    const int32_t *dv_header = nullptr;
+    uint32_t *d_cursor = nullptr;            // work-list cursor, never cleared
+    uint32_t cursor = 0;                     // its value when the next launch starts
     int32_t *d_scratch = nullptr;            // source-sort scratch of this slice's launch
-    hipEvent_t done = nullptr;
+    hipEvent_t swept = nullptr;              // the slice's sweep is complete
     hipStream_t stream = nullptr;            // stream the slice ran on
     bool busy = false;
     double pairs = 0.0;
+    int n_last = 0;                          // requests whose last tile is in the slice
     Clock::time_point t_launch;
-    std::vector<Request *> finishing;
     std::vector<uint64_t> carried;           // ids of the requests with tiles in the slice (trace)
 };
 
@@ -130,21 +135,29 @@ struct SliceSet {
 struct ServerImpl {
     Context *c = nullptr;
     dses_server_opts opt{};
+    // Streams.  A sweep workgroup holds a whole CU (all of its LDS and registers),
+    // so any other kernel -- the runtime's copy kernels included -- waits for a
+    // sweep workgroup to finish.  Nothing a slice needs is therefore ordered
+    // behind such a kernel: a request joins slices only once its uploads are seen
+    // complete, and top-k passes and copies to caller buffers are polled.
     hipStream_t up = nullptr;                // admission uploads and staging
-    hipStream_t down = nullptr;              // result copies of finished requests
+    hipStream_t down = nullptr;              // top-k passes and copies to caller buffers
     hipEvent_t up_done = nullptr;            // recorded after every admission's uploads
+    std::vector<Request *> uploading;        // admitted, uploads not yet seen complete
     hipStream_t stream = nullptr;            // even slices
     hipStream_t stream2 = nullptr;           // odd slices
-    hipEvent_t last_slice = nullptr;         // the most recently launched slice
-    bool have_last = false;
     uint64_t n_slices = 0;
     double rate = 5.0e11;                    // estimated sweep rate, pairs per second
     void *pool_mem = nullptr;
     Pool pool;
     int max_slots = 0;
     SweepArgs *d_args = nullptr;             // one per slot
-    DevResult *d_res = nullptr, *h_res = nullptr;
-    uint32_t *d_status = nullptr;
+    uint32_t *d_done = nullptr;              // per slot: rotations swept (kernel-owned)
+    DevResult *h_res = nullptr;              // per slot, host memory written by the kernel
+    uint32_t *h_flag = nullptr;              // per slot, raised by the kernel after h_res
+    DevResult *dv_res = nullptr;             // device addresses of h_res and h_flag
+    uint32_t *dv_flag = nullptr;
+    std::vector<hipEvent_t> slot_event;      // per slot: end of a request's copies
     float *h_stage = nullptr;                // pinned per-slot source staging
     SliceSet sets[kSliceSets];
     int grid = 0;
@@ -171,6 +184,7 @@ struct ServerImpl {
     bool admit_locked();
     bool launch_slice();
     void poll_slices();
+    bool finish(Request *r);
     size_t need_bytes(const Request &r) const;
     dses_status prepare(Request *r);
     ~ServerImpl();
@@ -191,21 +205,21 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     opt = o;
     if (opt.memory_budget <= 0) opt.memory_budget = (int64_t)1 << 30;
     if (opt.max_inflight <= 0) opt.max_inflight = 64;
-    if (opt.aging == 0.0f) opt.aging = 2.0f;
+    if (opt.aging == 0.0f) opt.aging = 3.0f;
     if (opt.aging < 0.0f) opt.aging = 0.0f;
     max_slots = opt.max_inflight;
-    grid = std::max(1, c->n_cu);
-    slice_pairs = 1.0e6 * (opt.slice_mpairs > 0 ? opt.slice_mpairs : 12000);
-    DSES_HIP(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
-    DSES_HIP(hipStreamCreateWithFlags(&down, hipStreamNonBlocking));
+    slice_pairs = 1.0e6 * (opt.slice_mpairs > 0 ? opt.slice_mpairs : 48000);
     // The slice streams must sit on two different hardware queues: kernels of one
     // queue never overlap, and streams created the ordinary way share a small
     // pool of queues (two of them can land on the same one).  A stream created
     // with a CU mask gets a queue of its own; the mask here covers every CU.
-    std::vector<uint32_t> cu_mask((size_t)(grid + 31) / 32, 0xffffffffu);
-    if (grid % 32) cu_mask.back() = (1u << (grid % 32)) - 1u;
-    DSES_HIP(hipExtStreamCreateWithCUMask(&stream, (uint32_t)cu_mask.size(), cu_mask.data()));
-    DSES_HIP(hipExtStreamCreateWithCUMask(&stream2, (uint32_t)cu_mask.size(), cu_mask.data()));
+    grid = std::max(1, c->n_cu);
+    std::vector<uint32_t> slice_mask((size_t)(grid + 31) / 32, 0u);
+    for (int cu = 0; cu < grid; ++cu) slice_mask[(size_t)cu / 32] |= 1u << (cu % 32);
+    DSES_HIP(hipExtStreamCreateWithCUMask(&stream, (uint32_t)slice_mask.size(), slice_mask.data()));
+    DSES_HIP(hipExtStreamCreateWithCUMask(&stream2, (uint32_t)slice_mask.size(), slice_mask.data()));
+    DSES_HIP(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
+    DSES_HIP(hipStreamCreateWithFlags(&down, hipStreamNonBlocking));
     DSES_HIP(hipEventCreateWithFlags(&up_done, hipEventDisableTiming));
     DSES_HIP(hipEventRecord(up_done, up));
     if (hipMalloc(&pool_mem, (size_t)opt.memory_budget) != hipSuccess) {
@@ -215,28 +229,41 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     }
     pool.init((size_t)opt.memory_budget);
     DSES_HIP(hipMalloc(&d_args, max_slots * sizeof(SweepArgs)));
-    DSES_HIP(hipMalloc(&d_res, max_slots * sizeof(DevResult)));
-    DSES_HIP(hipMalloc(&d_status, max_slots * sizeof(uint32_t)));
-    DSES_HIP(hipMemset(d_status, 0, max_slots * sizeof(uint32_t)));
+    DSES_HIP(hipMalloc(&d_done, max_slots * sizeof(uint32_t)));
+    DSES_HIP(hipMemset(d_done, 0, max_slots * sizeof(uint32_t)));
+    // host memory the kernels read or write in place: coherent (not cached by
+    // the device), mapped into the device's address space
     void *p = nullptr;
-    DSES_HIP(hipHostMalloc(&p, max_slots * sizeof(DevResult), hipHostMallocDefault));
+    auto host_mapped = [&](size_t bytes, void **h, void **dv) {
+        DSES_HIP(hipHostMalloc(h, bytes, hipHostMallocCoherent | hipHostMallocMapped));
+        std::memset(*h, 0, bytes);
+        DSES_HIP(hipHostGetDevicePointer(dv, *h, 0));
+        return DSES_OK;
+    };
+    void *dv = nullptr;
+    if (host_mapped(max_slots * sizeof(DevResult), &p, &dv) != DSES_OK) return DSES_E_DEVICE;
     h_res = static_cast<DevResult *>(p);
+    dv_res = static_cast<DevResult *>(dv);
+    if (host_mapped(max_slots * sizeof(uint32_t), &p, &dv) != DSES_OK) return DSES_E_DEVICE;
+    h_flag = static_cast<uint32_t *>(p);
+    dv_flag = static_cast<uint32_t *>(dv);
     DSES_HIP(hipHostMalloc(&p, (size_t)max_slots * kSlotStageBytes, hipHostMallocDefault));
     h_stage = static_cast<float *>(p);
     for (auto &s : sets) {
-        DSES_HIP(hipHostMalloc(&p, kMaxSliceItems * sizeof(BatchItem), hipHostMallocDefault));
+        if (host_mapped(kMaxSliceItems * sizeof(BatchItem), &p, &dv) != DSES_OK) return DSES_E_DEVICE;
         s.h_items = static_cast<BatchItem *>(p);
-        DSES_HIP(hipHostMalloc(&p, max_slots * sizeof(SelectDesc), hipHostMallocDefault));
-        s.h_sel = static_cast<SelectDesc *>(p);
-        DSES_HIP(hipHostMalloc(&p, 64, hipHostMallocDefault));
+        s.dv_items = static_cast<const BatchItem *>(dv);
+        if (host_mapped(64, &p, &dv) != DSES_OK) return DSES_E_DEVICE;
         s.h_header = static_cast<int32_t *>(p);
-        DSES_HIP(hipMalloc(&s.d_items, kMaxSliceItems * sizeof(BatchItem)));
-        DSES_HIP(hipMalloc(&s.d_sel, max_slots * sizeof(SelectDesc)));
-        DSES_HIP(hipMalloc(&s.d_header, 64));
+        s.dv_header = static_cast<const int32_t *>(dv);
         DSES_HIP(hipMalloc(&s.d_cursor, 64));
+        DSES_HIP(hipMemset(s.d_cursor, 0, 64));
         DSES_HIP(hipMalloc(&s.d_scratch, (size_t)grid * slot_words(kServeMaxSrc) * sizeof(int32_t)));
-        DSES_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+        DSES_HIP(hipEventCreateWithFlags(&s.swept, hipEventDisableTiming));
     }
+    DSES_HIP(hipDeviceSynchronize());
+    slot_event.assign(max_slots, nullptr);
+    for (auto &e : slot_event) DSES_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (int i = max_slots - 1; i >= 0; --i) free_slots.push_back(i);
     if (const char *tp = std::getenv("DSES_SERVE_TRACE")) trace = std::fopen(tp, "w");
     t0 = Clock::now();
@@ -260,19 +287,17 @@ ServerImpl::~ServerImpl()
     for (auto &s : sets) {
         if (s.d_scratch) (void)hipFree(s.d_scratch);
         if (s.h_items) (void)hipHostFree(s.h_items);
-        if (s.h_sel) (void)hipHostFree(s.h_sel);
         if (s.h_header) (void)hipHostFree(s.h_header);
-        if (s.d_items) (void)hipFree(s.d_items);
-        if (s.d_sel) (void)hipFree(s.d_sel);
-        if (s.d_header) (void)hipFree(s.d_header);
         if (s.d_cursor) (void)hipFree(s.d_cursor);
-        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.swept) (void)hipEventDestroy(s.swept);
     }
+    for (auto e : slot_event)
+        if (e) (void)hipEventDestroy(e);
     if (h_res) (void)hipHostFree(h_res);
+    if (h_flag) (void)hipHostFree(h_flag);
     if (h_stage) (void)hipHostFree(h_stage);
     if (d_args) (void)hipFree(d_args);
-    if (d_res) (void)hipFree(d_res);
-    if (d_status) (void)hipFree(d_status);
+    if (d_done) (void)hipFree(d_done);
     if (pool_mem) (void)hipFree(pool_mem);
     if (up) (void)hipStreamDestroy(up);
     if (down) (void)hipStreamDestroy(down);
@@ -285,8 +310,8 @@ ServerImpl::~ServerImpl()
 // Device preparation of an admitted request (scheduler thread; the request owns
 // its pool range and slot): the reference is staged once per target and pitch
 // (cached), so a request only uploads its source and its sweep arguments, both
-// from the slot's pinned staging area, asynchronously on the server stream ahead
-// of any slice that carries the request's tiles.
+// from the slot's pinned staging area, asynchronously on the upload stream; its
+// tiles join slices once those uploads are seen complete.
 dses_status ServerImpl::prepare(Request *r)
 {
     auto *tm = const_cast<TargetRes *>(r->target);
@@ -320,7 +345,7 @@ dses_status ServerImpl::prepare(Request *r)
     a.yt = stg->yt;
     const bool sorted = r->n <= kSortMax && stg->sorted;
     a.scratch = sorted ? reinterpret_cast<int32_t *>(4) : nullptr;   // per-slice scratch at launch
-    a.scratch_stride = kServeMaxSrc;
+    a.scratch_stride = r->n;                 // arrays inside the slice's fixed-size slots
     source_buckets(stg->ylo, stg->yhi, g.size[0], &a.sb_lo, &a.sb_shift, &a.sb_n);
     a.ref_x_extent = ref_x_extent(stg->ylo, stg->yhi);
     a.g = g;
@@ -353,6 +378,7 @@ bool ServerImpl::admit_locked()
         r->slot = free_slots.back();
         free_slots.pop_back();
         r->t_admit = Clock::now();
+        __atomic_store_n(h_flag + r->slot, 0u, __ATOMIC_RELEASE);
         mu.unlock();
         dses_status st = prepare(r);
         mu.lock();
@@ -367,6 +393,7 @@ bool ServerImpl::admit_locked()
         }
         r->state = Request::ADMITTED;
         active.push_back(r);
+        uploading.push_back(r);
         any = true;
     }
     return any;
@@ -381,7 +408,7 @@ bool ServerImpl::launch_slice()
     if (!s) return false;
     std::vector<Request *> order;
     for (Request *r : active)
-        if (r->next_k < r->k) order.push_back(r);
+        if (r->ready && r->next_k < r->k) order.push_back(r);
     if (order.empty()) return false;
     const auto now = Clock::now();
     const double aging = opt.aging;
@@ -393,9 +420,9 @@ bool ServerImpl::launch_slice()
     std::stable_sort(order.begin(), order.end(),
                      [&](const Request *a, const Request *b) { return prio(a) < prio(b); });
     const int scorer = order.front()->scorer;      // one kernel instantiation per slice
-    int n_items = 0, n_sel = 0;
+    int n_items = 0;
     double budget = slice_pairs;
-    s->finishing.clear();
+    s->n_last = 0;
     s->carried.clear();
     for (Request *r : order) {
         if (budget <= 0.0 || n_items >= kMaxSliceItems) break;
@@ -411,49 +438,24 @@ bool ServerImpl::launch_slice()
             r->next_k = k1;
             budget -= (k1 - k0) * r->pair_cost;
         }
-        if (r->next_k == r->k) {
-            const int slot = r->slot;
-            s->h_sel[n_sel++] = SelectDesc{r->d_rec, r->k, r->p.delta, r->rots->rot,
-                                           d_res + slot, d_status + slot};
-            s->finishing.push_back(r);
-        }
+        if (r->next_k == r->k) ++s->n_last;
     }
     s->h_header[0] = n_items;
-    s->h_header[1] = n_sel;
+    s->h_header[1] = 0;
     s->pairs = slice_pairs - budget;
     s->t_launch = Clock::now();
     mu.unlock();
     bool ok = true;
     auto chk = [&](hipError_t e) { if (e != hipSuccess) { ok = false; fatal = hipGetErrorString(e); } };
     // slices alternate between two streams so one slice's tail overlaps the next;
-    // each first waits for the admission uploads issued so far (on `up`)
+    // the kernel reads the work list from host memory, so a launch is the only
+    // device work a slice enqueues
     hipStream_t st = (n_slices & 1) ? stream2 : stream;
-    chk(hipStreamWaitEvent(st, up_done, 0));
-    chk(hipMemcpyAsync(s->d_items, s->h_items, n_items * sizeof(BatchItem), hipMemcpyHostToDevice, st));
-    chk(hipMemcpyAsync(s->d_sel, s->h_sel, std::max(1, n_sel) * sizeof(SelectDesc), hipMemcpyHostToDevice, st));
-    chk(hipMemcpyAsync(s->d_header, s->h_header, 8, hipMemcpyHostToDevice, st));
-    chk(launch_clear(static_cast<uint32_t *>(s->d_cursor), 1, st));
-    BatchArgs ba{d_args, static_cast<BatchItem *>(s->d_items),
-                 static_cast<int32_t *>(s->d_header), static_cast<uint32_t *>(s->d_cursor),
-                 s->d_scratch};
+    BatchArgs ba{d_args, s->dv_items, s->dv_header, s->d_cursor, s->d_scratch,
+                 slot_words(kServeMaxSrc), s->cursor, d_done, dv_res, dv_flag};
     chk(launch_sweep_batch(ba, scorer, grid, st));
-    if (n_sel > 0) {
-        // a finishing request's earlier tiles may sit in the previous slice on the
-        // other stream: select only after that slice is complete too
-        if (have_last) chk(hipStreamWaitEvent(st, last_slice, 0));
-        chk(launch_batch_aux(nullptr, static_cast<SelectDesc *>(s->d_sel),
-                             static_cast<int32_t *>(s->d_header), n_sel, 1, st));
-        for (Request *r : s->finishing) {
-            if (r->top_k > 0)
-                chk(launch_topk(r->d_rec, r->k, r->top_k, r->p.delta, r->d_topk_a, r->d_topk_b,
-                                r->d_topk, st));
-            chk(hipMemcpyAsync(h_res + r->slot, d_res + r->slot, sizeof(DevResult),
-                               hipMemcpyDeviceToHost, st));
-        }
-    }
-    chk(hipEventRecord(s->done, st));
-    last_slice = s->done;
-    have_last = true;
+    chk(hipEventRecord(s->swept, st));
+    s->cursor += (uint32_t)(n_items + grid);   // every workgroup fetches once past the end
     ++n_slices;
     mu.lock();
     s->stream = st;
@@ -461,67 +463,104 @@ bool ServerImpl::launch_slice()
     return ok;
 }
 
+// A request whose result the kernel has published (scheduler thread, mu held).
+// Top-k passes and copies to the caller's buffers are enqueued on `down` and
+// polled (they may wait for a sweep workgroup to free a CU); returns true once
+// the request is complete, its memory and slot returned.
+bool ServerImpl::finish(Request *r)
+{
+    const DevResult &d = h_res[r->slot];
+    if (!r->copying && (r->host_rec || (r->top_k > 0 && d.rot_index >= 0))) {
+        bool ok = true;
+        auto chk = [&](hipError_t e) { if (e != hipSuccess) ok = false; };
+        if (r->top_k > 0 && d.rot_index >= 0) {
+            chk(launch_topk(r->d_rec, r->k, r->top_k, r->p.delta, r->d_topk_a, r->d_topk_b,
+                            r->d_topk, down));
+            chk(hipMemcpyAsync(r->host_topk, r->d_topk, sizeof(dses_candidate) * r->top_k,
+                               hipMemcpyDeviceToHost, down));
+        }
+        if (r->host_rec)
+            chk(hipMemcpyAsync(r->host_rec, r->d_rec, sizeof(dses_record) * r->k,
+                               hipMemcpyDeviceToHost, down));
+        chk(hipEventRecord(slot_event[r->slot], down));
+        r->copying = true;
+        if (!ok) {
+            (void)hipGetLastError();
+            fatal = "enqueueing the copies of a finished request failed";
+            return false;
+        }
+    }
+    if (r->copying) {
+        const hipError_t e = hipEventQuery(slot_event[r->slot]);
+        if (e == hipErrorNotReady) return false;
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fatal = hipGetErrorString(e);
+            return false;
+        }
+    }
+    if (d.rot_index < 0) {
+        r->status = DSES_E_NOCANDIDATE;
+    } else {
+        std::memcpy(r->out.R, d.R, sizeof(r->out.R));
+        std::memcpy(r->out.t, d.t, sizeof(r->out.t));
+        r->out.rot_index = d.rot_index;
+        r->out.inliers = d.inliers;
+        r->out.error = d.error;
+        r->out.votes = d.votes;
+        r->out.n_valid = d.n_valid;
+    }
+    r->state = Request::DONE;
+    r->t_done = Clock::now();
+    if (trace)
+        std::fprintf(trace, "R %llu %d %d %d %.6f %.6f %.6f\n", (unsigned long long)r->id, r->n,
+                     r->m, r->k, since(r->t_submit), since(r->t_admit), since(r->t_done));
+    pool.release(r->off, r->bytes);
+    free_slots.push_back(r->slot);
+    r->src.clear();
+    r->src.shrink_to_fit();
+    return true;
+}
+
 void ServerImpl::poll_slices()
 {
-    // slices complete in stream order; finish requests of completed ones
-    for (auto &s : sets) {
-        if (!s.busy) continue;
-        if (hipEventQuery(s.done) != hipSuccess) continue;
-        for (Request *r : s.finishing) {
-            const DevResult &d = h_res[r->slot];
-            // the caller's record and top-k buffers: copied from the request's pool
-            // range before that range is returned (the slice is complete)
-            bool copied = true;
-            if (r->host_rec && !d.bad_input)
-                copied = hipMemcpyAsync(r->host_rec, r->d_rec, sizeof(dses_record) * r->k,
-                                        hipMemcpyDeviceToHost, down) == hipSuccess;
-            if (copied && r->top_k > 0 && !d.bad_input && d.rot_index >= 0)
-                copied = hipMemcpyAsync(r->host_topk, r->d_topk,
-                                        sizeof(dses_candidate) * r->top_k,
-                                        hipMemcpyDeviceToHost, down) == hipSuccess;
-            if (copied) copied = hipStreamSynchronize(down) == hipSuccess;
-            if (!copied) {
-                (void)hipGetLastError();
-                r->status = DSES_E_DEVICE;
-            } else if (d.bad_input) {
-                r->status = DSES_E_INVAL;
-            } else if (d.rot_index < 0) {
-                r->status = DSES_E_NOCANDIDATE;
-            } else {
-                std::memcpy(r->out.R, d.R, sizeof(r->out.R));
-                std::memcpy(r->out.t, d.t, sizeof(r->out.t));
-                r->out.rot_index = d.rot_index;
-                r->out.inliers = d.inliers;
-                r->out.error = d.error;
-                r->out.votes = d.votes;
-                r->out.n_valid = d.n_valid;
-            }
-            r->state = Request::DONE;
-            r->t_done = Clock::now();
-            if (trace)
-                std::fprintf(trace, "R %llu %d %d %d %.6f %.6f %.6f\n",
-                             (unsigned long long)r->id, r->n, r->m, r->k, since(r->t_submit),
-                             since(r->t_admit), since(r->t_done));
-            pool.release(r->off, r->bytes);
-            free_slots.push_back(r->slot);
-            active.erase(std::remove(active.begin(), active.end(), r), active.end());
-            r->src.clear();
-            r->src.shrink_to_fit();
+    // admission uploads: one event, recorded after each admission's, covers all
+    if (!uploading.empty() && hipEventQuery(up_done) == hipSuccess) {
+        for (Request *r : uploading) r->ready = true;
+        uploading.clear();
+    }
+    // requests with every tile handed out whose result flag is up
+    bool any = false;
+    for (size_t i = 0; i < active.size();) {
+        Request *r = active[i];
+        if (r->next_k < r->k || __atomic_load_n(h_flag + r->slot, __ATOMIC_ACQUIRE) == 0u) {
+            ++i;
+            continue;
         }
+        if (!finish(r)) {
+            ++i;
+            continue;
+        }
+        active.erase(active.begin() + (long)i);
+        any = true;
+    }
+    // slices whose sweep is complete free their work-list buffers
+    for (auto &s : sets) {
+        if (!s.busy || hipEventQuery(s.swept) != hipSuccess) continue;
         const auto now = Clock::now();
         if (trace) {
-            std::fprintf(trace, "S %d %.6f %.6f %.0f %zu", s.stream == stream2 ? 1 : 0,
-                         since(s.t_launch), since(now), s.pairs, s.finishing.size());
+            std::fprintf(trace, "S %d %.6f %.6f %.0f %d", s.stream == stream2 ? 1 : 0,
+                         since(s.t_launch), since(now), s.pairs, s.n_last);
             for (uint64_t id : s.carried) std::fprintf(trace, " %llu", (unsigned long long)id);
             std::fprintf(trace, "\n");
         }
         const double dt = std::chrono::duration<double>(now - s.t_launch).count();
         if (dt > 1e-4 && s.pairs > 0.0)
             rate = 0.8 * rate + 0.2 * std::min(4.0e12, std::max(1.0e10, s.pairs / dt));
-        s.finishing.clear();
         s.busy = false;
-        cv_done.notify_all();
+        any = true;
     }
+    if (any) cv_done.notify_all();
 }
 
 void ServerImpl::run()
@@ -544,6 +583,7 @@ void ServerImpl::run()
                 }
             queue.clear();
             active.clear();
+            uploading.clear();
             cv_done.notify_all();
             if (stop) break;
             cv_work.wait_for(lk, std::chrono::milliseconds(50));
@@ -553,7 +593,7 @@ void ServerImpl::run()
         for (auto &s : sets) busy += s.busy ? 1 : 0;
         if (stop && queue.empty() && active.empty() && busy == 0) break;
         if (!launched) {
-            if (busy > 0)
+            if (busy > 0 || !uploading.empty() || !active.empty())
                 cv_work.wait_for(lk, std::chrono::microseconds(100));
             else
                 cv_work.wait_for(lk, std::chrono::milliseconds(20));

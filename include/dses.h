@@ -225,6 +225,14 @@ const char *dses_version(void);
 /* Read (and with reset != 0 clear) the DSES_TIMING kernel statistics. */
 dses_status dses_kernel_stats(dses_kstats *out, int32_t reset);
 
+/* Fault injection, for tests of the error paths: of the library's next device
+ * and pinned-host allocations (every one it makes, in any thread), the first
+ * `skip` succeed and the `count` after them fail as if out of memory (the entry
+ * point that made the allocation reports DSES_E_NOMEM or DSES_E_DEVICE and
+ * leaves every object it was given usable).  (0, 0) turns injection off.
+ * Negative arguments: DSES_E_INVAL.  Process-wide; not for production use. */
+dses_status dses_debug_fail_allocs(int32_t skip, int32_t count);
+
 /* ---------------------------------------------------------------------------- */
 /* Plain registration (Alg. 2 with q = 0)                                        */
 /* ---------------------------------------------------------------------------- */

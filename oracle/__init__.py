@@ -51,7 +51,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        path = build_oracle(force=False)
+        # DSES_ORACLE_LIB: a prebuilt variant of this library (the sanitizer test's)
+        path = os.environ.get("DSES_ORACLE_LIB") or build_oracle(force=False)
         L = C.CDLL(path)
         fp, dp, ip, up = (C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                           C.POINTER(C.c_uint32))

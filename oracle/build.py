@@ -7,14 +7,21 @@ SRC = os.path.join(HERE, "dses_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build_oracle(force: bool = True) -> str:
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
+# AddressSanitizer + UndefinedBehaviorSanitizer build (tests only): any report aborts
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all"]
+
+
+def build_oracle(force: bool = True, out: str = None, sanitize: bool = False) -> str:
+    lib = out or LIB
+    if not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(SRC):
+        return lib
+    tmp = lib + ".tmp"
+    opt = SANITIZE_FLAGS if sanitize else ["-O2"]
+    subprocess.check_call(["gcc", *opt, "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
                            "-fPIC", "-shared", "-pthread", SRC, "-o", tmp, "-lm"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

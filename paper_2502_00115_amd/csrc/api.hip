@@ -19,13 +19,49 @@ static thread_local std::string g_err;
 
 void set_error(const std::string &msg) { g_err = msg; }
 
+namespace {
+std::mutex g_fault_mu;
+int64_t g_fault_skip = 0, g_fault_count = 0;   // dses_debug_fail_allocs
+
+// true if this allocation is one the injection makes fail
+bool injected_failure()
+{
+    std::lock_guard<std::mutex> lk(g_fault_mu);
+    if (g_fault_count <= 0) return false;
+    if (g_fault_skip > 0) {
+        --g_fault_skip;
+        return false;
+    }
+    --g_fault_count;
+    return true;
+}
+}  // namespace
+
+hipError_t dev_alloc_raw(void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (injected_failure()) return hipErrorOutOfMemory;
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) *p = nullptr;
+    return e;
+}
+
+hipError_t host_alloc_raw(void **p, size_t bytes, unsigned int flags)
+{
+    *p = nullptr;
+    if (injected_failure()) return hipErrorOutOfMemory;
+    const hipError_t e = hipHostMalloc(p, bytes, flags);
+    if (e != hipSuccess) *p = nullptr;
+    return e;
+}
+
 dses_status DevBuf::ensure(size_t want)
 {
     if (want <= bytes && ptr) return DSES_OK;
     release();
     size_t b = std::max<size_t>(want, 256);
     b = (b + 4095) & ~size_t(4095);
-    if (hipMalloc(&ptr, b) != hipSuccess) {
+    if (dev_alloc(&ptr, b) != hipSuccess) {
         ptr = nullptr;
         bytes = 0;
         (void)hipGetLastError();
@@ -48,7 +84,7 @@ dses_status PinnedBuf::ensure(size_t want)
     if (want <= bytes && ptr) return DSES_OK;
     release();
     const size_t b = (std::max<size_t>(want, 4096) + 4095) & ~size_t(4095);
-    if (hipHostMalloc(&ptr, b, hipHostMallocDefault) != hipSuccess) {
+    if (host_alloc(&ptr, b, hipHostMallocDefault) != hipSuccess) {
         ptr = nullptr;
         bytes = 0;
         (void)hipGetLastError();
@@ -105,9 +141,14 @@ static dses_status init_device(int device)
     int lds = 0;
     DSES_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
     c->lds_max = std::min(lds, 160 * 1024);
-    DSES_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     void *hr = nullptr;
-    DSES_HIP(hipHostMalloc(&hr, sizeof(DevResult), hipHostMallocDefault));
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = host_alloc(&hr, sizeof(DevResult), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        if (c->stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        DSES_HIP(e);
+    }
     c->host_res = static_cast<DevResult *>(hr);
     g_ctx = c;
     return DSES_OK;
@@ -768,6 +809,18 @@ const char *dses_last_error(void) { return g_err.c_str(); }
 const char *dses_version(void) { return "dses-mi355x 0.1"; }
 
 dses_status dses_init(int32_t device) { return init_device(device); }
+
+dses_status dses_debug_fail_allocs(int32_t skip, int32_t count)
+{
+    if (skip < 0 || count < 0) {
+        set_error("dses_debug_fail_allocs: negative argument");
+        return DSES_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_fault_mu);
+    g_fault_skip = count > 0 ? skip : 0;
+    g_fault_count = count;
+    return DSES_OK;
+}
 
 dses_status dses_kernel_stats(dses_kstats *out, int32_t reset)
 {

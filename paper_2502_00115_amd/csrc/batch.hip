@@ -105,6 +105,9 @@ static dses_status ensure_capacity(BatchState *b, int count, int n_items, size_t
     bool grew = false;
     if (count > b->cap_count) {
         const int cap = std::max(count, 64);
+        // until every buffer below is in place the capacity reads 0, so a failed
+        // allocation (which releases the old buffer) is retried by the next call
+        b->cap_count = 0;
         if ((st = b->inst.ensure(cap * sizeof(SweepArgs))) != DSES_OK) return st;
         if ((st = b->stage.ensure(cap * sizeof(StageDesc))) != DSES_OK) return st;
         if ((st = b->sel.ensure(cap * sizeof(SelectDesc))) != DSES_OK) return st;
@@ -113,19 +116,21 @@ static dses_status ensure_capacity(BatchState *b, int count, int n_items, size_t
         if (b->host_res) (void)hipHostFree(b->host_res);
         b->host_res = nullptr;
         void *hr = nullptr;
-        DSES_HIP(hipHostMalloc(&hr, cap * sizeof(DevResult), hipHostMallocDefault));
+        DSES_HIP(host_alloc(&hr, cap * sizeof(DevResult), hipHostMallocDefault));
         b->host_res = static_cast<DevResult *>(hr);
         b->cap_count = cap;
         grew = true;
     }
     if (n_items > b->cap_items) {
         const int cap = std::max(n_items, 4096);
+        b->cap_items = 0;
         if ((st = b->items.ensure(cap * sizeof(BatchItem))) != DSES_OK) return st;
         b->cap_items = cap;
         grew = true;
     }
     if ((st = b->header.ensure(64)) != DSES_OK) return st;
     if (scratch_bytes > b->cap_scratch) {
+        b->cap_scratch = 0;
         if ((st = b->scratch.ensure(scratch_bytes)) != DSES_OK) return st;
         b->cap_scratch = b->scratch.bytes;
         grew = true;

@@ -29,6 +29,28 @@ void set_error(const std::string &msg);
         }                                                                                   \
     } while (0)
 
+// Every device and pinned-host allocation of the library goes through these,
+// so that dses_debug_fail_allocs() can make chosen ones fail (tests of the
+// error paths).  On failure *p is null.
+hipError_t dev_alloc_raw(void **p, size_t bytes);
+hipError_t host_alloc_raw(void **p, size_t bytes, unsigned int flags);
+template <class T>
+inline hipError_t dev_alloc(T **p, size_t bytes)
+{
+    void *v = nullptr;
+    const hipError_t e = dev_alloc_raw(&v, bytes);
+    *p = static_cast<T *>(v);
+    return e;
+}
+template <class T>
+inline hipError_t host_alloc(T **p, size_t bytes, unsigned int flags)
+{
+    void *v = nullptr;
+    const hipError_t e = host_alloc_raw(&v, bytes, flags);
+    *p = static_cast<T *>(v);
+    return e;
+}
+
 // A device allocation that grows on demand (never shrinks while in use).
 struct DevBuf {
     void *ptr = nullptr;

@@ -69,7 +69,7 @@ extern "C" dses_status dses_measure_lds_atomics(int32_t pattern, double *adds_pe
     const int grid = c->n_cu;
     const int32_t iters = 4096;                       // 8 adds per iteration per lane
     uint32_t *sink = nullptr;
-    DSES_HIP(hipMalloc(&sink, grid * sizeof(uint32_t)));
+    DSES_HIP(dev_alloc(&sink, grid * sizeof(uint32_t)));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     DSES_HIP(hipEventCreate(&e0));
     DSES_HIP(hipEventCreate(&e1));

@@ -31,8 +31,8 @@ dses_status ensure_target_grid(TargetRes *tm, float r, CellGrid *cg)
         TargetRes::Grid g{r, nullptr, nullptr, HostGrid{}};
         dses_status st = build_grid(tm->host_aos.data(), tm->m, r, &g.meta);
         if (st != DSES_OK) return st;
-        if (hipMalloc(&g.pts, g.meta.pts.size() * sizeof(float)) != hipSuccess ||
-            hipMalloc(&g.start, g.meta.start.size() * sizeof(int32_t)) != hipSuccess ||
+        if (dev_alloc(&g.pts, g.meta.pts.size() * sizeof(float)) != hipSuccess ||
+            dev_alloc(&g.start, g.meta.start.size() * sizeof(int32_t)) != hipSuccess ||
             hipMemcpy(g.pts, g.meta.pts.data(), g.meta.pts.size() * sizeof(float),
                       hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(g.start, g.meta.start.data(), g.meta.start.size() * sizeof(int32_t),
@@ -89,17 +89,29 @@ dses_status ensure_target_stage(TargetRes *tm, const Params &p, hipStream_t stre
     const size_t m = (size_t)tm->m;
     if (tm->perm_x.empty()) sort_by_x(tm->host_aos.data(), tm->m, &tm->perm_x);
     if (!tm->d_perm) {
-        DSES_HIP(hipMalloc(&tm->d_perm, 4 * m));
-        DSES_HIP(hipMemcpy(tm->d_perm, tm->perm_x.data(), 4 * m, hipMemcpyHostToDevice));
+        int32_t *perm = nullptr;
+        DSES_HIP(dev_alloc(&perm, 4 * m));
+        const hipError_t e = hipMemcpy(perm, tm->perm_x.data(), 4 * m, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(perm);
+            DSES_HIP(e);
+        }
+        tm->d_perm = perm;
     }
     double S16, S15;
     lattice_scales(p.delta, &S16, &S15);
     TargetRes::Stage st{p.delta, {p.klo[0], p.klo[1], p.klo[2]}, nullptr, nullptr, false, 0, 0};
     st.sorted = ref_x_range(tm->host_aos.data(), tm->perm_x, p.delta, p.klo[0], &st.ylo, &st.yhi);
-    DSES_HIP(hipMalloc(&st.yq, 16 * m));
-    DSES_HIP(hipMalloc(&st.yt, 12 * m));
-    DSES_HIP(launch_stage(tm->aos, tm->d_perm, tm->m, S16, S15, p.klo, st.yq, st.yt, stream));
-    DSES_HIP(hipStreamSynchronize(stream));
+    hipError_t e = dev_alloc(&st.yq, 16 * m);
+    if (e == hipSuccess) e = dev_alloc(&st.yt, 12 * m);
+    if (e == hipSuccess)
+        e = launch_stage(tm->aos, tm->d_perm, tm->m, S16, S15, p.klo, st.yq, st.yt, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        if (st.yq) (void)hipFree(st.yq);
+        if (st.yt) (void)hipFree(st.yt);
+        DSES_HIP(e);
+    }
     tm->stages.push_back(st);
     *out = &tm->stages.back();
     return DSES_OK;
@@ -145,7 +157,7 @@ dses_status dses_target_create(const float *tgt, int64_t m, const dses_target_op
         dses_target_destroy(t);
         return s;
     };
-    if (hipMalloc(&T.aos, 3 * (size_t)m * sizeof(float)) != hipSuccess) {
+    if (dev_alloc(&T.aos, 3 * (size_t)m * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         set_error("device allocation failed");
         return fail(DSES_E_NOMEM);
@@ -177,9 +189,9 @@ dses_status dses_target_create(const float *tgt, int64_t m, const dses_target_op
         float *gp = nullptr;
         int32_t *gs = nullptr;
         const size_t nvox = (size_t)res * res * res;
-        if (hipMalloc(&gp, hg.pts.size() * sizeof(float)) != hipSuccess ||
-            hipMalloc(&gs, hg.start.size() * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&T.df, nvox * sizeof(float)) != hipSuccess) {
+        if (dev_alloc(&gp, hg.pts.size() * sizeof(float)) != hipSuccess ||
+            dev_alloc(&gs, hg.start.size() * sizeof(int32_t)) != hipSuccess ||
+            dev_alloc(&T.df, nvox * sizeof(float)) != hipSuccess) {
             (void)hipGetLastError();
             if (gp) (void)hipFree(gp);
             if (gs) (void)hipFree(gs);
@@ -270,7 +282,7 @@ dses_status dses_rotations_create(const float *rotations, int64_t k, uint32_t fl
     }
     auto *r = new dses_rotset();
     r->res.k = k;
-    if (hipMalloc(&r->res.rot, 9 * (size_t)k * sizeof(float)) != hipSuccess) {
+    if (dev_alloc(&r->res.rot, 9 * (size_t)k * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         delete r;
         set_error("device allocation failed");

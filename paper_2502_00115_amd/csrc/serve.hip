@@ -222,20 +222,20 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     DSES_HIP(hipStreamCreateWithFlags(&down, hipStreamNonBlocking));
     DSES_HIP(hipEventCreateWithFlags(&up_done, hipEventDisableTiming));
     DSES_HIP(hipEventRecord(up_done, up));
-    if (hipMalloc(&pool_mem, (size_t)opt.memory_budget) != hipSuccess) {
+    if (dev_alloc(&pool_mem, (size_t)opt.memory_budget) != hipSuccess) {
         (void)hipGetLastError();
         set_error("cannot reserve the serving memory budget on the device");
         return DSES_E_NOMEM;
     }
     pool.init((size_t)opt.memory_budget);
-    DSES_HIP(hipMalloc(&d_args, max_slots * sizeof(SweepArgs)));
-    DSES_HIP(hipMalloc(&d_done, max_slots * sizeof(uint32_t)));
+    DSES_HIP(dev_alloc(&d_args, max_slots * sizeof(SweepArgs)));
+    DSES_HIP(dev_alloc(&d_done, max_slots * sizeof(uint32_t)));
     DSES_HIP(hipMemset(d_done, 0, max_slots * sizeof(uint32_t)));
     // host memory the kernels read or write in place: coherent (not cached by
     // the device), mapped into the device's address space
     void *p = nullptr;
     auto host_mapped = [&](size_t bytes, void **h, void **dv) {
-        DSES_HIP(hipHostMalloc(h, bytes, hipHostMallocCoherent | hipHostMallocMapped));
+        DSES_HIP(host_alloc(h, bytes, hipHostMallocCoherent | hipHostMallocMapped));
         std::memset(*h, 0, bytes);
         DSES_HIP(hipHostGetDevicePointer(dv, *h, 0));
         return DSES_OK;
@@ -247,7 +247,7 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     if (host_mapped(max_slots * sizeof(uint32_t), &p, &dv) != DSES_OK) return DSES_E_DEVICE;
     h_flag = static_cast<uint32_t *>(p);
     dv_flag = static_cast<uint32_t *>(dv);
-    DSES_HIP(hipHostMalloc(&p, (size_t)max_slots * kSlotStageBytes, hipHostMallocDefault));
+    DSES_HIP(host_alloc(&p, (size_t)max_slots * kSlotStageBytes, hipHostMallocDefault));
     h_stage = static_cast<float *>(p);
     for (auto &s : sets) {
         if (host_mapped(kMaxSliceItems * sizeof(BatchItem), &p, &dv) != DSES_OK) return DSES_E_DEVICE;
@@ -256,9 +256,9 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
         if (host_mapped(64, &p, &dv) != DSES_OK) return DSES_E_DEVICE;
         s.h_header = static_cast<int32_t *>(p);
         s.dv_header = static_cast<const int32_t *>(dv);
-        DSES_HIP(hipMalloc(&s.d_cursor, 64));
+        DSES_HIP(dev_alloc(&s.d_cursor, 64));
         DSES_HIP(hipMemset(s.d_cursor, 0, 64));
-        DSES_HIP(hipMalloc(&s.d_scratch, (size_t)grid * slot_words(kServeMaxSrc) * sizeof(int32_t)));
+        DSES_HIP(dev_alloc(&s.d_scratch, (size_t)grid * slot_words(kServeMaxSrc) * sizeof(int32_t)));
         DSES_HIP(hipEventCreateWithFlags(&s.swept, hipEventDisableTiming));
     }
     DSES_HIP(hipDeviceSynchronize());

@@ -33,6 +33,7 @@ EXPORTED = [
     "dses_register_exhaustive", "dses_register_noalloc", "dses_noalloc_scratch_bytes",
     "dses_server_create", "dses_server_submit", "dses_server_wait", "dses_server_poll",
     "dses_server_timing", "dses_server_cancel", "dses_server_destroy",
+    "dses_debug_fail_allocs",
 ]
 
 
@@ -150,6 +151,7 @@ def lib():
         L.dses_server_timing.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double),
                                          C.POINTER(C.c_double)]
         L.dses_server_destroy.argtypes = [vp]
+        L.dses_debug_fail_allocs.argtypes = [i32, i32]
         for name in EXPORTED:
             if name not in ("dses_last_error", "dses_version", "dses_noalloc_scratch_bytes"):
                 getattr(L, name).restype = i32
@@ -345,6 +347,12 @@ def register_noalloc(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=Non
 
 def noalloc_scratch_bytes() -> int:
     return int(lib().dses_noalloc_scratch_bytes())
+
+
+def debug_fail_allocs(skip: int, count: int) -> None:
+    """dses_debug_fail_allocs: of the library's next allocations the first `skip`
+    succeed and the `count` after them fail; (0, 0) turns the injection off."""
+    _check(lib().dses_debug_fail_allocs(int(skip), int(count)))
 
 
 def register_exhaustive(src, tgt, rotations, eps, metric="trunc_l2", *, delta_t=None, tau=None,

@@ -67,6 +67,12 @@ def test_argument_errors_need_no_gpu(libpath):
         assert e.value.status == dses.DSES_E_INVAL, (kw, e.value)
     with pytest.raises(ValueError):
         dses.register(np.zeros((4, 2)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05)
+    # the allocation-failure hook checks its arguments on the host
+    for skip, count in ((-1, 1), (0, -1)):
+        with pytest.raises(dses.DsesError) as e:
+            dses.debug_fail_allocs(skip, count)
+        assert e.value.status == dses.DSES_E_INVAL
+    dses.debug_fail_allocs(0, 0)
     for q in (-0.1, 1.5, float("nan")):
         with pytest.raises(dses.DsesError) as e:
             dses.register(np.zeros((3, 3)), np.zeros((4, 3)), np.eye(3).reshape(1, 9), 0.05, q=q)

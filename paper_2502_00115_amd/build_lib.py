@@ -38,7 +38,8 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     for p in procs:
         _wait(p)
     tmp = LIB + ".tmp"
-    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp,
+                           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, LIB)
     return LIB
 

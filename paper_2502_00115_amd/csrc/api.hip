@@ -559,6 +559,8 @@ static int effective_scorer(const Job &job)
 dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check_inputs,
                       dses_result *out, const dses_options &o, Arena *arena)
 {
+    TraceRange whole("dses.registration");
+    TraceRange prepare("dses.prepare");        // host work and staging before the launches
     // a device buffer of the call: from the arena when given, else the context's
     auto dbuf = [&](DevBuf &b, size_t bytes, void **ptr) -> dses_status {
         if (arena) {
@@ -723,6 +725,8 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
         for (auto &e : ev) DSES_HIP(hipEventCreate(&e));
     auto rec_ev = [&](int i) { if (timing) (void)hipEventRecord(ev[i], stream); };
 
+    prepare.end();
+    TraceRange device("dses.sweep_select");    // launches to the result on the host
     rec_ev(0);
     DSES_HIP(launch_clear(bad, 16, stream));
     if (check_inputs) {
@@ -749,6 +753,7 @@ dses_status run_plain(Context *c, const Job &job, hipStream_t stream, bool check
     rec_ev(3);
     DSES_HIP(hipMemcpyAsync(c->host_res, d_res, sizeof(DevResult), hipMemcpyDeviceToHost, stream));
     DSES_HIP(hipStreamSynchronize(stream));
+    device.end();
     const DevResult r = *c->host_res;
     if (timing) {
         float t01 = 0, t12 = 0, t23 = 0;

@@ -209,6 +209,7 @@ extern "C" dses_status dses_register_batch(const dses_problem *probs, int32_t co
                                            dses_status *status_out)
 {
     set_error("");
+    TraceRange range("dses.batch");
     if (!probs || !out || !status_out || count <= 0) {
         set_error("invalid batch arguments");
         return DSES_E_INVAL;

@@ -13,6 +13,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "dses.h"
 #include "internal.h"
 
@@ -50,6 +52,21 @@ inline hipError_t host_alloc(T **p, size_t bytes, unsigned int flags)
     *p = static_cast<T *>(v);
     return e;
 }
+
+// A roctx range on the calling thread (rocprofv3 --marker-trace records it)
+// around a host-side phase of an entry point; end() closes it early.
+struct TraceRange {
+    bool open = true;
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    void end()
+    {
+        if (open) roctxRangePop();
+        open = false;
+    }
+    ~TraceRange() { end(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // A device allocation that grows on demand (never shrinks while in use).
 struct DevBuf {

@@ -127,6 +127,7 @@ dses_status dses_target_create(const float *tgt, int64_t m, const dses_target_op
                                dses_target **out)
 {
     set_error("");
+    TraceRange range("dses.target_create");
     if (!tgt || !out || m <= 0 || m >= ((int64_t)1 << 31)) {
         set_error("invalid reference cloud");
         return DSES_E_INVAL;

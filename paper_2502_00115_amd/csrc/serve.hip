@@ -451,6 +451,7 @@ bool ServerImpl::launch_slice()
     // the kernel reads the work list from host memory, so a launch is the only
     // device work a slice enqueues
     hipStream_t st = (n_slices & 1) ? stream2 : stream;
+    roctxMarkA("dses.slice_launch");
     BatchArgs ba{d_args, s->dv_items, s->dv_header, s->d_cursor, s->d_scratch,
                  slot_words(kServeMaxSrc), s->cursor, d_done, dv_res, dv_flag};
     chk(launch_sweep_batch(ba, scorer, grid, st));
@@ -512,6 +513,7 @@ bool ServerImpl::finish(Request *r)
     }
     r->state = Request::DONE;
     r->t_done = Clock::now();
+    roctxMarkA("dses.request_done");
     if (trace)
         std::fprintf(trace, "R %llu %d %d %d %.6f %.6f %.6f\n", (unsigned long long)r->id, r->n,
                      r->m, r->k, since(r->t_submit), since(r->t_admit), since(r->t_done));
@@ -565,6 +567,7 @@ void ServerImpl::poll_slices()
 
 void ServerImpl::run()
 {
+    roctxNameOsThread("dses.scheduler");
     (void)hipSetDevice(c->device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {

@@ -67,6 +67,61 @@ def load_traffic(workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+def write_traffic(workload, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
+    """Write profiles/traffic_k_sweep_<workload>.json from four rocprofv3 --pmc
+    counter_collection.csv files: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the
+    plain sweep launches of `bench.py --workload <workload> --alone --steps 1
+    --warmup 0 --cpu-sample 0`, and the same counters of `bench.py --calibrate-copy`,
+    whose known byte counts scale them to HBM bytes."""
+    import csv
+
+    def per_dispatch(path, counter, pick):
+        vals = {}
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] == counter and pick(row["Kernel_Name"]):
+                    key = row["Dispatch_Id"]
+                    vals[key] = vals.get(key, 0.0) + float(row["Counter_Value"])
+        if not vals:
+            raise SystemExit(f"bench.py: no {counter} rows in {path}")
+        return sum(vals.values()) / len(vals), len(vals)
+
+    is_sweep = lambda n: n.startswith("void dses::k_sweep<")  # noqa: E731
+    is_copy = lambda n: "_add<" in n  # noqa: E731  (the calibration's adds, not its fill)
+    fetch, nf = per_dispatch(fetch_csv, "FETCH_SIZE", is_sweep)
+    write, nw = per_dispatch(write_csv, "WRITE_SIZE", is_sweep)
+    cfetch, _ = per_dispatch(copy_fetch_csv, "FETCH_SIZE", is_copy)
+    cwrite, _ = per_dispatch(copy_write_csv, "WRITE_SIZE", is_copy)
+    nbytes = 4 * (64 << 20)
+    fs, ws = nbytes / (cfetch * 1024.0), nbytes / (cwrite * 1024.0)
+    rec = {"workload": workload, "kernel_source_sha": kernel_source_sha(),
+           "sweep_dispatches": [nf, nw],
+           "fetch_size_kib_per_launch": fetch, "write_size_kib_per_launch": write,
+           "calibration": {"kernel": "torch.add(a, 1.0, out=b) on 64 Mi float32",
+                           "bytes_read": nbytes, "bytes_written": nbytes,
+                           "fetch_size_kib": cfetch, "write_size_kib": cwrite,
+                           "fetch_scale": fs, "write_scale": ws},
+           "hbm_bytes_per_launch": fetch * 1024.0 * fs + write * 1024.0 * ws,
+           "commands": [
+               f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python3 "
+               f"bench.py --workload {workload} --alone --steps 1 --warmup 0 --cpu-sample 0",
+               f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python3 "
+               f"bench.py --workload {workload} --alone --steps 1 --warmup 0 --cpu-sample 0",
+               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python3 "
+               "bench.py --calibrate-copy",
+               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- python3 "
+               "bench.py --calibrate-copy",
+               "python3 bench.py --workload <w> --write-traffic <four counter_collection.csv>"],
+           "kernel_sources": list(SWEEP_SOURCES),
+           "kernel_source_hash": "sha256 over " + ", ".join(SWEEP_SOURCES) + " without comments "
+                                 "and with whitespace collapsed (bench.py kernel_source_sha)"}
+    path = os.path.join(ROOT, "profiles", f"traffic_k_sweep_{workload}.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps({"wrote": path, "hbm_bytes_per_launch": rec["hbm_bytes_per_launch"]}))
+
+
 def make_workload(name, grid_level=4):
     from paper_2502_00115_amd import synth
     if name == "c1":
@@ -161,6 +216,10 @@ def bench_batch(args):
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     same = all(a.rot_index == b.rot_index and a.error == b.error for a, b in zip(plain, res))
+    # algorithmic work with the exact cell-grid scorer, summed over the batch
+    flop = sum((11.0 * len(p.src) * len(p.tgt) + 18.0 * len(p.src)) * len(p.rotations)
+               for p in probs)
+    achieved = flop / batched / 1e12
     return {"metric": "candidate poses {R,t} scored/sec (1 GPU), batched",
             "value": cands / batched, "unit": "candidates/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": batched * 1e3, "higher_is_better": True,
@@ -168,7 +227,13 @@ def bench_batch(args):
             "config": {"workload": "64 registrations, M 512-4096 log-uniform, N 30-80% cut, "
                                    "K 4,608-36,864 rotations, one persistent launch replayed "
                                    "from a HIP graph", "candidates": cands},
+            "roofline": {"bound": "alu", "kernel": "k_sweep_batch (whole batched call timed)",
+                         "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                         "work": "algorithmic (11*N*M + 18*N) FLOP per candidate, summed "
+                                 "over the 64 registrations"},
             "plain": {"value": cands / plain_s, "ms_total": plain_s * 1e3,
+                      "frac": flop / plain_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
                       "path": "64 sequential dses_register calls"},
             "layout": layout, "untuned": {"ms": default_s * 1e3, "layout": default_cfg},
             "tuning": {"s": tune_s, "candidates": tuned_cfg["candidates"],
@@ -508,9 +573,16 @@ def main():
                     help="the headline workload only (no serving or object-scale figures)")
     ap.add_argument("--lds-probe", action="store_true",
                     help="print the device's LDS atomic throughput (vote ceiling) and exit")
+    ap.add_argument("--write-traffic", nargs=4, default=None,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write profiles/traffic_k_sweep_<workload>.json from rocprofv3 "
+                         "counter CSVs (no GPU work)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain elementwise copy of 256 MiB (counter calibration)")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.workload, *args.write_traffic)
+        return
     if args.calibrate_copy:
         import torch
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

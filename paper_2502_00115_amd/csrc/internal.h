@@ -11,7 +11,12 @@ namespace dses {
 constexpr int kBlock = 1024;            // threads per sweep workgroup (16 wave64s)
 constexpr int kWaves = kBlock / 64;
 constexpr int kLdsWords = 40960;        // 160 KB of LDS per workgroup on gfx950
-constexpr int kScratchWords = 256;      // LDS words reserved after the vote array
+// LDS words after the vote array: per-wave partials of the slab scans (8..39),
+// the scorer's sums (64..111), the sort's prefix (112..127), the unit counter and
+// the occupied source-bucket range (128..130), two words at the very end for the
+// batched kernels.  Kept small so that four 101 x 101 planes of 32-bit counters
+// fit in one slab.
+constexpr int kScratchWords = 136;
 constexpr int kHistWordsMax = kLdsWords - kScratchWords;
 
 // Per-registration constants of the sweep.
@@ -96,9 +101,9 @@ __host__ __device__ inline int lane_group_log2(int m, int n, int size_x, float x
     }
     return best;
 }
-constexpr int kUnitCounter = 200;       // LDS scratch word: next vote work unit
-constexpr int kSrcBmin = 210;           // LDS scratch words: lowest and highest occupied
-constexpr int kSrcBmax = 211;           // source bucket of the current rotation
+constexpr int kUnitCounter = 128;       // LDS scratch word: next vote work unit
+constexpr int kSrcBmin = 129;           // LDS scratch words: lowest and highest occupied
+constexpr int kSrcBmax = 130;           // source bucket of the current rotation
 // Kernel scorer value for a vote-only sweep (records unscored: error +inf,
 // 0 inliers); the public scorers are DSES_SCORER_BRUTE / GRID / DF.
 constexpr int kScoreNone = 0;

@@ -824,10 +824,10 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
         const uint32_t o = __shfl_up(incl, off, 64);
         if (lane >= off) incl += o;
     }
-    if (lane == 63) scr[160 + wave] = incl;
+    if (lane == 63) scr[112 + wave] = incl;
     __syncthreads();
     uint32_t run = incl - sum;
-    for (int w = 0; w < wave; ++w) run += scr[160 + w];
+    for (int w = 0; w < wave; ++w) run += scr[112 + w];
     const uint32_t n = (uint32_t)g.n;
 #pragma unroll
     for (int q = 0; q < kPerMax; ++q) {

@@ -4,7 +4,8 @@ Default (the headline): one step = one full registration (vote, mode, score ever
 candidate, select) of the scene-scale workload: a 16,384-point six-primitive
 reference, a 4,096-point partial source (sigma 0.005 clipped at 0.05, 20%
 outliers) and the 294,912-rotation uniform SO(3) grid, eps = 0.02, truncated-L2
-error, exact cell-grid scoring, float32.  Inputs are synthetic and already
+error, exact cell-grid scoring; the vote in 32-bit fixed point, the scoring in
+float32.  Inputs are synthetic and already
 resident in device memory when timing starts.
 
 Prints one JSON line with whole-job throughput (candidate poses scored per

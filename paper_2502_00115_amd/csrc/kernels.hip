@@ -2,20 +2,24 @@
 // sweep (vote -> mode -> score), candidate selection and top-k.
 //
 // Sweep design (one workgroup of 16 wave64s per rotation, one workgroup per CU):
-//  * Source points are rotated and scaled once per rotation and bucket-sorted by
-//    x into a per-workgroup scratch slot (x, y, z arrays and a bucket table).
-//  * In the vote each lane holds one point of the x-sorted reference (a work
+//  * Source points are rotated once per rotation, quantised to the fixed-point
+//    lattice (2^-16 bins, the lattice offset folded into the reference) and
+//    bucket-sorted by x into a per-workgroup scratch slot (an x array, a 64-bit
+//    (y, z) array and a bucket table).
+//  * In the vote each lane holds two points of the x-sorted reference (a work
 //    unit's lane group: 64, 32 or 16 consecutive points, the smaller groups
 //    repeated on the wave's lane sub-groups) and streams the sources of the
 //    window whose pairs can land in the current slab; the sub-groups take
 //    alternate 4-source pieces of it.  Sources arrive through 16-byte buffer
-//    loads (one address per sub-group), two blocks in flight.
-//  * The vote array of Alg. 2 lives in LDS as 16-bit counters packed two per
-//    32-bit word (incremented with ds_add_u32 of 1 or 1<<16), so the 41^3 box of
-//    delta = 0.05 fits one allocation.  Larger boxes are swept in x-slabs that
-//    each fit LDS.  16-bit counters are used only when the host has proven that
-//    no bin can reach 2^16 votes (see counter_bound in api.hip); otherwise every
-//    counter is 32-bit.
+//    loads (one address per sub-group), two blocks in flight.  A pair's bin is
+//    exact integer arithmetic: one 64-bit add for the y and z differences, one
+//    subtraction for x, the bin being the high 16 bits of each.
+//  * The vote array of Alg. 2 lives in LDS, in x-slabs that each fit it, as
+//    16-bit counters packed two per 32-bit word (incremented with ds_add_u32 of
+//    1 or 1<<16) or as 32-bit counters.  16-bit counters are used only when the
+//    host has proven that no bin can reach 2^16 votes (counter_bound in
+//    api.hip), and 32-bit ones also when every slab carries at least 2^20 pairs
+//    (counter_bits_for), where the cheaper pairs outweigh the extra slabs.
 //  * The mode per slab: the largest count by a packed 16-bit max over the slab,
 //    then, only when it beats the earlier slabs, its lowest linear index.
 //  * Scoring rotates the sources again, in input order; the error sum is a

@@ -146,6 +146,18 @@ def test_server_results_equal_alone():
     srv.close()
 
 
+def test_server_requests_spanning_many_slices_equal_alone():
+    # slices of 10^7 pairs: each request's rotations are counted to completion
+    # across many slices on both slice streams before its workgroup selects it
+    targets, rotset, rots, reqs = _serving_setup(n_req=4, k=192, seed=9)
+    alone = [dses.register_resident(targets[t], rotset, src, 0.03) for t, src in reqs]
+    srv = dses.Server(slice_mpairs=10)
+    ids = [srv.submit(targets[t], rotset, src, 0.03) for t, src in reqs]
+    for rid, a in zip(ids, alone):
+        _same(srv.wait(rid, timeout_ms=120000), a)
+    srv.close()
+
+
 def test_server_memory_admission_serialises_when_budget_fits_one():
     targets, rotset, rots, reqs = _serving_setup(n_req=3, k=256, seed=1)
     # a request needs 12 N + 24 K bytes (rounded); budget fits exactly one at a time

@@ -237,7 +237,12 @@ dses_status ServerImpl::init(Context *ctx, const dses_server_opts &o)
     auto host_mapped = [&](size_t bytes, void **h, void **dv) {
         DSES_HIP(host_alloc(h, bytes, hipHostMallocCoherent | hipHostMallocMapped));
         std::memset(*h, 0, bytes);
-        DSES_HIP(hipHostGetDevicePointer(dv, *h, 0));
+        const hipError_t e = hipHostGetDevicePointer(dv, *h, 0);
+        if (e != hipSuccess) {
+            (void)hipHostFree(*h);
+            *h = nullptr;
+        }
+        DSES_HIP(e);
         return DSES_OK;
     };
     void *dv = nullptr;

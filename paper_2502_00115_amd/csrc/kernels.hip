@@ -875,6 +875,28 @@ __device__ void sort_sources(const SweepArgs &a, const float *R, uint32_t *lds, 
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
+// Wave64 maximum / minimum of an unsigned value by DPP lane moves (no LDS round
+// trip): pairs and quads by quad permutations, eight and sixteen lanes by the
+// half-row and row mirrors, then row 0 into row 1 and row 2 into row 3
+// (row_bcast:15), rows 0-1 into rows 2-3 (row_bcast:31); lane 63 holds the
+// result, read back as a wave-uniform value.  Lanes a move does not write keep
+// the identity, so inactive sources never change the result.
+template <bool MAX>
+__device__ __forceinline__ uint32_t wave_ext_u32(uint32_t v)
+{
+    const int id = MAX ? 0 : -1;
+    auto op = [](uint32_t a, uint32_t b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0xB1, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x4E, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x141, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x140, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x142, 0xA, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x143, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) { return wave_ext_u32<true>(v); }
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) { return wave_ext_u32<false>(v); }
+
 // Largest counter of a slab (words4 uint4 of counters), workgroup-uniform;
 // `mine` receives the largest counter among this thread's own words.
 template <int CW>
@@ -900,7 +922,7 @@ __device__ uint32_t slab_max(const uint32_t *hist, int words4, uint32_t *scr, ui
         }
     }
     mine = mx;
-    for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+    mx = wave_max_u32(mx);
     if (lane == 0) scr[8 + wave] = mx;
     __syncthreads();
     uint32_t r = 0;
@@ -935,7 +957,7 @@ __device__ uint32_t slab_first(const uint32_t *hist, int words4, uint32_t c, uin
             }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, off, 64));
+    best = wave_min_u32(best);
     if (lane == 0) scr[24 + wave] = best;
     __syncthreads();
     uint32_t r = 0xFFFFFFFFu;
